@@ -1,0 +1,185 @@
+"""Trust-region SQP around the ADMM QP solver (Section II, Algorithm 1), with
+the multiplier recovery and step return of Section IV-B5.
+
+Readings where the paper is silent (also listed in the design notes):
+* start: flat start (``acopf.flat_start``), pi = 0, Delta0 = 1; the linear
+  feasibility projection (eq. linfeas) is not run: the power balance is
+  linear, so the first QP restores it;
+* the step: d_pg, d_qg from the generator side, d_w, d_th from the bus side,
+  d_wR, d_wI by the elimination (eq. elim) applied to the bus-side values,
+  so the linearised (opfc11, opfc12) hold exactly;
+* multipliers pi (eq. lag): pi13, pi14 = -mu of the line-limit rows of the
+  last line solve (the paper's plus-sign Lagrangian makes them <= 0);
+  pi11, pi12 from the stationarity of the line subproblem in (d_wR, d_wI)
+  before elimination, a 2x2 system with determinant -2(wR cos + wI sin);
+* acceptance: ared > 0 and pred > 0 (then ared/pred > 0); the trust radius
+  doubles (up to Delta_max) after an accepted step that reached it with
+  ared >= 0.75 pred, stays put after other accepted steps, and becomes
+  0.5 min(Delta, ||d||_inf) after a rejection;
+* the model q(d) uses the Hessian the QP used (reduced M, possibly PSD
+  projected);
+* pi and the ADMM multipliers are carried to the next iteration (warm
+  start); pi is replaced only on acceptance.
+
+Test infrastructure only (see the package docstring).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+from . import acopf, admm, qp as qpmod
+from .acopf import Iterate
+
+
+@dataclass
+class SqpParams:
+    rho: float = 2e4
+    max_sweeps: int = 20000
+    eps_pri: float = 1e-4
+    eps_dual: float = 1e-4
+    mu_merit: float = 1e5
+    delta0: float = 1.0
+    delta_max: float = 10.0
+    delta_min: float = 1e-8
+    tol_primal: float = 1e-4
+    tol_dual: float = 1e-4
+    tol_step: float = 1e-6
+    max_iter: int = 30
+    hessian_mode: str = "psd"
+
+
+@dataclass
+class SqpRecord:
+    k: int
+    accepted: bool
+    ared: float
+    pred: float
+    delta: float
+    step_inf: float
+    sweeps: int
+    r: float
+    s: float
+    objective: float
+    primal: float
+    dual: float
+
+
+@dataclass
+class SqpResult:
+    x: Iterate
+    pi: np.ndarray
+    outcome: str
+    iterations: int
+    records: list = field(default_factory=list)
+
+
+def assemble_step(grid, qp, st: admm.AdmmState) -> Iterate:
+    """Trial step d returned to SQP after the ADMM solve."""
+    z = np.stack([st.dw[grid.f], st.dth[grid.f], st.dw[grid.t], st.dth[grid.t]], 1)
+    L = qp.line
+    dwR = np.einsum("li,li->l", L.aR, z) + L.bR
+    dwI = np.einsum("li,li->l", L.aI, z) + L.bI
+    return Iterate(st.xg[:, 0].copy(), st.xg[:, 1].copy(), st.dw.copy(), st.dth.copy(), dwR, dwI)
+
+
+def recover_pi(grid, x: Iterate, qp, st: admm.AdmmState) -> np.ndarray:
+    """Multipliers pi of (opfc11-14) from the KKT conditions of the line
+    subproblems (eq. line_kernel) at the line-side solution."""
+    L = qp.line
+    z = st.xl[:, 4:8]
+    A, b = qpmod.lift_matrix(L.aR, L.bR, L.aI, L.bI)
+    u = (A @ z[:, :, None])[:, :, 0] + b
+    Hu = (L.H @ u[:, :, None])[:, :, 0]
+    lam = st.lam_l[:, :4]
+    mu = st.mu
+    pij, qij, pji, qji = L.pk[:, 0], L.pk[:, 1], L.pk[:, 2], L.pk[:, 3]
+    dfR = np.stack([grid.gij, -grid.bij, grid.gji, -grid.bji], 1)
+    dfI = np.stack([grid.bij, grid.gij, -grid.bji, -grid.gji], 1)
+    llR = np.stack([2 * pij * grid.gij - 2 * qij * grid.bij, 2 * pji * grid.gji - 2 * qji * grid.bji], 1)
+    llI = np.stack([2 * pij * grid.bij + 2 * qij * grid.gij, -2 * pji * grid.bji - 2 * qji * grid.gji], 1)
+    gR = Hu[:, 2] + np.sum(lam * dfR, 1) + np.sum(mu * llR, 1)
+    gI = Hu[:, 3] + np.sum(lam * dfI, 1) + np.sum(mu * llI, 1)
+    ph = x.th[grid.f] - x.th[grid.t]
+    s, c = np.sin(ph), np.cos(ph)
+    # [2wR  s] [pi11]     [gR]
+    # [2wI -c] [pi12] = - [gI]
+    det = -2 * x.wR * c - 2 * x.wI * s
+    p11 = (-gR * (-c) - s * (-gI)) / det
+    p12 = (2 * x.wR * (-gI) - 2 * x.wI * (-gR)) / det
+    return np.stack([p11, p12, -mu[:, 0], -mu[:, 1]], 1)
+
+
+def model_m(grid, x: Iterate, qp, d: Iterate) -> float:
+    """m(d) of Section II-C: l1 violation of the linearised nonlinear constraints."""
+    f, t = grid.f, grid.t
+    wi, wj = x.w[f], x.w[t]
+    ph = x.th[f] - x.th[t]
+    s, c = np.sin(ph), np.cos(ph)
+    c11, c12, c13, c14 = acopf.nonlinear_constraints(grid, x)
+    K = x.wR * c + x.wI * s
+    l11 = c11 + 2 * x.wR * d.wR + 2 * x.wI * d.wI - wj * d.w[f] - wi * d.w[t]
+    l12 = c12 + s * d.wR - c * d.wI + K * (d.th[f] - d.th[t])
+    dp = acopf.flows(grid, d.w, d.wR, d.wI)
+    pk = qp.line.pk
+    l13 = c13 - 2 * pk[:, 0] * dp[0] - 2 * pk[:, 1] * dp[1]
+    l14 = c14 - 2 * pk[:, 2] * dp[2] - 2 * pk[:, 3] * dp[3]
+    neg = lambda v: np.maximum(0.0, -v)
+    return float(np.abs(l11).sum() + np.abs(l12).sum() + neg(l13).sum() + neg(l14).sum())
+
+
+def predicted_reduction(grid, x: Iterate, qp, d: Iterate, mu_merit: float) -> float:
+    """q(0; mu) - q(d; mu) of Section II-C."""
+    z = np.stack([d.w[grid.f], d.th[grid.f], d.w[grid.t], d.th[grid.t]], 1)
+    quad = qpmod.qp_objective(qp, d.pg, z) - float(qp.line.c0.sum())
+    return float(-quad + mu_merit * (acopf.infeas_h(grid, x) - model_m(grid, x, qp, d)))
+
+
+def step_norm(d: Iterate) -> float:
+    return float(max(np.abs(d.pg).max(initial=0), np.abs(d.qg).max(initial=0),
+                     np.abs(d.w).max(initial=0), np.abs(d.th).max(initial=0)))
+
+
+def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time_fn=None) -> SqpResult:
+    """Algorithm 1 with the ADMM QP solver."""
+    x = acopf.flat_start(grid) if x0 is None else x0.copy()
+    pi = np.zeros((grid.n_line, 4))
+    delta = params.delta0
+    rho = admm.Rho.scalar(grid, params.rho)
+    lam_g = lam_l = None
+    recs = []
+    outcome = "MAX_ITER"
+    for k in range(params.max_iter):
+        qp = qpmod.build_qp(grid, x, pi, delta, params.hessian_mode)
+        start = admm.cold_state(grid) if lam_g is None else admm.warm_state(grid, lam_g, lam_l)
+        res = admm.solve(grid, qp, rho, params.max_sweeps, params.eps_pri, params.eps_dual, start)
+        st = res.state
+        lam_g, lam_l = st.lam_g, st.lam_l
+        d = assemble_step(grid, qp, st)
+        pi_new = recover_pi(grid, x, qp, st)
+        xt = x.plus(d)
+        ared = acopf.merit(grid, x, params.mu_merit) - acopf.merit(grid, xt, params.mu_merit)
+        pred = predicted_reduction(grid, x, qp, d, params.mu_merit)
+        dn = step_norm(d)
+        accepted = ared > 0 and pred > 0
+        if accepted:
+            x = xt
+            pi = pi_new
+            if dn >= 0.99 * delta and ared >= 0.75 * pred:
+                delta = min(2 * delta, params.delta_max)
+        else:
+            delta = 0.5 * min(delta, dn)
+        pr = acopf.primal_infeasibility(grid, x)["primal"]
+        du = acopf.dual_infeasibility(grid, x, st.nu[:, 0], st.nu[:, 1], pi)
+        recs.append(SqpRecord(k, accepted, ared, pred, delta, dn, res.sweeps, res.r, res.s,
+                              acopf.objective(grid, x.pg), pr, du))
+        if accepted and pr <= params.tol_primal and du <= params.tol_dual:
+            outcome = "CONVERGED"
+            break
+        if accepted and dn < params.tol_step:
+            outcome = "SMALL_STEP"
+            break
+        if delta < params.delta_min:
+            outcome = "TR_COLLAPSED"
+            break
+    return SqpResult(x, pi, outcome, len(recs), recs)
