@@ -1,0 +1,177 @@
+/*
+ * acopf_admm.h -- C ABI of the MI355X (gfx950) ADMM QP solver for the SQP
+ * method of "GPU-Accelerated Sequential Quadratic Programming Algorithm for
+ * Solving ACOPF" (Li, Schanen, Kim; arXiv 2310.13143).
+ *
+ * Every array argument is a DEVICE pointer unless its comment says "host".
+ * The caller owns all memory: it allocates the grid arrays, the iterate and
+ * one workspace of acopf_workspace_bytes() bytes per grid; the library
+ * never allocates or frees device memory.  Calls enqueue work on the given
+ * HIP stream and return; results are valid once the stream has completed
+ * (calls taking a host result pointer synchronise the stream themselves).
+ * All arithmetic is FP64.  Indices are int32, zero based.  A workspace must
+ * not be used by two calls at the same time.
+ *
+ * Errors: every entry point returns ACOPF_OK (0) or a negative
+ * acopf_status; acopf_last_error() then describes the failure (per host
+ * thread).  Convergence outcomes are not errors: they are reported in the
+ * result structs.
+ */
+#ifndef ACOPF_ADMM_H
+#define ACOPF_ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ACOPF_OK = 0,
+  ACOPF_ERR_INVALID_ARG = -1,     /* bad size, null pointer, index out of range */
+  ACOPF_ERR_HIP = -2,             /* a HIP runtime call failed */
+  ACOPF_ERR_NONCONVEX_LINE = -3,  /* raw Hessian mode: a line subproblem matrix is not positive definite */
+  ACOPF_ERR_NUMERIC = -4,         /* non-finite data or a vanishing elimination pivot */
+  ACOPF_ERR_UNSUPPORTED = -5,     /* request outside what the build supports */
+  ACOPF_ERR_BARRIER = -6          /* the persistent sweep kernel's grid barrier timed out */
+} acopf_status;
+
+typedef enum {
+  ACOPF_ADMM_CONVERGED = 0,       /* ||r||_2 <= eps_pri and ||s||_2 <= eps_dual */
+  ACOPF_ADMM_MAX_SWEEPS = 1       /* stopped at max_sweeps */
+} acopf_admm_outcome;
+
+typedef enum { ACOPF_HESSIAN_PSD = 0, ACOPF_HESSIAN_RAW = 1 } acopf_hessian_mode;
+typedef enum { ACOPF_SWEEP_PERSISTENT = 0, ACOPF_SWEEP_LAUNCHES = 1 } acopf_sweep_mode;
+
+/*
+ * Network data of the ACOPF model (Section III-A, eqs. acopf and acopf_pf),
+ * per unit.  Branch (i, j) = (line_from, line_to); g_ii + j b_ii, g_ij + j
+ * b_ij, g_ji + j b_ji, g_jj + j b_jj are the entries of the branch's own
+ * 2x2 admittance matrix used by the flow definitions; smax_* are the limits
+ * s_bar (not squared).  Generator cost f(p) = cost2 p^2 + cost1 p.  Shunt
+ * g_sh + j b_sh enters the balance as in (opfc5, opfc6).  Every bus must be
+ * the end of at least one branch.
+ */
+typedef struct {
+  int32_t n_bus, n_line, n_gen, ref_bus;
+  const double *vmin, *vmax, *pd, *qd, *gsh, *bsh;                   /* [n_bus]  */
+  const int32_t *line_from, *line_to;                                /* [n_line] */
+  const double *gii, *bii, *gij, *bij, *gji, *bji, *gjj, *bjj;       /* [n_line] */
+  const double *smax_ij, *smax_ji;                                   /* [n_line] */
+  const int32_t *gen_bus;                                            /* [n_gen]  */
+  const double *pmin, *pmax, *qmin, *qmax, *cost2, *cost1;           /* [n_gen]  */
+} acopf_grid;
+
+/* SQP iterate x^(k) (Section III-B) and line multipliers pi of (eq. lag):
+ * pi[k * n_line + l] multiplies constraint (opfc11 + k) of line l, with the
+ * paper's plus-sign Lagrangian (limits' multipliers are <= 0). */
+typedef struct {
+  double *pg, *qg;      /* [n_gen]      */
+  double *w, *th;       /* [n_bus]      w = v^2, angle */
+  double *wR, *wI;      /* [n_line]     */
+  double *pi;           /* [4 * n_line] */
+} acopf_iterate;
+
+typedef struct {
+  int32_t max_sweeps;   /* cap on ADMM iterations (Algorithm 2)                    */
+  double eps_pri;       /* stop when ||r||_2 <= eps_pri ...                       */
+  double eps_dual;      /* ... and ||s||_2 <= eps_dual (Section IV-B5); 0 = never */
+  int32_t sweep_mode;   /* acopf_sweep_mode                                       */
+  int32_t block_size;   /* threads per block, multiple of 64, <= 1024; 0 = 256    */
+  int32_t max_blocks;   /* persistent grid size cap; 0 = as many as fit resident  */
+} acopf_admm_params;
+
+typedef struct {
+  int32_t sweeps;            /* sweeps run                                           */
+  int32_t outcome;           /* acopf_admm_outcome                                   */
+  double r_norm, s_norm;     /* ||r||_2, ||s||_2 of the last sweep                   */
+  int32_t infeasible_lines;  /* line subproblems without a feasible point, last sweep */
+  int32_t blocks;            /* grid size the sweeps ran with                        */
+} acopf_admm_result;
+
+/* Layout of an ADMM state held by the caller (export / warm start), line-
+ * major like the coupling order of (eq. cpl):
+ *   per generator 2 couplings (p, q): xg, xbar_g, lam_g, rho_g  [2 * n_gen], index c * n_gen + g
+ *   per line 8 couplings (p_ij, q_ij, p_ji, q_ji, w_i, th_i, w_j, th_j):
+ *       xl, lam_l, rho_l [8 * n_line], index c * n_line + l; xbar_f [4 * n_line] (flow copies)
+ *   per bus: dw, dth [n_bus], nu [2 * n_bus] (balance multipliers, P rows then Q rows)
+ *   per line: mu [2 * n_line] (multipliers of the two limit rows in the last line solve)
+ * x is the generator/line side, xbar the bus side of a coupling. */
+typedef struct {
+  double *xg, *xbar_g, *lam_g, *rho_g;
+  double *xl, *xbar_f, *lam_l, *rho_l;
+  double *dw, *dth, *nu, *mu;
+} acopf_admm_state;
+
+/* Bytes of device workspace for one grid (QP data, ADMM state, topology). */
+size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen);
+
+/* Validate the grid and build the bus incidence tables in the workspace.
+ * Copies the three index arrays to the host once (synchronous).  Must be
+ * called once per workspace, with the same grid, before any other call on
+ * it; the library keeps no state outside the workspace. */
+acopf_status acopf_setup(const acopf_grid* grid, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/* Build the QP subproblem (QPsub) at iterate x with trust radius delta:
+ * elimination of d_wR, d_wI (eq. elim), line Hessian of (eq. lag) reduced
+ * by A_ij (Section IV-B2; PSD-projected in ACOPF_HESSIAN_PSD mode), flow
+ * map, linearised limits (opfqpc13, opfqpc14), boxes (opfqpc1-4 with the
+ * trust region; the reference angle fixed), generator gradients and the
+ * bus constants p^{d,(k)}, q^{d,(k)}.  Returns ACOPF_ERR_NUMERIC if a line
+ * has |wR cos + wI sin| < 1e-8 at x (after the stream syncs this is
+ * reported by the next solve). */
+acopf_status acopf_qp_build(const acopf_grid* grid, const acopf_iterate* x, double delta,
+                            int32_t hessian_mode, void* workspace, void* stream);
+
+/* Start an ADMM solve: copy the penalties rho (host-layout arrays of
+ * acopf_admm_state, each entry > 0) and the warm-start multipliers
+ * (lam_g, lam_l; NULL = cold start, all zero) into the workspace, zero the
+ * primal values x, xbar and the bus values (Algorithm 2, line 1), and
+ * factor each line subproblem matrix Q = M + sum rho_f F_f^T F_f +
+ * diag(rho_v).  Requires a built QP. */
+acopf_status acopf_admm_init(const acopf_grid* grid, const double* rho_g, const double* rho_l,
+                             const double* lam_g, const double* lam_l, void* workspace, void* stream);
+
+/* Run ADMM sweeps (Algorithm 2) from the workspace state until the stop
+ * test of Section IV-B5 holds or max_sweeps: generator closed form (eq.
+ * gen_kernel), exact line subproblem (eq. line_kernel, dual active-set
+ * method on the 4-variable strictly convex QP), bus closed form (eq.
+ * bus_kernel_simp), multiplier update (eq. multiplier), residuals.  If
+ * result is non-NULL (host) the stream is synchronised and the result
+ * copied; otherwise the result is kept in the workspace
+ * (acopf_admm_result_get). */
+acopf_status acopf_admm_solve(const acopf_grid* grid, const acopf_admm_params* params,
+                              void* workspace, void* stream, acopf_admm_result* result);
+
+/* Copy the last solve's result to host memory (synchronises the stream). */
+acopf_status acopf_admm_result_get(const acopf_grid* grid, void* workspace, void* stream,
+                                   acopf_admm_result* result);
+
+/* Export the ADMM state to caller arrays in the line-major layout above
+ * (any member may be NULL to skip it). */
+acopf_status acopf_admm_state_get(const acopf_grid* grid, void* workspace,
+                                  const acopf_admm_state* out, void* stream);
+
+/* Step returned to SQP and multiplier estimates (Section IV-B5): d_pg,
+ * d_qg from the generator side, d_w, d_th from the bus side, d_wR, d_wI by
+ * the elimination applied to the bus-side values; pi13, pi14 = -mu of the
+ * last line solve, pi11, pi12 from the stationarity of the line subproblem
+ * in (d_wR, d_wI) (a 2x2 solve).  Outputs: d (an iterate layout whose pi
+ * member receives the new multipliers). */
+acopf_status acopf_step(const acopf_grid* grid, const acopf_iterate* x, void* workspace,
+                        const acopf_iterate* d, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+/* Last error message of the calling host thread (never NULL). */
+#ifdef __cplusplus
+extern "C"
+#endif
+const char* acopf_last_error(void);
+
+#endif /* ACOPF_ADMM_H */

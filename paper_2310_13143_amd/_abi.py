@@ -1,0 +1,93 @@
+"""ctypes mirror of include/acopf_admm.h and loader of the in-tree library."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_double, c_int32, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libacopf_admm.so")
+
+ACOPF_OK = 0
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "NONCONVEX_LINE", -4: "NUMERIC",
+                -5: "UNSUPPORTED", -6: "BARRIER"}
+HESSIAN_PSD, HESSIAN_RAW = 0, 1
+SWEEP_PERSISTENT, SWEEP_LAUNCHES = 0, 1
+ADMM_CONVERGED, ADMM_MAX_SWEEPS = 0, 1
+
+GRID_BUS_FIELDS = ("vmin", "vmax", "pd", "qd", "gsh", "bsh")
+GRID_LINE_INT = ("line_from", "line_to")
+GRID_LINE_FIELDS = ("gii", "bii", "gij", "bij", "gji", "bji", "gjj", "bjj", "smax_ij", "smax_ji")
+GRID_GEN_INT = ("gen_bus",)
+GRID_GEN_FIELDS = ("pmin", "pmax", "qmin", "qmax", "cost2", "cost1")
+ITERATE_FIELDS = ("pg", "qg", "w", "th", "wR", "wI", "pi")
+STATE_FIELDS = ("xg", "xbar_g", "lam_g", "rho_g", "xl", "xbar_f", "lam_l", "rho_l", "dw", "dth", "nu", "mu")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = ([("n_bus", c_int32), ("n_line", c_int32), ("n_gen", c_int32), ("ref_bus", c_int32)]
+                + [(n, c_void_p) for n in GRID_BUS_FIELDS + GRID_LINE_INT + GRID_LINE_FIELDS
+                   + GRID_GEN_INT + GRID_GEN_FIELDS])
+
+
+class Iterate(ctypes.Structure):
+    _fields_ = [(n, c_void_p) for n in ITERATE_FIELDS]
+
+
+class AdmmParams(ctypes.Structure):
+    _fields_ = [("max_sweeps", c_int32), ("eps_pri", c_double), ("eps_dual", c_double),
+                ("sweep_mode", c_int32), ("block_size", c_int32), ("max_blocks", c_int32)]
+
+
+class AdmmResult(ctypes.Structure):
+    _fields_ = [("sweeps", c_int32), ("outcome", c_int32), ("r_norm", c_double), ("s_norm", c_double),
+                ("infeasible_lines", c_int32), ("blocks", c_int32)]
+
+
+class AdmmState(ctypes.Structure):
+    _fields_ = [(n, c_void_p) for n in STATE_FIELDS]
+
+
+EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_qp_build",
+           "acopf_admm_init", "acopf_admm_solve", "acopf_admm_result_get", "acopf_admm_state_get",
+           "acopf_step")
+
+
+class AcopfError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built (there is no
+    other implementation to fall back to)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run paper_2310_13143_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    lib.acopf_last_error.restype = ctypes.c_char_p
+    lib.acopf_workspace_bytes.restype = c_size_t
+    lib.acopf_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
+    P = ctypes.POINTER
+    lib.acopf_setup.argtypes = [P(Grid), c_void_p, c_size_t, c_void_p]
+    lib.acopf_qp_build.argtypes = [P(Grid), P(Iterate), c_double, c_int32, c_void_p, c_void_p]
+    lib.acopf_admm_init.argtypes = [P(Grid), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.acopf_admm_solve.argtypes = [P(Grid), P(AdmmParams), c_void_p, c_void_p, P(AdmmResult)]
+    lib.acopf_admm_result_get.argtypes = [P(Grid), c_void_p, c_void_p, P(AdmmResult)]
+    lib.acopf_admm_state_get.argtypes = [P(Grid), c_void_p, P(AdmmState), c_void_p]
+    lib.acopf_step.argtypes = [P(Grid), P(Iterate), c_void_p, P(Iterate), c_void_p]
+    for name in EXPORTS[2:]:
+        getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def check(code: int):
+    if code != ACOPF_OK:
+        raise AcopfError(code, load().acopf_last_error().decode())

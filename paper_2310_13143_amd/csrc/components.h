@@ -1,0 +1,492 @@
+// Per-component arithmetic of the ADMM QP solver: one call handles one line,
+// one generator or one bus.  The GPU kernels call these from one thread per
+// component; every memory access is an explicit structure-of-arrays index so
+// that the same source can be compiled for the host to test its arithmetic.
+#pragma once
+
+#include "line_qp.h"
+#include "small_linalg.h"
+#include "workspace.h"
+#include "../../include/acopf_admm.h"
+
+namespace acopf {
+
+static constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// QP data of line l at the iterate (Sections III-B, III-C and IV-B2).
+// Returns false if the elimination pivot wR cos + wI sin vanishes or the
+// data are not finite.
+ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double delta, int mode,
+                         const Workspace& w, int l) {
+  const int L = g.n_line;
+  const int f = g.line_from[l], t = g.line_to[l];
+  const double wi = x.w[f], wj = x.w[t], thi = x.th[f], thj = x.th[t];
+  const double wR = x.wR[l], wI = x.wI[l];
+  const double p11 = x.pi[l], p12 = x.pi[L + l], p13 = x.pi[2 * L + l], p14 = x.pi[3 * L + l];
+  const double gii = g.gii[l], bii = g.bii[l], gij = g.gij[l], bij = g.bij[l];
+  const double gji = g.gji[l], bji = g.bji[l], gjj = g.gjj[l], bjj = g.bjj[l];
+  const double ph = thi - thj;
+  const double s = sin(ph), c = cos(ph);
+  // elimination (eq. elim): linearised opfc11, opfc12 solved for d_wR, d_wI
+  const double K = wR * c + wI * s;
+  const double r1 = wi * wj - wR * wR - wI * wI;
+  const double r2 = -wR * s + wI * c;
+  bool ok = fabs(K) >= 1e-8;
+  const double K2 = 2.0 * (ok ? K : 1.0);
+  const double aR[4] = {c * wj / K2, -wI, c * wi / K2, wI};
+  const double aI[4] = {s * wj / K2, wR, s * wi / K2, -wR};
+  const double bR = (c * r1 + 2.0 * wI * r2) / K2;
+  const double bI = (s * r1 - 2.0 * wR * r2) / K2;
+
+  // Hessian of L_ij (eq. lag) in u = (w_i, th_i, wR, wI, w_j, th_j)
+  double H[6][6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) H[a][b] = 0.0;
+  H[2][2] += 2.0 * p11;
+  H[3][3] += 2.0 * p11;
+  H[0][4] -= p11;
+  H[4][0] -= p11;
+  const double T = -wR * s + wI * c;
+  H[1][1] += p12 * T;
+  H[5][5] += p12 * T;
+  H[1][5] -= p12 * T;
+  H[5][1] -= p12 * T;
+  H[2][1] += p12 * c; H[1][2] += p12 * c;
+  H[2][5] -= p12 * c; H[5][2] -= p12 * c;
+  H[3][1] += p12 * s; H[1][3] += p12 * s;
+  H[3][5] -= p12 * s; H[5][3] -= p12 * s;
+  {
+    const double gp_ij[6] = {gii, 0.0, gij, bij, 0.0, 0.0};
+    const double gq_ij[6] = {-bii, 0.0, -bij, gij, 0.0, 0.0};
+    const double gp_ji[6] = {0.0, 0.0, gji, -bji, gjj, 0.0};
+    const double gq_ji[6] = {0.0, 0.0, -bji, -gji, -bjj, 0.0};
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = 0; b < 6; ++b)
+        H[a][b] -= 2.0 * p13 * (gp_ij[a] * gp_ij[b] + gq_ij[a] * gq_ij[b]) +
+                   2.0 * p14 * (gp_ji[a] * gp_ji[b] + gq_ji[a] * gq_ji[b]);
+  }
+  // A (6x4): rows e0, e1, aR, aI, e2, e3; M = A^T H A, q = A^T H b
+  double A[6][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    A[0][k] = (k == 0) ? 1.0 : 0.0;
+    A[1][k] = (k == 1) ? 1.0 : 0.0;
+    A[2][k] = aR[k];
+    A[3][k] = aI[k];
+    A[4][k] = (k == 2) ? 1.0 : 0.0;
+    A[5][k] = (k == 3) ? 1.0 : 0.0;
+  }
+  double HA[6][4];
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) v += H[a][b] * A[b][k];
+      HA[a][k] = v;
+    }
+  double M[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v += A[a][i] * HA[a][j];
+      M[i][j] = v;
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) {
+      double v = 0.5 * (M[i][j] + M[j][i]);
+      M[i][j] = v;
+      M[j][i] = v;
+    }
+  if (mode == ACOPF_HESSIAN_PSD) psd_project4(M);
+  double q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = HA[2][i] * bR + HA[3][i] * bI;  // (A^T H b)_i = (HA)^T b
+  const double c0 = 0.5 * (bR * bR * H[2][2] + 2.0 * bR * bI * H[2][3] + bI * bI * H[3][3]);
+
+  // flow map (substitution after eq. line_kernel)
+  double F[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double e0 = (k == 0) ? 1.0 : 0.0, e2 = (k == 2) ? 1.0 : 0.0;
+    F[0][k] = gii * e0 + gij * aR[k] + bij * aI[k];
+    F[1][k] = -bii * e0 - bij * aR[k] + gij * aI[k];
+    F[2][k] = gjj * e2 + gji * aR[k] - bji * aI[k];
+    F[3][k] = -bjj * e2 - bji * aR[k] - gji * aI[k];
+  }
+  const double f0[4] = {gij * bR + bij * bI, -bij * bR + gij * bI, gji * bR - bji * bI,
+                        -bji * bR - gji * bI};
+  // boxes of the voltage copies: bounds shifted to the iterate and the TR
+  double lo[4], hi[4];
+  {
+    const int bus[2] = {f, t};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = bus[e];
+      const double vl = g.vmin[i], vh = g.vmax[i];
+      double wl = fmax(-delta, vl * vl - x.w[i]);
+      double wh = fmin(delta, vh * vh - x.w[i]);
+      double tl = fmax(-delta, -kTwoPi - x.th[i]);
+      double th = fmin(delta, kTwoPi - x.th[i]);
+      if (i == g.ref_bus) { tl = 0.0; th = 0.0; }
+      lo[2 * e] = fmin(wl, wh);
+      hi[2 * e] = wh;
+      lo[2 * e + 1] = fmin(tl, th);
+      hi[2 * e + 1] = th;
+    }
+  }
+  // flows at the iterate and linearised limits (opfqpc13, opfqpc14)
+  const double pij = gii * wi + gij * wR + bij * wI;
+  const double qij = -bii * wi - bij * wR + gij * wI;
+  const double pji = gjj * wj + gji * wR - bji * wI;
+  const double qji = -bjj * wj - bji * wR - gji * wI;
+  double Gr[2][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Gr[0][k] = 2.0 * pij * F[0][k] + 2.0 * qij * F[1][k];
+    Gr[1][k] = 2.0 * pji * F[2][k] + 2.0 * qji * F[3][k];
+  }
+  const double sij = g.smax_ij[l], sji = g.smax_ji[l];
+  const double hr0 = sij * sij - pij * pij - qij * qij - 2.0 * pij * f0[0] - 2.0 * qij * f0[1];
+  const double hr1 = sji * sji - pji * pji - qji * qji - 2.0 * pji * f0[2] - 2.0 * qji * f0[3];
+  ok = ok && isfinite(hr0) && isfinite(hr1) && isfinite(c0);
+
+  double* d = w.line;
+  double Mp[10];
+  sym_pack(M, Mp);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) d[(LF_M + k) * L + l] = Mp[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    d[(LF_Q + k) * L + l] = q[k];
+    d[(LF_F0 + k) * L + l] = f0[k];
+    d[(LF_LO + k) * L + l] = lo[k];
+    d[(LF_HI + k) * L + l] = hi[k];
+    d[(LF_AR + k) * L + l] = aR[k];
+    d[(LF_AI + k) * L + l] = aI[k];
+    d[(LF_G + k) * L + l] = Gr[0][k];
+    d[(LF_G + 4 + k) * L + l] = Gr[1][k];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[(LF_F + 4 * r + k) * L + l] = F[r][k];
+  d[(LF_H + 0) * L + l] = hr0;
+  d[(LF_H + 1) * L + l] = hr1;
+  d[LF_BR * L + l] = bR;
+  d[LF_BI * L + l] = bI;
+  d[(LF_PK + 0) * L + l] = pij;
+  d[(LF_PK + 1) * L + l] = qij;
+  d[(LF_PK + 2) * L + l] = pji;
+  d[(LF_PK + 3) * L + l] = qji;
+  d[LF_C0 * L + l] = c0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    d[(LF_HR + k) * L + l] = H[2][k];
+    d[(LF_HI_ROW + k) * L + l] = H[3][k];
+  }
+  return ok;
+}
+
+ACOPF_HD void build_gen(const acopf_grid& g, const acopf_iterate& x, double delta, const Workspace& w,
+                        int k) {
+  const int G = g.n_gen;
+  const double p = x.pg[k], qv = x.qg[k];
+  double* d = w.gen;
+  d[GF_FP * G + k] = 2.0 * g.cost2[k] * p + g.cost1[k];
+  d[GF_FPP * G + k] = 2.0 * g.cost2[k];
+  const double phi = fmin(delta, g.pmax[k] - p), qhi = fmin(delta, g.qmax[k] - qv);
+  d[GF_PLO * G + k] = fmin(fmax(-delta, g.pmin[k] - p), phi);
+  d[GF_PHI * G + k] = phi;
+  d[GF_QLO * G + k] = fmin(fmax(-delta, g.qmin[k] - qv), qhi);
+  d[GF_QHI * G + k] = qhi;
+}
+
+// p^{d,(k)}, q^{d,(k)} of bus i (constants after eq. acopf_qppf).
+ACOPF_HD void build_bus(const acopf_grid& g, const acopf_iterate& x, const Workspace& w, int i) {
+  double pd = g.pd[i] + g.gsh[i] * x.w[i];
+  double qd = g.qd[i] - g.bsh[i] * x.w[i];
+  for (int e = w.bus_gen_ptr[i]; e < w.bus_gen_ptr[i + 1]; ++e) {
+    const int k = w.bus_gen[e];
+    pd -= x.pg[k];
+    qd -= x.qg[k];
+  }
+  for (int e = w.bus_end_ptr[i]; e < w.bus_end_ptr[i + 1]; ++e) {
+    const int code = w.bus_end[e];
+    const int l = code >> 1;
+    const double wR = x.wR[l], wI = x.wI[l];
+    if ((code & 1) == 0) {
+      pd += g.gii[l] * x.w[i] + g.gij[l] * wR + g.bij[l] * wI;
+      qd += -g.bii[l] * x.w[i] - g.bij[l] * wR + g.gij[l] * wI;
+    } else {
+      pd += g.gjj[l] * x.w[i] + g.gji[l] * wR - g.bji[l] * wI;
+      qd += -g.bjj[l] * x.w[i] - g.bji[l] * wR - g.gji[l] * wI;
+    }
+  }
+  w.bus_pdk[i] = pd;
+  w.bus_qdk[i] = qd;
+}
+
+// Factorisation of line l's subproblem matrix for the current penalties:
+// P = Q^{-1}, Q = M + sum_f rho_f F_f^T F_f + diag(rho_v), and the constant
+// part of its linear term, q + sum_f rho_f f0_f F_f.  False if Q is not
+// positive definite.
+ACOPF_HD bool prep_line(const Workspace& w, int l) {
+  const int L = w.n_line;
+  const double* d = w.line;
+  double Mp[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) Mp[k] = d[(LF_M + k) * L + l];
+  double Q[4][4];
+  sym_unpack(Mp, Q);
+  double cc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cc[i] = d[(LF_Q + i) * L + l];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double rho = w.rho_l[r * L + l];
+    const double f0 = d[(LF_F0 + r) * L + l];
+    double Fr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Fr[k] = d[(LF_F + 4 * r + k) * L + l];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cc[i] += rho * f0 * Fr[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Q[i][j] += rho * Fr[i] * Fr[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Q[i][i] += w.rho_l[(4 + i) * L + l];
+  double Lc[4][4], Pinv[4][4];
+  const bool ok = chol4(Q, Lc);
+  chol4_inverse(Lc, Pinv);
+  double Pp[10];
+  sym_pack(Pinv, Pp);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) w.line_P[k * L + l] = Pp[k];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w.line_cc[i * L + l] = cc[i];
+  return ok;
+}
+
+// Line update of one ADMM sweep (eq. line_kernel): exact minimiser of the
+// line subproblem given the multipliers and the bus-side values of the
+// previous sweep.  Writes the line-side values of the 8 couplings and the
+// limit-row multipliers; returns the solver status (0 solved).
+ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
+  const int L = w.n_line;
+  const double* d = w.line;
+  const int f = g.line_from[l], t = g.line_to[l];
+  double Pp[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) Pp[k] = w.line_P[k * L + l];
+  double F[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F[r][k] = d[(LF_F + 4 * r + k) * L + l];
+  const double xbv[4] = {w.dw[f], w.dth[f], w.dw[t], w.dth[t]};
+  double c[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    c[i] = w.line_cc[i * L + l] + w.lam_l[(4 + i) * L + l] - w.rho_l[(4 + i) * L + l] * xbv[i];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double a = w.lam_l[r * L + l] - w.rho_l[r * L + l] * w.xbar_f[r * L + l];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] += F[r][i] * a;
+  }
+  double lo[4], hi[4], G[2][4], h[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    lo[k] = d[(LF_LO + k) * L + l];
+    hi[k] = d[(LF_HI + k) * L + l];
+    G[0][k] = d[(LF_G + k) * L + l];
+    G[1][k] = d[(LF_G + 4 + k) * L + l];
+  }
+  h[0] = d[(LF_H + 0) * L + l];
+  h[1] = d[(LF_H + 1) * L + l];
+  const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double fl = F[r][0] * res.z[0] + F[r][1] * res.z[1] + F[r][2] * res.z[2] +
+                      F[r][3] * res.z[3] + d[(LF_F0 + r) * L + l];
+    w.xl[r * L + l] = fl;
+    w.xl[(4 + r) * L + l] = res.z[r];
+  }
+  w.mu[l] = res.mu[0];
+  w.mu[L + l] = res.mu[1];
+  return res.status;
+}
+
+// Generator update (eq. gen_kernel, closed form clamp) of generator k.
+ACOPF_HD void update_gen(const Workspace& w, int k) {
+  const int G = w.n_gen;
+  const double* d = w.gen;
+  const double rp = w.rho_g[k], rq = w.rho_g[G + k];
+  double xp = (rp * w.xbar_g[k] - w.lam_g[k] - d[GF_FP * G + k]) / (d[GF_FPP * G + k] + rp);
+  double xq = (rq * w.xbar_g[G + k] - w.lam_g[G + k]) / rq;
+  xp = fmin(fmax(xp, d[GF_PLO * G + k]), d[GF_PHI * G + k]);
+  xq = fmin(fmax(xq, d[GF_QLO * G + k]), d[GF_QHI * G + k]);
+  w.xg[k] = xp;
+  w.xg[G + k] = xq;
+}
+
+// Bus update (eq. bus_kernel, closed form of eq. bus_kernel_simp with
+// diagonal Q), multiplier update (eq. multiplier) of every coupling that
+// ends at bus i, and that bus's contribution to ||r||^2 and ||s||^2.
+// Generators of the bus are updated first (they only read values of the
+// previous bus update), which keeps the two-block order of Algorithm 2.
+ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2) {
+  const int G = w.n_gen, L = w.n_line;
+  const int g0 = w.bus_gen_ptr[i], g1 = w.bus_gen_ptr[i + 1];
+  const int e0 = w.bus_end_ptr[i], e1 = w.bus_end_ptr[i + 1];
+  double spp = 0.0, sqq = 0.0, rp = 0.0, rq = 0.0, qw = 0.0, cw = 0.0, qt = 0.0, ct = 0.0;
+  for (int e = g0; e < g1; ++e) {
+    const int k = w.bus_gen[e];
+    update_gen(w, k);
+    const double rhp = w.rho_g[k], rhq = w.rho_g[G + k];
+    spp += 1.0 / rhp;
+    sqq += 1.0 / rhq;
+    rp += (rhp * w.xg[k] + w.lam_g[k]) / rhp;
+    rq += (rhq * w.xg[G + k] + w.lam_g[G + k]) / rhq;
+  }
+  for (int e = e0; e < e1; ++e) {
+    const int code = w.bus_end[e];
+    const int l = code >> 1, side = code & 1;
+    const int kp = 2 * side, kq = kp + 1, kw = 4 + 2 * side, kt = kw + 1;
+    const double rhp = w.rho_l[kp * L + l], rhq = w.rho_l[kq * L + l];
+    const double rhw = w.rho_l[kw * L + l], rht = w.rho_l[kt * L + l];
+    spp += 1.0 / rhp;
+    sqq += 1.0 / rhq;
+    rp -= (rhp * w.xl[kp * L + l] + w.lam_l[kp * L + l]) / rhp;
+    rq -= (rhq * w.xl[kq * L + l] + w.lam_l[kq * L + l]) / rhq;
+    qw += rhw;
+    cw += rhw * w.xl[kw * L + l] + w.lam_l[kw * L + l];
+    qt += rht;
+    ct += rht * w.xl[kt * L + l] + w.lam_l[kt * L + l];
+  }
+  const double gsh = g.gsh[i], bsh = g.bsh[i];
+  spp += gsh * gsh / qw;
+  sqq += bsh * bsh / qw;
+  const double spq = -gsh * bsh / qw;
+  rp += -gsh * cw / qw - w.bus_pdk[i];
+  rq += bsh * cw / qw - w.bus_qdk[i];
+  const double det = spp * sqq - spq * spq;
+  const double nup = (sqq * rp - spq * rq) / det;
+  const double nuq = (spp * rq - spq * rp) / det;
+  const double dw_new = (cw + gsh * nup - bsh * nuq) / qw;
+  const double dth_new = (i == g.ref_bus) ? 0.0 : ct / qt;
+  const double dw_old = w.dw[i], dth_old = w.dth[i];
+  double rr = 0.0, ss = 0.0;
+  for (int e = g0; e < g1; ++e) {
+    const int k = w.bus_gen[e];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int idx = j * G + k;
+      const double rho = w.rho_g[idx], xv = w.xg[idx], lam = w.lam_g[idx];
+      const double xb = (rho * xv + lam - (j == 0 ? nup : nuq)) / rho;
+      const double ds = rho * (xb - w.xbar_g[idx]);
+      w.lam_g[idx] = lam + rho * (xv - xb);
+      w.xbar_g[idx] = xb;
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+    }
+  }
+  for (int e = e0; e < e1; ++e) {
+    const int code = w.bus_end[e];
+    const int l = code >> 1, side = code & 1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {  // flow copies p, q
+      const int kk = 2 * side + j;
+      const int idx = kk * L + l;
+      const double rho = w.rho_l[idx], xv = w.xl[idx], lam = w.lam_l[idx];
+      const double xb = (rho * xv + lam + (j == 0 ? nup : nuq)) / rho;
+      const int fi = kk * L + l;
+      const double ds = rho * (xb - w.xbar_f[fi]);
+      w.lam_l[idx] = lam + rho * (xv - xb);
+      w.xbar_f[fi] = xb;
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {  // voltage copies w, th
+      const int idx = (4 + 2 * side + j) * L + l;
+      const double rho = w.rho_l[idx], xv = w.xl[idx], lam = w.lam_l[idx];
+      const double xb = (j == 0) ? dw_new : dth_new;
+      const double ds = rho * (xb - ((j == 0) ? dw_old : dth_old));
+      w.lam_l[idx] = lam + rho * (xv - xb);
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+    }
+  }
+  w.dw[i] = dw_new;
+  w.dth[i] = dth_new;
+  w.nu[i] = nup;
+  w.nu[w.n_bus + i] = nuq;
+  r2 += rr;
+  s2 += ss;
+}
+
+// Step and multiplier estimates of line l (Section IV-B5).
+ACOPF_HD void step_line(const acopf_grid& g, const acopf_iterate& x, const Workspace& w,
+                        const acopf_iterate& d, int l) {
+  const int L = w.n_line;
+  const double* q = w.line;
+  const int f = g.line_from[l], t = g.line_to[l];
+  double aR[4], aI[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    aR[k] = q[(LF_AR + k) * L + l];
+    aI[k] = q[(LF_AI + k) * L + l];
+  }
+  const double bR = q[LF_BR * L + l], bI = q[LF_BI * L + l];
+  // step: elimination applied to the bus-side values
+  const double zb[4] = {w.dw[f], w.dth[f], w.dw[t], w.dth[t]};
+  d.wR[l] = aR[0] * zb[0] + aR[1] * zb[1] + aR[2] * zb[2] + aR[3] * zb[3] + bR;
+  d.wI[l] = aI[0] * zb[0] + aI[1] * zb[1] + aI[2] * zb[2] + aI[3] * zb[3] + bI;
+  // multipliers from the line subproblem's KKT conditions at its own solution
+  double z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = w.xl[(4 + k) * L + l];
+  const double u[6] = {z[0], z[1], aR[0] * z[0] + aR[1] * z[1] + aR[2] * z[2] + aR[3] * z[3] + bR,
+                       aI[0] * z[0] + aI[1] * z[1] + aI[2] * z[2] + aI[3] * z[3] + bI, z[2], z[3]};
+  double huR = 0.0, huI = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    huR += q[(LF_HR + k) * L + l] * u[k];
+    huI += q[(LF_HI_ROW + k) * L + l] * u[k];
+  }
+  const double gij = g.gij[l], bij = g.bij[l], gji = g.gji[l], bji = g.bji[l];
+  const double pij = q[(LF_PK + 0) * L + l], qij = q[(LF_PK + 1) * L + l];
+  const double pji = q[(LF_PK + 2) * L + l], qji = q[(LF_PK + 3) * L + l];
+  const double lam[4] = {w.lam_l[l], w.lam_l[L + l], w.lam_l[2 * L + l], w.lam_l[3 * L + l]};
+  const double mu0 = w.mu[l], mu1 = w.mu[L + l];
+  const double gR = huR + lam[0] * gij - lam[1] * bij + lam[2] * gji - lam[3] * bji +
+                    mu0 * (2.0 * pij * gij - 2.0 * qij * bij) + mu1 * (2.0 * pji * gji - 2.0 * qji * bji);
+  const double gI = huI + lam[0] * bij + lam[1] * gij - lam[2] * bji - lam[3] * gji +
+                    mu0 * (2.0 * pij * bij + 2.0 * qij * gij) + mu1 * (-2.0 * pji * bji - 2.0 * qji * gji);
+  const double ph = x.th[f] - x.th[t];
+  const double s = sin(ph), c = cos(ph);
+  const double wR = x.wR[l], wI = x.wI[l];
+  // [2wR  s] [pi11]     [gR]
+  // [2wI -c] [pi12] = - [gI]
+  const double det = -2.0 * wR * c - 2.0 * wI * s;
+  d.pi[l] = (gR * c + s * gI) / det;
+  d.pi[L + l] = (-2.0 * wR * gI + 2.0 * wI * gR) / det;
+  d.pi[2 * L + l] = -mu0;
+  d.pi[3 * L + l] = -mu1;
+}
+
+}  // namespace acopf

@@ -1,0 +1,111 @@
+// Host build of the library's per-component arithmetic (the device code in
+// paper_2310_13143_amd/csrc compiled as plain C++), used by CPU tests to
+// check the kernels' arithmetic against the oracle before any GPU run.  The
+// loops below stand in for the kernels' thread grids, in component order.
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../paper_2310_13143_amd/csrc/components.h"
+
+using namespace acopf;
+
+extern "C" {
+
+void emu_line_qp(int n, const double* P, const double* c, const double* lo, const double* hi,
+                 const double* G, const double* h, double* z, double* mu, int* status) {
+  for (int k = 0; k < n; ++k) {
+    double Gk[2][4] = {{G[8 * k + 0], G[8 * k + 1], G[8 * k + 2], G[8 * k + 3]},
+                       {G[8 * k + 4], G[8 * k + 5], G[8 * k + 6], G[8 * k + 7]}};
+    LineQPResult r = solve_line_qp(P + 10 * k, c + 4 * k, lo + 4 * k, hi + 4 * k, Gk, h + 2 * k);
+    for (int i = 0; i < 4; ++i) z[4 * k + i] = r.z[i];
+    mu[2 * k] = r.mu[0];
+    mu[2 * k + 1] = r.mu[1];
+    status[k] = r.status;
+  }
+}
+
+void emu_psd_project(int n, double* m) {
+  for (int k = 0; k < n; ++k) {
+    double a[4][4];
+    std::memcpy(a, m + 16 * k, sizeof(a));
+    psd_project4(a);
+    std::memcpy(m + 16 * k, a, sizeof(a));
+  }
+}
+
+// Full solve emulation: setup tables, QP build, init, `sweeps` sweeps, step.
+// The workspace is a host buffer of acopf_workspace_bytes-equivalent size.
+size_t emu_workspace_bytes(int nb, int nl, int ng) { return layout_workspace(nullptr, nb, nl, ng, nullptr); }
+
+int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode, const double* rho_g,
+            const double* rho_l, const double* lam_g, const double* lam_l, int sweeps, void* ws_base,
+            const acopf_iterate* d, double* rs_out) {
+  const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
+  Workspace w;
+  layout_workspace(ws_base, nb, nl, ng, &w);
+  // incidence tables (same construction as acopf_setup)
+  std::vector<int> deg(nb, 0), gdeg(nb, 0);
+  for (int l = 0; l < nl; ++l) { deg[g->line_from[l]]++; deg[g->line_to[l]]++; }
+  for (int k = 0; k < ng; ++k) gdeg[g->gen_bus[k]]++;
+  w.bus_end_ptr[0] = 0;
+  w.bus_gen_ptr[0] = 0;
+  for (int i = 0; i < nb; ++i) {
+    w.bus_end_ptr[i + 1] = w.bus_end_ptr[i] + deg[i];
+    w.bus_gen_ptr[i + 1] = w.bus_gen_ptr[i] + gdeg[i];
+  }
+  std::vector<int> fe(w.bus_end_ptr, w.bus_end_ptr + nb), fg(w.bus_gen_ptr, w.bus_gen_ptr + nb);
+  for (int l = 0; l < nl; ++l) {
+    w.bus_end[fe[g->line_from[l]]++] = 2 * l;
+    w.bus_end[fe[g->line_to[l]]++] = 2 * l + 1;
+  }
+  for (int k = 0; k < ng; ++k) w.bus_gen[fg[g->gen_bus[k]]++] = k;
+  int bad = 0;
+  for (int l = 0; l < nl; ++l) bad += build_line(*g, *x, delta, mode, w, l) ? 0 : 1;
+  for (int k = 0; k < ng; ++k) build_gen(*g, *x, delta, w, k);
+  for (int i = 0; i < nb; ++i) build_bus(*g, *x, w, i);
+  std::memcpy(w.rho_g, rho_g, sizeof(double) * 2 * ng);
+  std::memcpy(w.rho_l, rho_l, sizeof(double) * 8 * nl);
+  if (lam_l) {
+    std::memcpy(w.lam_g, lam_g, sizeof(double) * 2 * ng);
+    std::memcpy(w.lam_l, lam_l, sizeof(double) * 8 * nl);
+  } else {
+    std::memset(w.lam_g, 0, sizeof(double) * 2 * ng);
+    std::memset(w.lam_l, 0, sizeof(double) * 8 * nl);
+  }
+  std::memset(w.xg, 0, sizeof(double) * 2 * ng);
+  std::memset(w.xbar_g, 0, sizeof(double) * 2 * ng);
+  std::memset(w.xl, 0, sizeof(double) * 8 * nl);
+  std::memset(w.xbar_f, 0, sizeof(double) * 4 * nl);
+  std::memset(w.dw, 0, sizeof(double) * nb);
+  std::memset(w.dth, 0, sizeof(double) * nb);
+  std::memset(w.nu, 0, sizeof(double) * 2 * nb);
+  std::memset(w.mu, 0, sizeof(double) * 2 * nl);
+  for (int l = 0; l < nl; ++l) bad += prep_line(w, l) ? 0 : 1000;
+  int infeasible = 0;
+  for (int k = 0; k < sweeps; ++k) {
+    infeasible = 0;
+    for (int l = 0; l < nl; ++l) infeasible += update_line(*g, w, l) != 0;
+    double r2 = 0.0, s2 = 0.0;
+    for (int i = 0; i < nb; ++i) update_bus(*g, w, i, r2, s2);
+    rs_out[2 * k] = r2;
+    rs_out[2 * k + 1] = s2;
+  }
+  if (d) {
+    for (int l = 0; l < nl; ++l) step_line(*g, *x, w, *d, l);
+    for (int i = 0; i < nb; ++i) { d->w[i] = w.dw[i]; d->th[i] = w.dth[i]; }
+    for (int k = 0; k < ng; ++k) { d->pg[k] = w.xg[k]; d->qg[k] = w.xg[ng + k]; }
+  }
+  return bad * 10000 + infeasible;
+}
+
+// Addresses of the ADMM state arrays inside a host workspace, in the order
+// xl, lam_l, xbar_f, xg, lam_g, dw, dth, nu.
+void emu_state_ptrs(void* base, int nb, int nl, int ng, double** out) {
+  Workspace w;
+  layout_workspace(base, nb, nl, ng, &w);
+  out[0] = w.xl; out[1] = w.lam_l; out[2] = w.xbar_f; out[3] = w.xg;
+  out[4] = w.lam_g; out[5] = w.dw; out[6] = w.dth; out[7] = w.nu;
+}
+
+}  // extern "C"

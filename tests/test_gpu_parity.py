@@ -1,0 +1,239 @@
+"""Parity of the HIP path with the oracle on the GPU.
+
+Iterates of the ADMM sweeps (Algorithm 2) must match the serial oracle
+within 1e-8 (norm-wise relative, per array) for fixed sweep counts; the
+limit must match the direct solve of the QP within 1e-6 relative objective
+and 1e-5 constraint violation.  All calls go through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+
+from synth.grids import grid_14, grid_2000, grid_70000, tiny_grid
+from oracle import acopf, admm, direct, qp as qpm, sqp
+from tests._util import rel_err, start_point
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _dev():
+    from paper_2310_13143_amd.solver import DeviceGrid
+    return DeviceGrid
+
+
+def _rho(g, seed, lo=5e3, hi=3e4):
+    rng = np.random.default_rng(seed)
+    return admm.Rho(rng.uniform(lo, hi, (g.n_gen, 2)), rng.uniform(lo, hi, (g.n_line, 8)))
+
+
+def _run_gpu(g, x, pi, delta, rho, lam_g, lam_l, sweeps, mode=0, eps=0.0, hessian=0, **kw):
+    dg = _dev()(g)
+    xi = dg.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pi)
+    dg.qp_build(xi, delta, hessian)
+    dg.admm_init(rho.g.T.reshape(-1), rho.l.T.reshape(-1),
+                 None if lam_g is None else lam_g.T.reshape(-1), None if lam_l is None else lam_l.T.reshape(-1))
+    res = dg.admm_solve(sweeps, eps, eps, sweep_mode=mode, **kw)
+    st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    return dg, xi, res, st
+
+
+def _compare_state(st, ref, tol=TOL):
+    G, L, B = ref.xg.shape[0], ref.xl.shape[0], ref.dw.shape[0]
+    pairs = {
+        "xl": (st["xl"].reshape(8, L).T, ref.xl), "lam_l": (st["lam_l"].reshape(8, L).T, ref.lam_l),
+        "xbar_f": (st["xbar_f"].reshape(4, L).T, ref.xbar_f), "xg": (st["xg"].reshape(2, G).T, ref.xg),
+        "lam_g": (st["lam_g"].reshape(2, G).T, ref.lam_g), "xbar_g": (st["xbar_g"].reshape(2, G).T, ref.xbar_g),
+        "dw": (st["dw"], ref.dw), "dth": (st["dth"], ref.dth), "nu": (st["nu"].reshape(2, B).T, ref.nu),
+    }
+    for name, (a, b) in pairs.items():
+        e = rel_err(a, b)
+        assert e <= tol, f"{name}: relative error {e:.3e}"
+
+
+CASES = {
+    "ring14": lambda: grid_14(),
+    "tiny_shunt": lambda: tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04),
+}
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "launches"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_sweeps_match_oracle(case, mode):
+    print(f"[gpu] sweeps {case} mode={mode}", flush=True)
+    g = CASES[case]()
+    x, pi = start_point(g, pi_scale=50.0, seed=3)
+    delta = 0.05
+    rho = _rho(g, 4)
+    rng = np.random.default_rng(5)
+    lam_g, lam_l = rng.standard_normal((g.n_gen, 2)) * 100, rng.standard_normal((g.n_line, 8)) * 100
+    nsw = 60
+    Q = qpm.build_qp(g, x, pi, delta, "psd")
+    ref = admm.solve(g, Q, rho, nsw, 0.0, 0.0, state=admm.warm_state(g, lam_g, lam_l), record=True)
+    dg, xi, res, st = _run_gpu(g, x, pi, delta, rho, lam_g, lam_l, nsw, mode=mode)
+    assert res["sweeps"] == nsw and res["infeasible_lines"] == 0
+    _compare_state(st, ref.state)
+    assert abs(res["r"] - ref.r) <= 1e-7 * ref.r and abs(res["s"] - ref.s) <= 1e-7 * ref.s
+    # step and multiplier estimates (Section IV-B5)
+    d = {k: v.cpu().numpy() for k, v in dg.step(xi).items()}
+    dref = sqp.assemble_step(g, Q, ref.state)
+    pref = sqp.recover_pi(g, x, Q, ref.state)
+    for k in ("pg", "qg", "w", "th", "wR", "wI"):
+        assert rel_err(d[k], getattr(dref, k)) <= TOL, k
+    assert rel_err(d["pi"].reshape(4, -1).T, pref) <= 1e-7
+
+
+def test_raw_hessian_and_cold_start_match_oracle():
+    print("[gpu] raw hessian ring14", flush=True)
+    g = grid_14()
+    x, pi = start_point(g, pi_scale=20.0, seed=8)
+    rho = admm.Rho.scalar(g, 2e4)
+    Q = qpm.build_qp(g, x, pi, 0.1, "raw")
+    ref = admm.solve(g, Q, rho, 50, 0.0, 0.0)
+    _, _, res, st = _run_gpu(g, x, pi, 0.1, rho, None, None, 50, hessian=1)
+    _compare_state(st, ref.state)
+
+
+def test_stop_rule_and_limit_match_direct_solve():
+    """With eps > 0 the GPU stops at the oracle's sweep (ties within 1
+    sweep allowed) and its limit solves the QP: objective within 1e-6
+    relative and violation within 1e-5 of the direct interior-point solve."""
+    print("[gpu] stop rule tiny", flush=True)
+    g = tiny_grid(seed=8, n_bus=5, n_line=6, n_gen=2, shunt_scale=0.03)
+    x, pi = start_point(g, pi_scale=30.0, seed=0)
+    Q = qpm.build_qp(g, x, pi, 0.2, "psd")
+    rho = admm.Rho.scalar(g, 1e3)
+    ref = admm.solve(g, Q, rho, 40000, 1e-9, 1e-9)
+    ds = direct.solve(g, Q)
+    for mode in (0, 1):
+        dg, xi, res, st = _run_gpu(g, x, pi, 0.2, rho, None, None, 40000, mode=mode, eps=1e-9)
+        assert res["converged"] and abs(res["sweeps"] - ref.sweeps) <= 1
+        d = {k: v.cpu().numpy() for k, v in dg.step(xi).items()}
+        z = np.stack([d["w"][g.f], d["th"][g.f], d["w"][g.t], d["th"][g.t]], 1)
+        obj = qpm.qp_objective(Q, d["pg"], z)
+        assert abs(obj - ds.objective) <= 1e-6 * abs(ds.objective)
+        assert direct.max_violation(g, Q, np.concatenate([d["pg"], d["qg"], d["w"], d["th"]])) <= 1e-5
+
+
+def test_determinism_bitwise():
+    print("[gpu] determinism ring14", flush=True)
+    g = grid_14()
+    x, pi = start_point(g, pi_scale=10.0, seed=1)
+    rho = admm.Rho.scalar(g, 2e4)
+    _, _, r1, s1 = _run_gpu(g, x, pi, 0.1, rho, None, None, 200)
+    _, _, r2, s2 = _run_gpu(g, x, pi, 0.1, rho, None, None, 200)
+    for k in s1:
+        assert np.array_equal(s1[k], s2[k]), k
+    assert r1["r"] == r2["r"] and r1["s"] == r2["s"]
+
+
+def test_rgg2000_sweeps_match_oracle():
+    print("[gpu] rgg2000 20 sweeps", flush=True)
+    g = grid_2000()
+    x, pi = start_point(g, pi_scale=20.0, seed=2)
+    rho = admm.Rho.scalar(g, 2e4)
+    Q = qpm.build_qp(g, x, pi, 0.05, "psd")
+    ref = admm.solve(g, Q, rho, 20, 0.0, 0.0)
+    for mode in (0, 1):
+        _, _, res, st = _run_gpu(g, x, pi, 0.05, rho, None, None, 20, mode=mode)
+        _compare_state(st, ref.state)
+
+
+def test_rgg70000_sampled_line_and_bus_updates():
+    """At 70,000 buses (88,000 lines, the bench workload) the oracle checks one
+    sweep of sampled lines and all buses from the GPU's own previous state."""
+    print("[gpu] rgg70000 sampled", flush=True)
+    g = grid_70000()
+    x, pi = start_point(g, pi_scale=20.0, seed=2)
+    rho = admm.Rho.scalar(g, 2e4)
+    Q = qpm.build_qp(g, x, pi, 0.05, "psd")
+    dg = _dev()(g)
+    xi = dg.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pi)
+    dg.qp_build(xi, 0.05, 0)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    dg.admm_solve(7, 0.0, 0.0)
+    s0 = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    dg.admm_solve(1, 0.0, 0.0)   # continues from the state: one more sweep
+    s1 = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    G, L, B = g.n_gen, g.n_line, g.n_bus
+    st = admm.cold_state(g)
+    st.xg, st.xbar_g, st.lam_g = (s0[k].reshape(2, G).T.copy() for k in ("xg", "xbar_g", "lam_g"))
+    st.xl, st.lam_l = (s0[k].reshape(8, L).T.copy() for k in ("xl", "lam_l"))
+    st.xbar_f = s0["xbar_f"].reshape(4, L).T.copy()
+    st.dw, st.dth = s0["dw"].copy(), s0["dth"].copy()
+    # sampled line updates
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(L, 2000, replace=False))
+    Qm = admm.line_matrices(Q, rho)
+    sub = _subset_lines(Q, sample)
+    xl_ref, _, _ = admm.line_update(_subgrid(g, sample), sub, st_sub(st, g, sample), _subrho(rho, sample), Qm[sample])
+    assert rel_err(s1["xl"].reshape(8, L).T[sample], xl_ref) <= TOL
+    # all generators and buses from the GPU's line values of this sweep
+    xg = admm.gen_update(Q, st, rho)
+    assert rel_err(s1["xg"].reshape(2, G).T, xg) <= TOL
+    xbar_g, xbar_f, dw, dth, nu = admm.bus_update(g, Q, xg, s1["xl"].reshape(8, L).T, st, rho)
+    assert rel_err(s1["dw"], dw) <= TOL and rel_err(s1["dth"], dth) <= TOL
+    assert rel_err(s1["xbar_f"].reshape(4, L).T, xbar_f) <= TOL
+    assert rel_err(s1["nu"].reshape(2, B).T, nu) <= TOL
+
+
+def _subset_lines(Q, idx):
+    import copy
+    L = copy.copy(Q.line)
+    for f in ("aR", "bR", "aI", "bI", "H", "M", "q", "F", "f0", "lo", "hi", "G", "h", "pk", "c0"):
+        setattr(L, f, getattr(Q.line, f)[idx])
+    out = copy.copy(Q)
+    out.line = L
+    return out
+
+
+def _subgrid(g, idx):
+    import copy
+    s = copy.copy(g)
+    s.f, s.t = g.f[idx], g.t[idx]
+    return s
+
+
+def st_sub(st, g, idx):
+    import copy
+    s = copy.copy(st)
+    s.lam_l, s.xbar_f = st.lam_l[idx], st.xbar_f[idx]
+    return s
+
+
+def _subrho(rho, idx):
+    return admm.Rho(rho.g, rho.l[idx])
+
+
+def test_error_paths():
+    """Invalid arguments and non-finite data are reported as errors."""
+    from paper_2310_13143_amd import AcopfError
+    print("[gpu] error paths", flush=True)
+    g = grid_14()
+    x, pi = start_point(g)
+    DeviceGrid = _dev()
+    dg = DeviceGrid(g)
+    w = x.w.copy()
+    w[3] = np.nan
+    xi = dg.iterate(x.pg, x.qg, w, x.th, x.wR, x.wI, pi)
+    dg.qp_build(xi, 0.1)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    with pytest.raises(AcopfError) as e:
+        dg.admm_solve(5)
+    assert e.value.code == -4
+    with pytest.raises(AcopfError):
+        dg.qp_build(xi, -1.0)
+    bad = grid_14()
+    bad.f = bad.f.copy()
+    bad.f[0] = bad.n_bus + 3
+    with pytest.raises(AcopfError) as e:
+        DeviceGrid(bad)
+    assert e.value.code == -1

@@ -1,0 +1,171 @@
+"""The library's per-component arithmetic (device code compiled for the host
+with g++) against the oracle, on the CPU: line QP solver vs enumeration,
+PSD projection, QP build, full ADMM sweeps and the SQP step/multipliers.
+This checks the kernels' arithmetic and indexing before a GPU runs them."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from synth.grids import grid_14, tiny_grid, power_flow_start
+from oracle import acopf, admm, lineqp, qp as qpm, sqp
+from paper_2310_13143_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("emu") / "libemu.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "native", "emulate.cpp"), "-o", out], check=True)
+    lib = ctypes.CDLL(out)
+    lib.emu_workspace_bytes.restype = ctypes.c_size_t
+    lib.emu_workspace_bytes.argtypes = [ctypes.c_int] * 3
+    lib.emu_run.restype = ctypes.c_int
+    return lib
+
+
+def ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def test_line_qp_solver_matches_enumeration(emu):
+    rng = np.random.default_rng(11)
+    n = 400
+    A = rng.standard_normal((n, 4, 4))
+    Q = A @ np.swapaxes(A, 1, 2) + 0.3 * np.eye(4)
+    # badly scaled instances like the ADMM's (rho ~ 1e4 times admittance^2)
+    Q[: n // 2] *= rng.uniform(1e2, 1e6, (n // 2, 1, 1))
+    c = rng.standard_normal((n, 4)) * np.abs(Q).max(axis=(1, 2))[:, None] * rng.uniform(0.01, 2, (n, 1))
+    lo = -rng.uniform(0.01, 0.3, (n, 4))
+    hi = rng.uniform(0.01, 0.3, (n, 4))
+    G = rng.standard_normal((n, 2, 4))
+    h = rng.uniform(0.01, 0.2, (n, 2))
+    fx = rng.random(n) < 0.25
+    lo[fx, 3] = 0.0
+    hi[fx, 3] = 0.0
+    P = np.linalg.inv(Q)
+    iu = np.triu_indices(4)
+    Pp = np.ascontiguousarray(P[:, iu[0], iu[1]])
+    z = np.zeros((n, 4)); mu = np.zeros((n, 2)); st = np.zeros(n, dtype=np.int32)
+    emu.emu_line_qp(n, ptr(Pp), ptr(np.ascontiguousarray(c)), ptr(lo), ptr(hi), ptr(np.ascontiguousarray(G)),
+                    ptr(h), ptr(z), ptr(mu), ptr(st))
+    zr, mur, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h)
+    assert feas.all() and (st == 0).all()
+    scale = 1.0 + np.abs(zr).max(1)
+    assert (np.abs(z - zr).max(1) / scale).max() < 1e-8
+    mscale = 1.0 + np.abs(mur).max(1)
+    assert (np.abs(mu - mur).max(1) / mscale).max() < 1e-6
+
+
+def test_psd_projection_matches_oracle(emu):
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((50, 4, 4))
+    M = np.ascontiguousarray(A + np.swapaxes(A, 1, 2))
+    out = M.copy()
+    emu.emu_psd_project(50, ptr(out))
+    np.testing.assert_allclose(out, qpm.psd_project(M), atol=1e-12)
+
+
+class HostGrid:
+    """acopf_grid / acopf_iterate structs over host numpy arrays."""
+
+    def __init__(self, g):
+        self.keep = []
+        vals = []
+        for n in _abi.GRID_BUS_FIELDS:
+            vals.append(self.arr(getattr(g, n)))
+        vals += [self.arr(g.f, np.int32), self.arr(g.t, np.int32)]
+        for n in _abi.GRID_LINE_FIELDS:
+            vals.append(self.arr(getattr(g, n)))
+        vals.append(self.arr(g.gbus, np.int32))
+        for n in _abi.GRID_GEN_FIELDS:
+            vals.append(self.arr(getattr(g, n)))
+        self.c = _abi.Grid(g.n_bus, g.n_line, g.n_gen, g.ref, *vals)
+
+    def arr(self, a, dt=np.float64):
+        a = np.ascontiguousarray(a, dtype=dt)
+        self.keep.append(a)
+        return a.ctypes.data
+
+    def iterate(self, x, pi):
+        arrays = [np.ascontiguousarray(v, dtype=np.float64) for v in (x.pg, x.qg, x.w, x.th, x.wR, x.wI)]
+        arrays.append(np.ascontiguousarray(pi.T.reshape(-1)))
+        self.keep += arrays
+        return _abi.Iterate(*[a.ctypes.data for a in arrays]), arrays
+
+
+def _setup(g, delta, pi_scale, seed):
+    s = power_flow_start(g)
+    x = acopf.Iterate(s["pg"], s["qg"], s["w"], s["th"], s["wR"], s["wI"])
+    rng = np.random.default_rng(seed)
+    pi = rng.standard_normal((g.n_line, 4)) * pi_scale
+    pi[:, 2:] = -np.abs(pi[:, 2:])
+    return x, pi
+
+
+@pytest.mark.parametrize("case", ["ring14", "tiny_shunt"])
+def test_sweeps_and_step_match_oracle(emu, case):
+    g = grid_14() if case == "ring14" else tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04)
+    delta = 0.05
+    x, pi = _setup(g, delta, 50.0, 3)
+    Q = qpm.build_qp(g, x, pi, delta, "psd")
+    rng = np.random.default_rng(4)
+    rho = admm.Rho(rng.uniform(5e3, 3e4, (g.n_gen, 2)), rng.uniform(5e3, 3e4, (g.n_line, 8)))
+    lam0_g = rng.standard_normal((g.n_gen, 2)) * 100
+    lam0_l = rng.standard_normal((g.n_line, 8)) * 100
+    nsw = 40
+    ref = admm.solve(g, Q, rho, nsw, 0.0, 0.0, state=admm.warm_state(g, lam0_g, lam0_l), record=True)
+
+    hg = HostGrid(g)
+    cx, _ = hg.iterate(x, pi)
+    ws = np.zeros(emu.emu_workspace_bytes(g.n_bus, g.n_line, g.n_gen) // 8 + 64)
+    rho_g = np.ascontiguousarray(rho.g.T.reshape(-1)); rho_l = np.ascontiguousarray(rho.l.T.reshape(-1))
+    lg = np.ascontiguousarray(lam0_g.T.reshape(-1)); ll = np.ascontiguousarray(lam0_l.T.reshape(-1))
+    d_arrays = [np.zeros(n) for n in (g.n_gen, g.n_gen, g.n_bus, g.n_bus, g.n_line, g.n_line, 4 * g.n_line)]
+    cd = _abi.Iterate(*[a.ctypes.data for a in d_arrays])
+    rs = np.zeros(2 * nsw)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    rc = emu.emu_run(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.c_double(delta), 0, ptr(rho_g), ptr(rho_l),
+                     ptr(lg), ptr(ll), nsw, ctypes.c_void_p(base), ctypes.byref(cd), ptr(rs))
+    assert rc == 0
+    # read the state back out of the host workspace through the same layout
+    lay = _layout(emu, g, base)
+    st = ref.state
+
+    def close(a, b, tol=1e-8):
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= tol * scale, (np.abs(a - b).max(), scale)
+
+    close(lay("xl", 8 * g.n_line).reshape(8, -1).T, st.xl)
+    close(lay("lam_l", 8 * g.n_line).reshape(8, -1).T, st.lam_l)
+    close(lay("xbar_f", 4 * g.n_line).reshape(4, -1).T, st.xbar_f)
+    close(lay("xg", 2 * g.n_gen).reshape(2, -1).T, st.xg)
+    close(lay("lam_g", 2 * g.n_gen).reshape(2, -1).T, st.lam_g)
+    close(lay("dw", g.n_bus), st.dw)
+    close(lay("dth", g.n_bus), st.dth)
+    close(lay("nu", 2 * g.n_bus).reshape(2, -1).T, st.nu)
+    hist = np.array(ref.history)
+    np.testing.assert_allclose(np.sqrt(rs.reshape(-1, 2)), hist, rtol=1e-7, atol=1e-12)
+    # step and multipliers
+    dref = sqp.assemble_step(g, Q, st)
+    pref = sqp.recover_pi(g, x, Q, st)
+    close(d_arrays[4], dref.wR)
+    close(d_arrays[5], dref.wI)
+    close(d_arrays[0], dref.pg)
+    close(d_arrays[6].reshape(4, -1).T, pref, tol=1e-7)
+
+
+def _layout(emu, g, base):
+    """Reader of the ADMM state arrays inside the host workspace."""
+    ptrs = (ctypes.POINTER(ctypes.c_double) * 8)()
+    emu.emu_state_ptrs(ctypes.c_void_p(base), g.n_bus, g.n_line, g.n_gen, ptrs)
+    names = ("xl", "lam_l", "xbar_f", "xg", "lam_g", "dw", "dth", "nu")
+    where = dict(zip(names, ptrs))
+
+    def get(name, n):
+        return np.ctypeslib.as_array(where[name], (n,)).copy()
+    return get
