@@ -79,7 +79,7 @@ typedef struct {
   double eps_pri;       /* stop when ||r||_2 <= eps_pri ...                       */
   double eps_dual;      /* ... and ||s||_2 <= eps_dual (Section IV-B5); 0 = never */
   int32_t sweep_mode;   /* acopf_sweep_mode                                       */
-  int32_t block_size;   /* threads per block, multiple of 64, <= 1024; 0 = 256    */
+  int32_t block_size;   /* threads per block, multiple of 64, <= 256; 0 = 256     */
   int32_t max_blocks;   /* persistent grid size cap; 0 = as many as fit resident  */
 } acopf_admm_params;
 

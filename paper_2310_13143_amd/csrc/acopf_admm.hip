@@ -76,6 +76,10 @@ __global__ void k_fill(double* p, long long n, double v) {
   for (long long i = gtid(); i < n; i += gstride()) p[i] = v;
 }
 
+__global__ void k_fill_int(int32_t* p, long long n, int32_t v) {
+  for (long long i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
 __global__ void k_copy(double* dst, const double* src, long long n) {
   for (long long i = gtid(); i < n; i += gstride()) dst[i] = src[i];
 }
@@ -86,8 +90,10 @@ __global__ void k_prep_lines(Workspace w) {
 }
 
 __global__ void k_reset_sync(Workspace w, int blocks) {
+  for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
   if (gtid() == 0) {
     SyncState* s = w.sync;
+    s->go = 0u;
     s->converged = 0;
     s->blocks = blocks;
     s->count = 0;
@@ -150,13 +156,13 @@ __device__ void finish_sweep(const Workspace& w, int nparts, int max_sweeps, dou
   }
 }
 
-__global__ void k_line_phase(acopf_grid g, Workspace w) {
+__global__ void __launch_bounds__(256) k_line_phase(acopf_grid g, Workspace w) {
   if (__hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int k = w.sync->sweeps;
   phase_lines(g, w, &w.sync->infeasible[k & 1]);
 }
 
-__global__ void k_bus_phase(acopf_grid g, Workspace w) {
+__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w) {
   __shared__ double lds[16];
   if (__hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   phase_buses(g, w, lds);
@@ -168,38 +174,41 @@ __global__ void k_finish_phase(Workspace w, int nparts, int max_sweeps, double e
   finish_sweep(w, nparts, max_sweeps, eps_pri, eps_dual, lds);
 }
 
-// Grid barrier for a cooperative launch (all blocks resident).  The last
-// block to arrive runs `last` (with the other blocks' writes visible) before
-// releasing the others.  Waits are bounded: on timeout the barrier error
-// flag is raised and the block continues, so every block reaches the end of
-// the kernel.
+// Grid barrier for a cooperative launch (all blocks resident).  Each block
+// publishes its arrival by storing the barrier's epoch to its own flag (no
+// contended read-modify-write); block 0 waits for every flag, runs `last`
+// with the other blocks' writes visible, and releases the grid by storing
+// the epoch to `go`.  Only one wave per block executes the device-scope
+// fences; the workgroup barrier orders the block's other waves around them.
+// Waits are bounded: on timeout the barrier error flag is raised and the
+// block continues, so every block reaches the end of the kernel.
 template <typename F>
-__device__ void grid_barrier(SyncState* sy, F&& last) {
-  __shared__ unsigned int s_gen;
-  __shared__ int s_last;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+__device__ void grid_barrier(const Workspace& w, unsigned int epoch, F&& last) {
+  SyncState* sy = w.sync;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int g0 = __hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int old =
-        __hip_atomic_fetch_add(&sy->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_gen = g0;
-    s_last = (old == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    last();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+  if (blockIdx.x != 0) {
     if (threadIdx.x == 0) {
-      __hip_atomic_store(&sy->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&sy->gen, s_gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&w.arrive[blockIdx.x * kArriveStride], epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      long long spins = 0;
+      while (__hip_atomic_load(&sy->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(&sy->barrier_error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-  } else if (threadIdx.x == 0) {
+    __syncthreads();
+    return;
+  }
+  // block 0: wait for every other block
+  for (unsigned int b = 1 + threadIdx.x; b < gridDim.x; b += blockDim.x) {
     long long spins = 0;
-    while (__hip_atomic_load(&sy->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == s_gen) {
-      __builtin_amdgcn_s_sleep(2);
+    while (__hip_atomic_load(&w.arrive[b * kArriveStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         __hip_atomic_store(&sy->barrier_error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -207,21 +216,34 @@ __device__ void grid_barrier(SyncState* sy, F&& last) {
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  last();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&sy->go, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
 }
 
-__global__ void __launch_bounds__(1024) k_sweep_persistent(acopf_grid g, Workspace w, int max_sweeps,
-                                                           double eps_pri, double eps_dual) {
+__global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspace w, int max_sweeps,
+                                                          double eps_pri, double eps_dual) {
   __shared__ double lds[16];
+  __shared__ int s_stop;
   SyncState* sy = w.sync;
   for (int k = 0; k < max_sweeps; ++k) {
     phase_lines(g, w, &sy->infeasible[k & 1]);
-    grid_barrier(sy, [] {});
+    grid_barrier(w, 2u * k + 1u, [] {});
     phase_buses(g, w, lds);
-    grid_barrier(sy, [&] { finish_sweep(w, gridDim.x, max_sweeps, eps_pri, eps_dual, lds); });
-    const int done = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int berr = __hip_atomic_load(&sy->barrier_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done || berr) break;
+    grid_barrier(w, 2u * k + 2u, [&] { finish_sweep(w, gridDim.x, max_sweeps, eps_pri, eps_dual, lds); });
+    if (threadIdx.x == 0) {
+      const int done = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int berr = __hip_atomic_load(&sy->barrier_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_stop = (done || berr) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_stop) break;
   }
 }
 
@@ -389,8 +411,10 @@ acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const dou
   fill(w.dth, g->n_bus, 0.0);
   fill(w.nu, 2LL * g->n_bus, 0.0);
   fill(w.mu, 2LL * g->n_line, 0.0);
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, w.line_mask,
+                     (long long)g->n_line, 0);
   hipLaunchKernelGGL(k_prep_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, w);
-  hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, w, 0);
+  hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, 0);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -401,7 +425,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   if (p->max_sweeps < 0 || !(p->eps_pri >= 0.0) || !(p->eps_dual >= 0.0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: bad parameters");
   const int bs = p->block_size > 0 ? p->block_size : kDefaultBlock;
-  if (bs % 64 != 0 || bs > 1024) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: block_size must be a multiple of 64, <= 1024");
+  if (bs % 64 != 0 || bs > 256) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: block_size must be a multiple of 64, <= 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
   // errors recorded by the QP build and the factorisation
@@ -411,7 +435,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   if (st.numeric_error) return fail(ACOPF_ERR_NUMERIC, "acopf_admm_solve: the QP build met a vanishing elimination pivot or non-finite data");
   if (st.nonconvex) return fail(ACOPF_ERR_NONCONVEX_LINE, "acopf_admm_solve: a line subproblem matrix is not positive definite");
   if (p->max_sweeps == 0) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, w, 0);
+    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, 0);
     HIP_TRY(hipGetLastError());
     if (result) return acopf_admm_result_get(g, workspace, stream, result);
     return ACOPF_OK;
@@ -419,7 +443,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES) {
     const int nbl = blocks_for(g->n_line, bs), nbb = blocks_for(g->n_bus, bs);
     if (nbb > w.max_partials) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: too many bus blocks");
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, w, nbb);
+    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, nbb);
     for (int k = 0; k < p->max_sweeps; ++k) {
       hipLaunchKernelGGL(k_line_phase, dim3(nbl), dim3(bs), 0, s, *g, w);
       hipLaunchKernelGGL(k_bus_phase, dim3(nbb), dim3(bs), 0, s, *g, w);
@@ -441,7 +465,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     if (p->max_blocks > 0) nblk = std::min<long long>(nblk, p->max_blocks);
     nblk = std::min<long long>(nblk, w.max_partials);
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, w, (int)nblk);
+    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, (int)nblk);
     acopf_grid gg = *g;
     int ms = p->max_sweeps;
     double ep = p->eps_pri, ed = p->eps_dual;

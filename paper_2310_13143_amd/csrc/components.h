@@ -317,7 +317,8 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   }
   h[0] = d[(LF_H + 0) * L + l];
   h[1] = d[(LF_H + 1) * L + l];
-  const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h);
+  const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h, w.line_mask[l]);
+  w.line_mask[l] = res.mask;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const double fl = F[r][0] * res.z[0] + F[r][1] * res.z[1] + F[r][2] * res.z[2] +
@@ -348,6 +349,11 @@ ACOPF_HD void update_gen(const Workspace& w, int k) {
 // ends at bus i, and that bus's contribution to ||r||^2 and ||s||^2.
 // Generators of the bus are updated first (they only read values of the
 // previous bus update), which keeps the two-block order of Algorithm 2.
+//
+// With Q_c = rho_c and c_c = rho_c x_c + lam_c the closed form gives, for a
+// generator or flow copy with balance coefficient a_c = +-1,
+//   xbar_c = x_c + (lam_c - a_c nu) / rho_c,   lam_c + rho_c (x_c - xbar_c) = a_c nu,
+// so the multiplier update of these couplings is written as a_c nu.
 ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2) {
   const int G = w.n_gen, L = w.n_line;
   const int g0 = w.bus_gen_ptr[i], g1 = w.bus_gen_ptr[i + 1];
@@ -356,37 +362,38 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
   for (int e = g0; e < g1; ++e) {
     const int k = w.bus_gen[e];
     update_gen(w, k);
-    const double rhp = w.rho_g[k], rhq = w.rho_g[G + k];
-    spp += 1.0 / rhp;
-    sqq += 1.0 / rhq;
-    rp += (rhp * w.xg[k] + w.lam_g[k]) / rhp;
-    rq += (rhq * w.xg[G + k] + w.lam_g[G + k]) / rhq;
+    const double ip = 1.0 / w.rho_g[k], iq = 1.0 / w.rho_g[G + k];
+    spp += ip;
+    sqq += iq;
+    rp += w.xg[k] + w.lam_g[k] * ip;
+    rq += w.xg[G + k] + w.lam_g[G + k] * iq;
   }
   for (int e = e0; e < e1; ++e) {
     const int code = w.bus_end[e];
     const int l = code >> 1, side = code & 1;
     const int kp = 2 * side, kq = kp + 1, kw = 4 + 2 * side, kt = kw + 1;
-    const double rhp = w.rho_l[kp * L + l], rhq = w.rho_l[kq * L + l];
+    const double ip = 1.0 / w.rho_l[kp * L + l], iq = 1.0 / w.rho_l[kq * L + l];
     const double rhw = w.rho_l[kw * L + l], rht = w.rho_l[kt * L + l];
-    spp += 1.0 / rhp;
-    sqq += 1.0 / rhq;
-    rp -= (rhp * w.xl[kp * L + l] + w.lam_l[kp * L + l]) / rhp;
-    rq -= (rhq * w.xl[kq * L + l] + w.lam_l[kq * L + l]) / rhq;
+    spp += ip;
+    sqq += iq;
+    rp -= w.xl[kp * L + l] + w.lam_l[kp * L + l] * ip;
+    rq -= w.xl[kq * L + l] + w.lam_l[kq * L + l] * iq;
     qw += rhw;
     cw += rhw * w.xl[kw * L + l] + w.lam_l[kw * L + l];
     qt += rht;
     ct += rht * w.xl[kt * L + l] + w.lam_l[kt * L + l];
   }
   const double gsh = g.gsh[i], bsh = g.bsh[i];
-  spp += gsh * gsh / qw;
-  sqq += bsh * bsh / qw;
-  const double spq = -gsh * bsh / qw;
-  rp += -gsh * cw / qw - w.bus_pdk[i];
-  rq += bsh * cw / qw - w.bus_qdk[i];
-  const double det = spp * sqq - spq * spq;
-  const double nup = (sqq * rp - spq * rq) / det;
-  const double nuq = (spp * rq - spq * rp) / det;
-  const double dw_new = (cw + gsh * nup - bsh * nuq) / qw;
+  const double iqw = 1.0 / qw;
+  spp += gsh * gsh * iqw;
+  sqq += bsh * bsh * iqw;
+  const double spq = -gsh * bsh * iqw;
+  rp += -gsh * cw * iqw - w.bus_pdk[i];
+  rq += bsh * cw * iqw - w.bus_qdk[i];
+  const double idet = 1.0 / (spp * sqq - spq * spq);
+  const double nup = (sqq * rp - spq * rq) * idet;
+  const double nuq = (spp * rq - spq * rp) * idet;
+  const double dw_new = (cw + gsh * nup - bsh * nuq) * iqw;
   const double dth_new = (i == g.ref_bus) ? 0.0 : ct / qt;
   const double dw_old = w.dw[i], dth_old = w.dth[i];
   double rr = 0.0, ss = 0.0;
@@ -396,9 +403,10 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
     for (int j = 0; j < 2; ++j) {
       const int idx = j * G + k;
       const double rho = w.rho_g[idx], xv = w.xg[idx], lam = w.lam_g[idx];
-      const double xb = (rho * xv + lam - (j == 0 ? nup : nuq)) / rho;
+      const double lam_new = (j == 0) ? nup : nuq;
+      const double xb = xv + (lam - lam_new) / rho;
       const double ds = rho * (xb - w.xbar_g[idx]);
-      w.lam_g[idx] = lam + rho * (xv - xb);
+      w.lam_g[idx] = lam_new;
       w.xbar_g[idx] = xb;
       rr += (xv - xb) * (xv - xb);
       ss += ds * ds;
@@ -408,15 +416,14 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
     const int code = w.bus_end[e];
     const int l = code >> 1, side = code & 1;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {  // flow copies p, q
-      const int kk = 2 * side + j;
-      const int idx = kk * L + l;
+    for (int j = 0; j < 2; ++j) {  // flow copies p, q (balance coefficient -1)
+      const int idx = (2 * side + j) * L + l;
       const double rho = w.rho_l[idx], xv = w.xl[idx], lam = w.lam_l[idx];
-      const double xb = (rho * xv + lam + (j == 0 ? nup : nuq)) / rho;
-      const int fi = kk * L + l;
-      const double ds = rho * (xb - w.xbar_f[fi]);
-      w.lam_l[idx] = lam + rho * (xv - xb);
-      w.xbar_f[fi] = xb;
+      const double lam_new = -((j == 0) ? nup : nuq);
+      const double xb = xv + (lam - lam_new) / rho;
+      const double ds = rho * (xb - w.xbar_f[idx]);
+      w.lam_l[idx] = lam_new;
+      w.xbar_f[idx] = xb;
       rr += (xv - xb) * (xv - xb);
       ss += ds * ds;
     }

@@ -4,15 +4,23 @@
 //
 // with Q symmetric positive definite, given its inverse P = Q^{-1}.  The
 // paper solves this problem with an augmented Lagrangian and TRON; its limit
-// is the unique minimiser, which this routine computes in finitely many steps
-// with the dual active-set method of Goldfarb and Idnani (Math. Programming
-// 27, 1983): start at the unconstrained minimiser, add the most violated
-// constraint, take the primal/dual step that keeps the active multipliers
-// non-negative (dropping a constraint whose multiplier reaches zero), until
-// no constraint is violated.  The working set never holds more than four
-// linearly independent constraints.  Everything is unrolled over the 10
-// constraints (4 lower bounds, 4 upper bounds, 2 rows) so it stays in
-// registers.
+// is the unique minimiser, which this routine computes exactly:
+//
+//  1. warm start: the working set that was optimal in the previous ADMM
+//     sweep is tried first; its equality-constrained minimiser is accepted
+//     when it satisfies every constraint and its multipliers are
+//     non-negative (the KKT conditions, which certify the minimiser of a
+//     strictly convex QP).  Between sweeps the working set rarely changes.
+//  2. otherwise the dual active-set method of Goldfarb and Idnani (Math.
+//     Programming 27, 1983) runs from the unconstrained minimiser: add the
+//     most violated constraint, take the primal/dual step that keeps the
+//     active multipliers non-negative (dropping a constraint whose
+//     multiplier reaches zero), until no constraint is violated.
+//
+// Constraints are numbered 0-3 (lower bounds of z_0..z_3), 4-7 (upper
+// bounds) and 8-9 (the two rows), written as n_k . z >= b_k.  The working
+// set never holds more than four linearly independent constraints.  All
+// loops have fixed trip counts so the arrays stay in registers.
 #pragma once
 
 #include "small_linalg.h"
@@ -23,33 +31,8 @@ struct LineQPResult {
   double z[4];
   double mu[2];   // multipliers (>= 0) of the rows G z <= h
   int status;     // 0 solved, 1 infeasible, 2 iteration cap
+  int mask;       // bit k set: constraint k in the optimal working set
 };
-
-// Constraint k in "n_k . z >= b_k" form: k < 4 lower bound of z_k, 4 <= k < 8
-// upper bound of z_{k-4}, k = 8, 9 row k-8 of G z <= h.
-ACOPF_HD void gi_normal(int k, const double G[2][4], double n[4]) {
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    double v = 0.0;
-    v = (k == d) ? 1.0 : v;
-    v = (k == d + 4) ? -1.0 : v;
-    v = (k == 8) ? -G[0][d] : v;
-    v = (k == 9) ? -G[1][d] : v;
-    n[d] = v;
-  }
-}
-
-ACOPF_HD double gi_rhs(int k, const double lo[4], const double hi[4], const double h[2]) {
-  double b = 0.0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    b = (k == d) ? lo[d] : b;
-    b = (k == d + 4) ? -hi[d] : b;
-  }
-  b = (k == 8) ? -h[0] : b;
-  b = (k == 9) ? -h[1] : b;
-  return b;
-}
 
 ACOPF_HD double dot4(const double a[4], const double b[4]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
@@ -60,14 +43,70 @@ ACOPF_HD void matvec4(const double P[4][4], const double v[4], double out[4]) {
   for (int i = 0; i < 4; ++i) out[i] = P[i][0] * v[0] + P[i][1] * v[1] + P[i][2] * v[2] + P[i][3] * v[3];
 }
 
-// Direction of adding constraint with normal np to the working set with
-// normals N[0..q-1]: dual direction r = (N^T P N)^{-1} N^T P np and primal
-// direction dz = P np - P N r.
-ACOPF_HD void gi_directions(const double P[4][4], const double N[4][4], int q, const double np[4],
-                            double r[4], double dz[4]) {
-  double v[4];
-  matvec4(P, np, v);
-  double W[4][4];  // W[:, j] = P N[j]
+// Normal and right-hand side of constraint k (n_k . z >= b_k).
+ACOPF_HD void gi_constraint(int k, const double G[2][4], const double lo[4], const double hi[4],
+                            const double h[2], double n[4], double& b) {
+  const bool row = k >= 8;
+  const int r = k - 8;
+  const int v = k & 3;
+  const double sgn = (k < 4) ? 1.0 : -1.0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) n[d] = row ? -(r == 0 ? G[0][d] : G[1][d]) : ((d == v) ? sgn : 0.0);
+  b = row ? -(r == 0 ? h[0] : h[1]) : ((k < 4) ? lo[v] : -hi[v]);
+}
+
+// Solve S y = rhs for the q x q leading block of S (SPD), padded to 4x4.
+ACOPF_HD void spd_solve_padded(const double S[4][4], int q, const double rhs[4], double y[4]) {
+  double A[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) A[a][b] = (a < q && b < q) ? S[a][b] : ((a == b) ? 1.0 : 0.0);
+  double L[4][4], inv_d[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double d = A[j][j];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < j) d -= L[j][k] * L[j][k];
+    const double ljj = sqrt(fmax(d, 1e-300));
+    inv_d[j] = 1.0 / ljj;
+    L[j][j] = ljj;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i > j) {
+        double s = A[i][j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < j) s -= L[i][k] * L[j][k];
+        L[i][j] = s * inv_d[j];
+      }
+    }
+  }
+  double t[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double s = (i < q) ? rhs[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < i) s -= L[i][k] * t[k];
+    t[i] = s * inv_d[i];
+  }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const int i = 3 - ii;
+    double s = t[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k > i) s -= L[k][i] * y[k];
+    y[i] = s * inv_d[i];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) y[a] = (a < q) ? y[a] : 0.0;
+}
+
+// Working-set products: W[:, j] = P N_j and S = N^T P N (padded).
+ACOPF_HD void gi_products(const double P[4][4], const double N[4][4], int q, double W[4][4], double S[4][4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     double t[4];
@@ -75,116 +114,170 @@ ACOPF_HD void gi_directions(const double P[4][4], const double N[4][4], int q, c
 #pragma unroll
     for (int i = 0; i < 4; ++i) W[i][j] = (j < q) ? t[i] : 0.0;
   }
-  // S = N^T P N (q x q, padded with identity), rhs = N^T v
-  double S[4][4], rhs[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double s = N[a][0] * W[0][b] + N[a][1] * W[1][b] + N[a][2] * W[2][b] + N[a][3] * W[3][b];
-      S[a][b] = (a < q && b < q) ? s : ((a == b) ? 1.0 : 0.0);
-    }
-    rhs[a] = (a < q) ? dot4(N[a], v) : 0.0;
-  }
-  double L[4][4];
-  chol4(S, L);
-  // solve L L^T r = rhs
-  double y[4];
+    for (int b = 0; b < 4; ++b)
+      S[a][b] = N[a][0] * W[0][b] + N[a][1] * W[1][b] + N[a][2] * W[2][b] + N[a][3] * W[3][b];
+}
+
+// Most violated constraint outside the working set at z (scaled by the
+// constraint's 1-norm); -1 if none is violated beyond the tolerance.
+ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], const double hi[4],
+                              const double G[2][4], const double h[2], const double gn[2]) {
+  const double zs = fabs(z[0]) + fabs(z[1]) + fabs(z[2]) + fabs(z[3]);
+  int p = -1;
+  double worst = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double s = rhs[i];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (k < i) s -= L[i][k] * y[k];
-    y[i] = s / L[i][i];
-  }
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    int i = 3 - ii;
-    double s = y[i];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (k > i) s -= L[k][i] * r[k];
-    r[i] = s / L[i][i];
+  for (int k = 0; k < 4; ++k) {
+    const double sl = z[k] - lo[k];
+    const bool vl = !((mask >> k) & 1) && sl < -1e-12 * (1.0 + fabs(lo[k]) + zs) && sl < worst;
+    worst = vl ? sl : worst;
+    p = vl ? k : p;
+    const double su = hi[k] - z[k];
+    const bool vu = !((mask >> (k + 4)) & 1) && su < -1e-12 * (1.0 + fabs(hi[k]) + zs) && su < worst;
+    worst = vu ? su : worst;
+    p = vu ? k + 4 : p;
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) r[a] = (a < q) ? r[a] : 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    dz[i] = v[i] - (W[i][0] * r[0] + W[i][1] * r[1] + W[i][2] * r[2] + W[i][3] * r[3]);
+  for (int r = 0; r < 2; ++r) {
+    const double gz = G[r][0] * z[0] + G[r][1] * z[1] + G[r][2] * z[2] + G[r][3] * z[3];
+    const double s = h[r] - gz;
+    const double sc = s / fmax(gn[r], 1e-300);
+    const bool v = gn[r] > 0.0 && !((mask >> (8 + r)) & 1) && s < -1e-12 * (1.0 + fabs(h[r]) + gn[r] * zs) &&
+                   sc < worst;
+    worst = v ? sc : worst;
+    p = v ? 8 + r : p;
+  }
+  return p;
 }
 
 ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], const double lo[4],
-                                    const double hi[4], const double G[2][4], const double h[2]) {
+                                    const double hi[4], const double G[2][4], const double h[2],
+                                    int warm_mask) {
   const double INF = 1e300;
   const int MAX_STEPS = 48;
   double P[4][4];
   sym_unpack(Pp, P);
-  LineQPResult res;
-  double z[4];
-  matvec4(P, c, z);
+  const double gn[2] = {fabs(G[0][0]) + fabs(G[0][1]) + fabs(G[0][2]) + fabs(G[0][3]),
+                        fabs(G[1][0]) + fabs(G[1][1]) + fabs(G[1][2]) + fabs(G[1][3])};
+  double zu[4];
+  matvec4(P, c, zu);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) z[i] = -z[i];
+  for (int i = 0; i < 4; ++i) zu[i] = -zu[i];
+  const double cs = 1.0 + fabs(c[0]) + fabs(c[1]) + fabs(c[2]) + fabs(c[3]);
 
+  LineQPResult res;
+  double z[4] = {zu[0], zu[1], zu[2], zu[3]};
   int act[4] = {-1, -1, -1, -1};
-  double N[4][4];
-  double u[4] = {0.0, 0.0, 0.0, 0.0};
+  double N[4][4], u[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int d = 0; d < 4; ++d) N[j][d] = 0.0;
-  int q = 0;
-  int status = 0;
-  int steps = 0;
-  // feasibility tolerance, relative to the size of each constraint
-  double zs = fabs(z[0]) + fabs(z[1]) + fabs(z[2]) + fabs(z[3]);
+  int q = 0, mask = 0, status = 0;
+  bool done = false;
 
-  while (true) {
-    // most violated constraint outside the working set (scaled violation)
-    int p = -1;
-    double worst = 0.0;
+  // 1. warm start from the previous working set
+  if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
+    double b[4] = {0.0, 0.0, 0.0, 0.0};
+    int qq = 0;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
-      bool inw = (act[0] == k) || (act[1] == k) || (act[2] == k) || (act[3] == k);
-      double n[4];
-      gi_normal(k, G, n);
-      double b = gi_rhs(k, lo, hi, h);
-      double nn = fabs(n[0]) + fabs(n[1]) + fabs(n[2]) + fabs(n[3]);
-      double s = dot4(n, z) - b;
-      double tol = 1e-12 * (1.0 + fabs(b) + nn * zs);
-      double sc = s / fmax(nn, 1e-300);
-      bool viol = !inw && nn > 0.0 && s < -tol && sc < worst;
-      worst = viol ? sc : worst;
-      p = viol ? k : p;
+      if ((warm_mask >> k) & 1) {
+        double n[4], bk;
+        gi_constraint(k, G, lo, hi, h, n, bk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool here = (j == qq);
+          act[j] = here ? k : act[j];
+          b[j] = here ? bk : b[j];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) N[j][d] = here ? n[d] : N[j][d];
+        }
+        qq += 1;
+      }
     }
+    q = qq;
+    double W[4][4], S[4][4], rhs[4], y[4];
+    gi_products(P, N, q, W, S);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rhs[j] = b[j] - dot4(N[j], zu);
+    spd_solve_padded(S, q, rhs, y);
+    double zw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zw[i] = zu[i] + W[i][0] * y[0] + W[i][1] * y[1] + W[i][2] * y[2] + W[i][3] * y[3];
+    // KKT check: multipliers non-negative (free sign for a bound of a fixed
+    // variable), every other constraint satisfied, working set reproduced
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = act[j];
+      const bool fixed_var = (k >= 0 && k < 8) && (lo[k & 3] >= hi[k & 3]);
+      ok = ok && (j >= q || fixed_var || y[j] >= -1e-10 * cs);
+      double n[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) n[d] = N[j][d];
+      ok = ok && (j >= q || fabs(dot4(n, zw) - b[j]) <= 1e-9 * (1.0 + fabs(b[j])));
+    }
+    ok = ok && gi_most_violated(zw, warm_mask, lo, hi, G, h, gn) < 0;
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[i] = zw[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = (j < q) ? y[j] : 0.0;
+      mask = warm_mask;
+      done = true;
+    } else {
+      // restart from the unconstrained minimiser with an empty working set
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        act[j] = -1;
+        u[j] = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) N[j][d] = 0.0;
+      }
+      q = 0;
+    }
+  }
+
+  // 2. dual active-set method
+  int steps = 0;
+  while (!done) {
+    const int p = gi_most_violated(z, mask, lo, hi, G, h, gn);
     if (p < 0) break;
-    double np_[4];
-    gi_normal(p, G, np_);
-    double bp = gi_rhs(p, lo, hi, h);
+    double np_[4], bp;
+    gi_constraint(p, G, lo, hi, h, np_, bp);
+    double v[4];
+    matvec4(P, np_, v);
+    const double npn = dot4(np_, v);
     double up = 0.0;
     bool added = false;
     while (!added) {
       if (++steps > MAX_STEPS) { status = 2; break; }
-      double r[4], dz[4];
-      gi_directions(P, N, q, np_, r, dz);
+      double W[4][4], S[4][4], rhs[4], r[4];
+      gi_products(P, N, q, W, S);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rhs[j] = (j < q) ? dot4(N[j], v) : 0.0;
+      spd_solve_padded(S, q, rhs, r);
+      double dz[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dz[i] = v[i] - (W[i][0] * r[0] + W[i][1] * r[1] + W[i][2] * r[2] + W[i][3] * r[3]);
       // dual step length: first active multiplier that would become negative
       double t1 = INF;
       int kdrop = -1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        bool cand = (j < q) && (r[j] > 0.0);
-        double ratio = cand ? u[j] / r[j] : INF;
-        bool better = cand && ratio < t1;
+        const bool cand = (j < q) && (r[j] > 0.0);
+        const double ratio = cand ? u[j] / r[j] : INF;
+        const bool better = cand && ratio < t1;
         t1 = better ? ratio : t1;
         kdrop = better ? j : kdrop;
       }
-      // primal step length: reach the constraint
-      double v[4];
-      matvec4(P, np_, v);
-      double npn = dot4(np_, v);
-      double nz = dot4(np_, dz);
-      double t2 = (nz > 1e-14 * npn) ? -(dot4(np_, z) - bp) / nz : INF;
-      double t = fmin(t1, t2);
+      // primal step length: reach constraint p
+      const double nz = dot4(np_, dz);
+      const double t2 = (nz > 1e-14 * npn) ? -(dot4(np_, z) - bp) / nz : INF;
+      const double t = fmin(t1, t2);
       if (t >= INF) { status = 1; break; }
 #pragma unroll
       for (int j = 0; j < 4; ++j) u[j] = (j < q) ? u[j] - t * r[j] : u[j];
@@ -194,22 +287,23 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
         for (int i = 0; i < 4; ++i) z[i] += t * dz[i];
       }
       if (t2 <= t1) {
-        // add p to the working set
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          bool here = (j == q);
+          const bool here = (j == q);
           act[j] = here ? p : act[j];
           u[j] = here ? up : u[j];
 #pragma unroll
           for (int d = 0; d < 4; ++d) N[j][d] = here ? np_[d] : N[j][d];
         }
         q += 1;
+        mask |= 1 << p;
         added = true;
       } else {
-        // drop constraint kdrop (shift the later ones down)
+        const int kd = act[kdrop];
+        mask &= ~(1 << kd);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          bool shift = (j >= kdrop);
+          const bool shift = (j >= kdrop);
           act[j] = shift ? act[j + 1] : act[j];
           u[j] = shift ? u[j + 1] : u[j];
 #pragma unroll
@@ -223,7 +317,6 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
       }
     }
     if (status != 0) break;
-    zs = fabs(z[0]) + fabs(z[1]) + fabs(z[2]) + fabs(z[3]);
   }
 
 #pragma unroll
@@ -236,6 +329,7 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
     res.mu[1] = (act[j] == 9) ? u[j] : res.mu[1];
   }
   res.status = status;
+  res.mask = (status == 0) ? mask : 0;
   return res;
 }
 

@@ -44,7 +44,8 @@ struct SyncState {
   int infeasible[2];       // infeasible line subproblems, by sweep parity
   int converged;           // the stop test held at the last sweep
   int blocks;              // grid size of the last solve
-  int pad[2];
+  unsigned int go;         // grid-barrier release epoch (persistent kernel)
+  int pad;
   double r_norm, s_norm;
 };
 
@@ -69,10 +70,15 @@ struct Workspace {
   double *xbar_f;                        // [4][n_line]
   double *dw, *dth, *nu;                 // [n_bus], [n_bus], [2][n_bus]
   double *mu;                            // [2][n_line]
+  int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
   // reductions
   double* partials;        // [2][max_partials]
+  unsigned int* arrive;    // [max_partials * kArriveStride] grid-barrier arrival epochs
   SyncState* sync;
 };
+
+// Arrival flags of different blocks sit on different 128-byte lines.
+constexpr int kArriveStride = 32;
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -114,7 +120,9 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, W
   t.dth = (double*)take((size_t)nb * D);
   t.nu = (double*)take((size_t)2 * nb * D);
   t.mu = (double*)take((size_t)2 * nl * D);
+  t.line_mask = (int32_t*)take((size_t)nl * I);
   t.partials = (double*)take((size_t)2 * maxp * D);
+  t.arrive = (unsigned int*)take((size_t)maxp * kArriveStride * sizeof(unsigned int));
   t.sync = (SyncState*)take(sizeof(SyncState));
   if (w) *w = t;
   return off;

@@ -17,7 +17,7 @@ void emu_line_qp(int n, const double* P, const double* c, const double* lo, cons
   for (int k = 0; k < n; ++k) {
     double Gk[2][4] = {{G[8 * k + 0], G[8 * k + 1], G[8 * k + 2], G[8 * k + 3]},
                        {G[8 * k + 4], G[8 * k + 5], G[8 * k + 6], G[8 * k + 7]}};
-    LineQPResult r = solve_line_qp(P + 10 * k, c + 4 * k, lo + 4 * k, hi + 4 * k, Gk, h + 2 * k);
+    LineQPResult r = solve_line_qp(P + 10 * k, c + 4 * k, lo + 4 * k, hi + 4 * k, Gk, h + 2 * k, 0);
     for (int i = 0; i < 4; ++i) z[4 * k + i] = r.z[i];
     mu[2 * k] = r.mu[0];
     mu[2 * k + 1] = r.mu[1];
@@ -81,6 +81,7 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   std::memset(w.dth, 0, sizeof(double) * nb);
   std::memset(w.nu, 0, sizeof(double) * 2 * nb);
   std::memset(w.mu, 0, sizeof(double) * 2 * nl);
+  std::memset(w.line_mask, 0, sizeof(int32_t) * nl);
   for (int l = 0; l < nl; ++l) bad += prep_line(w, l) ? 0 : 1000;
   int infeasible = 0;
   for (int k = 0; k < sweeps; ++k) {
