@@ -164,6 +164,55 @@ acopf_status acopf_admm_state_get(const acopf_grid* grid, void* workspace,
 acopf_status acopf_step(const acopf_grid* grid, const acopf_iterate* x, void* workspace,
                         const acopf_iterate* d, void* stream);
 
+/* One iteration of the basic trust-region SQP (Section II, Algorithm 1):
+ * build the QP at x with radius state->delta, solve it by ADMM (params
+ * admm; warm_start = 1 starts from the multipliers of the previous solve in
+ * this workspace, 0 from zero), form the step d (caller scratch in the
+ * iterate layout) and multiplier estimates, evaluate the l1 merit
+ * phi_1 = f + mu h and its model q (Section II-C), accept the step iff
+ * ared > 0 and pred > 0, and update the radius: doubled (up to delta_max)
+ * after an accepted step that reached it with ared >= grow_ratio * pred,
+ * unchanged after another accepted step, 0.5 min(delta, ||d||_inf) after a
+ * rejection.  On acceptance x <- x + d and x.pi <- the new estimates, on
+ * the device.  Synchronises the stream and fills *state (host). */
+typedef struct {
+  double mu;             /* l1 merit penalty (the paper uses 1e5)         */
+  double delta_max;      /* trust-radius cap                              */
+  double grow_ratio;     /* radius growth threshold on ared / pred        */
+  int32_t hessian_mode;  /* acopf_hessian_mode                            */
+  int32_t warm_start;    /* 1 = previous solve's multipliers, 0 = zero    */
+  acopf_admm_params admm;
+} acopf_sqp_params;
+
+typedef struct {
+  double delta;          /* in: radius of this iteration; out: the next  */
+  int32_t accepted;      /* the step was accepted                         */
+  int32_t admm_sweeps;   /* sweeps of this iteration's ADMM solve         */
+  double ared, pred;     /* actual and predicted merit reduction          */
+  double step_inf;       /* ||d||_inf over (pg, qg, w, th)                */
+  double objective;      /* f at the returned iterate                     */
+  double merit;          /* phi_1 at the returned iterate                 */
+  double admm_r, admm_s; /* final ADMM residual norms                     */
+  double admm_ms;        /* duration of the ADMM sweeps (HIP events on the stream) */
+} acopf_sqp_state;
+
+acopf_status acopf_sqp_step(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
+                            const double* rho_g, const double* rho_l, const acopf_sqp_params* params,
+                            void* workspace, void* stream, acopf_sqp_state* state);
+
+/* Infeasibility report of the ACOPF (eq. acopf) at x (synchronises; host
+ * result): infinity norms of the power-balance residuals, of (opfc11),
+ * (opfc12), of the line-limit violations and of the bound violations;
+ * primal = their maximum; dual = infinity norm of the Lagrangian gradient
+ * projected at active bounds, with the balance multipliers of the last bus
+ * update and the line multipliers x.pi, divided by max(1, |f'|_inf). */
+typedef struct {
+  double primal, balance, c11, c12, limit, bounds, dual;
+} acopf_residuals_report;
+
+acopf_status acopf_residuals(const acopf_grid* grid, const acopf_iterate* x, void* workspace, void* stream,
+                             acopf_residuals_report* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,9 +48,24 @@ class AdmmState(ctypes.Structure):
     _fields_ = [(n, c_void_p) for n in STATE_FIELDS]
 
 
+class SqpParams(ctypes.Structure):
+    _fields_ = [("mu", c_double), ("delta_max", c_double), ("grow_ratio", c_double),
+                ("hessian_mode", c_int32), ("warm_start", c_int32), ("admm", AdmmParams)]
+
+
+class SqpState(ctypes.Structure):
+    _fields_ = [("delta", c_double), ("accepted", c_int32), ("admm_sweeps", c_int32), ("ared", c_double),
+                ("pred", c_double), ("step_inf", c_double), ("objective", c_double), ("merit", c_double),
+                ("admm_r", c_double), ("admm_s", c_double), ("admm_ms", c_double)]
+
+
+class ResidualsReport(ctypes.Structure):
+    _fields_ = [(n, c_double) for n in ("primal", "balance", "c11", "c12", "limit", "bounds", "dual")]
+
+
 EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_qp_build",
            "acopf_admm_init", "acopf_admm_solve", "acopf_admm_result_get", "acopf_admm_state_get",
-           "acopf_step")
+           "acopf_step", "acopf_sqp_step", "acopf_residuals")
 
 
 class AcopfError(RuntimeError):
@@ -82,6 +97,9 @@ def load(path: str = LIB_PATH):
     lib.acopf_admm_result_get.argtypes = [P(Grid), c_void_p, c_void_p, P(AdmmResult)]
     lib.acopf_admm_state_get.argtypes = [P(Grid), c_void_p, P(AdmmState), c_void_p]
     lib.acopf_step.argtypes = [P(Grid), P(Iterate), c_void_p, P(Iterate), c_void_p]
+    lib.acopf_sqp_step.argtypes = [P(Grid), P(Iterate), P(Iterate), c_void_p, c_void_p, P(SqpParams), c_void_p,
+                                   c_void_p, P(SqpState)]
+    lib.acopf_residuals.argtypes = [P(Grid), P(Iterate), c_void_p, c_void_p, P(ResidualsReport)]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = c_int32
     _lib = lib

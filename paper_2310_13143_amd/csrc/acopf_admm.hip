@@ -263,7 +263,200 @@ __global__ void k_step_nodes(acopf_grid g, Workspace w, acopf_iterate d) {
   }
 }
 
+// ---------------------------------------------------------------- SQP step
+// Block-wise sums of the merit pieces and the maximum step component.
+__global__ void __launch_bounds__(256) k_merit(acopf_grid g, acopf_iterate x, Workspace w, acopf_iterate d) {
+  __shared__ double lds[16];
+  double acc[kMeritFields];
+#pragma unroll
+  for (int k = 0; k < kMeritFields; ++k) acc[k] = 0.0;
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    double o[4];
+    merit_line(g, x, w, d, l, o);
+    acc[3] += o[0];
+    acc[4] += o[1];
+    acc[5] += o[2];
+    acc[6] += o[3];
+  }
+  double smax = 0.0;
+  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    double o[3];
+    merit_gen(g, x, d, k, o);
+    acc[0] += o[0];
+    acc[1] += o[1];
+    acc[2] += o[2];
+    smax = fmax(smax, fmax(fabs(d.pg[k]), fabs(d.qg[k])));
+  }
+  for (int i = gtid(); i < g.n_bus; i += gstride()) smax = fmax(smax, fmax(fabs(d.w[i]), fabs(d.th[i])));
+#pragma unroll
+  for (int k = 0; k < kMeritFields - 1; ++k) acc[k] = block_sum(acc[k], lds);
+  // block maximum of the step (order independent)
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = smax;
+  __syncthreads();
+  double m = 0.0;
+  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kMeritFields - 1; ++k) w.merit_partials[k * w.max_partials + blockIdx.x] = acc[k];
+    w.merit_partials[(kMeritFields - 1) * w.max_partials + blockIdx.x] = m;
+  }
+}
+
+// Acceptance test and trust-radius update of Algorithm 1 (one block).
+__global__ void k_decide(Workspace w, int nparts, double mu, double delta, double delta_max, double grow) {
+  __shared__ double lds[16];
+  double acc[kMeritFields];
+#pragma unroll
+  for (int k = 0; k < kMeritFields; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kMeritFields - 1; ++k) acc[k] += w.merit_partials[k * w.max_partials + b];
+    acc[kMeritFields - 1] = fmax(acc[kMeritFields - 1], w.merit_partials[(kMeritFields - 1) * w.max_partials + b]);
+  }
+#pragma unroll
+  for (int k = 0; k < kMeritFields - 1; ++k) acc[k] = block_sum(acc[k], lds);
+  double smax = acc[kMeritFields - 1];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = smax;
+  __syncthreads();
+  double m = 0.0;
+  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
+  if (threadIdx.x == 0) {
+    SqpDecision* dc = w.decision;
+    dc->f_x = acc[0];
+    dc->f_xd = acc[1];
+    dc->h_x = acc[3];
+    dc->h_xd = acc[4];
+    dc->m_d = acc[5];
+    dc->quad = acc[2] + acc[6];
+    const double ared = (acc[0] + mu * acc[3]) - (acc[1] + mu * acc[4]);
+    const double pred = -(acc[2] + acc[6]) + mu * (acc[3] - acc[5]);
+    dc->ared = ared;
+    dc->pred = pred;
+    dc->step_inf = m;
+    dc->delta_in = delta;
+    const bool acc_ok = ared > 0.0 && pred > 0.0;
+    double dn = delta;
+    if (acc_ok) {
+      if (m >= 0.99 * delta && ared >= grow * pred) dn = fmin(2.0 * delta, delta_max);
+    } else {
+      dn = 0.5 * fmin(delta, m);
+    }
+    dc->delta_out = dn;
+    dc->accepted = acc_ok ? 1 : 0;
+  }
+}
+
+// x <- x + d and pi <- new estimates, if the step was accepted.
+__global__ void k_apply(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspace w) {
+  if (!w.decision->accepted) return;
+  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    x.pg[k] += d.pg[k];
+    x.qg[k] += d.qg[k];
+  }
+  for (int i = gtid(); i < g.n_bus; i += gstride()) {
+    x.w[i] += d.w[i];
+    x.th[i] += d.th[i];
+  }
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    x.wR[l] += d.wR[l];
+    x.wI[l] += d.wI[l];
+    x.pi[l] = d.pi[l];
+    x.pi[g.n_line + l] = d.pi[g.n_line + l];
+    x.pi[2 * g.n_line + l] = d.pi[2 * g.n_line + l];
+    x.pi[3 * g.n_line + l] = d.pi[3 * g.n_line + l];
+  }
+}
+
+// ---------------------------------------------------------------- residuals
+__device__ double block_max(double v, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
+  __syncthreads();
+  return m;
+}
+
+__global__ void __launch_bounds__(256) k_residuals(acopf_grid g, acopf_iterate x, Workspace w) {
+  __shared__ double lds[16];
+  double acc[kResidFields];
+#pragma unroll
+  for (int k = 0; k < kResidFields; ++k) acc[k] = 0.0;
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
+    residual_line(g, x, w, l, pr, du);
+    acc[1] = fmax(acc[1], pr[1]);
+    acc[2] = fmax(acc[2], pr[2]);
+    acc[3] = fmax(acc[3], pr[3]);
+    acc[5] = fmax(acc[5], du);
+  }
+  for (int i = gtid(); i < g.n_bus; i += gstride()) {
+    double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
+    residual_bus(g, x, w, i, pr, du);
+    acc[0] = fmax(acc[0], pr[0]);
+    acc[4] = fmax(acc[4], pr[4]);
+    acc[5] = fmax(acc[5], du);
+  }
+  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    double bnd, du, gf;
+    residual_gen(g, x, w, k, bnd, du, gf);
+    acc[4] = fmax(acc[4], bnd);
+    acc[5] = fmax(acc[5], du);
+    acc[6] = fmax(acc[6], gf);
+  }
+#pragma unroll
+  for (int k = 0; k < kResidFields; ++k) acc[k] = block_max(acc[k], lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kResidFields; ++k) w.resid_partials[k * w.max_partials + blockIdx.x] = acc[k];
+  }
+}
+
+__global__ void k_residuals_final(Workspace w, int nparts) {
+  __shared__ double lds[16];
+  double acc[kResidFields];
+#pragma unroll
+  for (int k = 0; k < kResidFields; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kResidFields; ++k) acc[k] = fmax(acc[k], w.resid_partials[k * w.max_partials + b]);
+  }
+#pragma unroll
+  for (int k = 0; k < kResidFields; ++k) acc[k] = block_max(acc[k], lds);
+  if (threadIdx.x == 0) {
+    ResidualReport* r = w.report;
+    r->balance = acc[0];
+    r->c11 = acc[1];
+    r->c12 = acc[2];
+    r->limit = acc[3];
+    r->bounds = acc[4];
+    r->dual = acc[5];
+    r->gradf = acc[6];
+  }
+}
+
 // ---------------------------------------------------------------- host helpers
+// Two HIP events released when the owner goes out of scope.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t create() {
+    hipError_t e = hipEventCreate(&a);
+    return e == hipSuccess ? hipEventCreate(&b) : e;
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
 int blocks_for(long long n, int bs) {
   long long b = (n + bs - 1) / bs;
   if (b < 1) b = 1;
@@ -378,8 +571,9 @@ acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double 
   return ACOPF_OK;
 }
 
-acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const double* rho_l,
-                             const double* lam_g, const double* lam_l, void* workspace, void* stream) {
+static acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const double* rho_l,
+                            const double* lam_g, const double* lam_l, bool keep_lam, void* workspace,
+                            void* stream) {
   if (!grid_ok(g) || !workspace || !rho_l || (g->n_gen > 0 && !rho_g))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_init: null argument");
   if ((lam_g == nullptr) != (lam_l == nullptr))
@@ -396,7 +590,9 @@ acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const dou
   };
   copy(w.rho_g, rho_g, G2);
   copy(w.rho_l, rho_l, L8);
-  if (lam_l) {
+  if (keep_lam) {
+    // multipliers of the previous solve stay in place (previous-iterate warm start)
+  } else if (lam_l) {
     copy(w.lam_g, lam_g, G2);
     copy(w.lam_l, lam_l, L8);
   } else {
@@ -417,6 +613,11 @@ acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const dou
   hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, 0);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
+}
+
+acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const double* rho_l,
+                             const double* lam_g, const double* lam_l, void* workspace, void* stream) {
+  return admm_init_impl(g, rho_g, rho_l, lam_g, lam_l, false, workspace, stream);
 }
 
 acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, void* workspace,
@@ -533,6 +734,84 @@ acopf_status acopf_step(const acopf_grid* g, const acopf_iterate* x, void* works
   hipLaunchKernelGGL(k_step_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, w, *d);
   hipLaunchKernelGGL(k_step_nodes, dim3(blocks_for(std::max(g->n_bus, g->n_gen), bs)), dim3(bs), 0, s, *g, w, *d);
   HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_sqp_step(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d,
+                            const double* rho_g, const double* rho_l, const acopf_sqp_params* p, void* workspace,
+                            void* stream, acopf_sqp_state* state) {
+  if (!grid_ok(g) || !iterate_ok(x) || !iterate_ok(d) || !p || !workspace || !state)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: null argument");
+  if (!(state->delta > 0.0) || !(p->mu > 0.0) || !(p->delta_max > 0.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: trust radius, penalty and radius cap must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  acopf_status rc = acopf_qp_build(g, x, state->delta, p->hessian_mode, workspace, stream);
+  if (rc != ACOPF_OK) return rc;
+  rc = admm_init_impl(g, rho_g, rho_l, nullptr, nullptr, p->warm_start != 0, workspace, stream);
+  if (rc != ACOPF_OK) return rc;
+  // the solve checks the build's error flags first (a synchronising read),
+  // so the events bracket the sweep launches only
+  SyncState pre;
+  rc = read_sync(workspace, g, s, &pre);
+  if (rc != ACOPF_OK) return rc;
+  EventPair ev;
+  HIP_TRY(ev.create());
+  HIP_TRY(hipEventRecord(ev.a, s));
+  rc = acopf_admm_solve(g, &p->admm, workspace, stream, nullptr);
+  if (rc != ACOPF_OK) return rc;
+  HIP_TRY(hipEventRecord(ev.b, s));
+  rc = acopf_step(g, x, workspace, d, stream);
+  if (rc != ACOPF_OK) return rc;
+  const int bs = 256;
+  const int nb = std::min(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs), w.max_partials);
+  hipLaunchKernelGGL(k_merit, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, w, nb, p->mu, state->delta, p->delta_max, p->grow_ratio);
+  hipLaunchKernelGGL(k_apply, dim3(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs)), dim3(bs), 0, s,
+                     *g, *x, *d, w);
+  HIP_TRY(hipGetLastError());
+  SqpDecision dc;
+  HIP_TRY(hipMemcpyAsync(&dc, w.decision, sizeof(dc), hipMemcpyDeviceToHost, s));
+  acopf_admm_result ar;
+  rc = acopf_admm_result_get(g, workspace, stream, &ar);
+  if (rc != ACOPF_OK) return rc;
+  state->accepted = dc.accepted;
+  state->ared = dc.ared;
+  state->pred = dc.pred;
+  state->step_inf = dc.step_inf;
+  state->delta = dc.delta_out;
+  state->objective = dc.accepted ? dc.f_xd : dc.f_x;
+  state->merit = dc.accepted ? dc.f_xd + p->mu * dc.h_xd : dc.f_x + p->mu * dc.h_x;
+  state->admm_sweeps = ar.sweeps;
+  state->admm_r = ar.r_norm;
+  state->admm_s = ar.s_norm;
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+  state->admm_ms = ms;
+  return ACOPF_OK;
+}
+
+acopf_status acopf_residuals(const acopf_grid* g, const acopf_iterate* x, void* workspace, void* stream,
+                             acopf_residuals_report* out) {
+  if (!grid_ok(g) || !iterate_ok(x) || !workspace || !out)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_residuals: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int bs = 256;
+  const int nb = std::min(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs), w.max_partials);
+  hipLaunchKernelGGL(k_residuals, dim3(nb), dim3(bs), 0, s, *g, *x, w);
+  hipLaunchKernelGGL(k_residuals_final, dim3(1), dim3(256), 0, s, w, nb);
+  HIP_TRY(hipGetLastError());
+  ResidualReport r;
+  HIP_TRY(hipMemcpyAsync(&r, w.report, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->balance = r.balance;
+  out->c11 = r.c11;
+  out->c12 = r.c12;
+  out->limit = r.limit;
+  out->bounds = r.bounds;
+  out->primal = std::max(std::max(std::max(r.balance, r.c11), std::max(r.c12, r.limit)), r.bounds);
+  out->dual = r.dual / std::max(1.0, r.gradf);
   return ACOPF_OK;
 }
 

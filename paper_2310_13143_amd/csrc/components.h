@@ -497,3 +497,168 @@ ACOPF_HD void step_line(const acopf_grid& g, const acopf_iterate& x, const Works
 }
 
 }  // namespace acopf
+
+namespace acopf {
+
+// Merit pieces of line l (Section II-C) at x and at the trial point x + d:
+// out[0] = h contribution at x, out[1] = at x + d, out[2] = m(d)
+// contribution (linearised constraints), out[3] = the line's model
+// quadratic 0.5 z^T M z + q^T z at the bus-side step z.
+ACOPF_HD void merit_line(const acopf_grid& g, const acopf_iterate& x, const Workspace& w,
+                         const acopf_iterate& d, int l, double out[4]) {
+  const int L = w.n_line;
+  const int f = g.line_from[l], t = g.line_to[l];
+  const double gii = g.gii[l], bii = g.bii[l], gij = g.gij[l], bij = g.bij[l];
+  const double gji = g.gji[l], bji = g.bji[l], gjj = g.gjj[l], bjj = g.bjj[l];
+  const double s2ij = g.smax_ij[l] * g.smax_ij[l], s2ji = g.smax_ji[l] * g.smax_ji[l];
+  double hv[2];
+#pragma unroll
+  for (int trial = 0; trial < 2; ++trial) {
+    const double a = trial ? 1.0 : 0.0;
+    const double wi = x.w[f] + a * d.w[f], wj = x.w[t] + a * d.w[t];
+    const double wR = x.wR[l] + a * d.wR[l], wI = x.wI[l] + a * d.wI[l];
+    const double ph = (x.th[f] + a * d.th[f]) - (x.th[t] + a * d.th[t]);
+    const double c11 = wR * wR + wI * wI - wi * wj;
+    const double c12 = wR * sin(ph) - wI * cos(ph);
+    const double pij = gii * wi + gij * wR + bij * wI, qij = -bii * wi - bij * wR + gij * wI;
+    const double pji = gjj * wj + gji * wR - bji * wI, qji = -bjj * wj - bji * wR - gji * wI;
+    const double c13 = s2ij - pij * pij - qij * qij, c14 = s2ji - pji * pji - qji * qji;
+    hv[trial] = fabs(c11) + fabs(c12) + fmax(0.0, -c13) + fmax(0.0, -c14);
+  }
+  // linearised constraints at x along d
+  const double wi = x.w[f], wj = x.w[t], wR = x.wR[l], wI = x.wI[l];
+  const double ph = x.th[f] - x.th[t];
+  const double s = sin(ph), c = cos(ph);
+  const double K = wR * c + wI * s;
+  const double c11 = wR * wR + wI * wI - wi * wj, c12 = wR * s - wI * c;
+  const double pij = gii * wi + gij * wR + bij * wI, qij = -bii * wi - bij * wR + gij * wI;
+  const double pji = gjj * wj + gji * wR - bji * wI, qji = -bjj * wj - bji * wR - gji * wI;
+  const double c13 = s2ij - pij * pij - qij * qij, c14 = s2ji - pji * pji - qji * qji;
+  const double dwi = d.w[f], dwj = d.w[t], dR = d.wR[l], dI = d.wI[l];
+  const double l11 = c11 + 2.0 * wR * dR + 2.0 * wI * dI - wj * dwi - wi * dwj;
+  const double l12 = c12 + s * dR - c * dI + K * (d.th[f] - d.th[t]);
+  const double dpij = gii * dwi + gij * dR + bij * dI, dqij = -bii * dwi - bij * dR + gij * dI;
+  const double dpji = gjj * dwj + gji * dR - bji * dI, dqji = -bjj * dwj - bji * dR - gji * dI;
+  const double l13 = c13 - 2.0 * pij * dpij - 2.0 * qij * dqij;
+  const double l14 = c14 - 2.0 * pji * dpji - 2.0 * qji * dqji;
+  // model quadratic with the QP's reduced Hessian
+  const double z[4] = {d.w[f], d.th[f], d.w[t], d.th[t]};
+  double Mp[10], M[4][4];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) Mp[k] = w.line[(LF_M + k) * L + l];
+  sym_unpack(Mp, M);
+  double quad = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double mz = M[i][0] * z[0] + M[i][1] * z[1] + M[i][2] * z[2] + M[i][3] * z[3];
+    quad += 0.5 * z[i] * mz + w.line[(LF_Q + i) * L + l] * z[i];
+  }
+  out[0] = hv[0];
+  out[1] = hv[1];
+  out[2] = fabs(l11) + fabs(l12) + fmax(0.0, -l13) + fmax(0.0, -l14);
+  out[3] = quad;
+}
+
+// Objective pieces of generator k: f(p), f(p + d), model f'(p) d + 0.5 f'' d^2.
+ACOPF_HD void merit_gen(const acopf_grid& g, const acopf_iterate& x, const acopf_iterate& d, int k,
+                        double out[3]) {
+  const double p = x.pg[k], dp = d.pg[k], pt = p + dp;
+  out[0] = g.cost2[k] * p * p + g.cost1[k] * p;
+  out[1] = g.cost2[k] * pt * pt + g.cost1[k] * pt;
+  out[2] = (2.0 * g.cost2[k] * p + g.cost1[k]) * dp + g.cost2[k] * dp * dp;
+}
+
+// Residual report pieces.  Each routine returns maxima so the reduction is
+// order independent.  primal[0..4] = balance, c11, c12, limit, bounds;
+// dual = projected Lagrangian-gradient magnitude; gradf = |f'(p)|.
+ACOPF_HD double proj_grad(double gr, double v, double lo, double hi) {
+  const double tol = 1e-6;
+  const bool atlo = v <= lo + tol, athi = v >= hi - tol;
+  double r = fabs(gr);
+  r = atlo ? fmax(-gr, 0.0) : r;
+  r = athi ? fmax(gr, 0.0) : r;
+  return (atlo && athi) ? 0.0 : r;
+}
+
+ACOPF_HD void residual_line(const acopf_grid& g, const acopf_iterate& x, const Workspace& w, int l,
+                            double primal[5], double& dual) {
+  const int L = w.n_line, B = w.n_bus;
+  const int f = g.line_from[l], t = g.line_to[l];
+  const double gii = g.gii[l], bii = g.bii[l], gij = g.gij[l], bij = g.bij[l];
+  const double gji = g.gji[l], bji = g.bji[l], gjj = g.gjj[l], bjj = g.bjj[l];
+  const double wi = x.w[f], wj = x.w[t], wR = x.wR[l], wI = x.wI[l];
+  const double ph = x.th[f] - x.th[t];
+  const double s = sin(ph), c = cos(ph);
+  const double pij = gii * wi + gij * wR + bij * wI, qij = -bii * wi - bij * wR + gij * wI;
+  const double pji = gjj * wj + gji * wR - bji * wI, qji = -bjj * wj - bji * wR - gji * wI;
+  const double c11 = wR * wR + wI * wI - wi * wj, c12 = wR * s - wI * c;
+  const double c13 = g.smax_ij[l] * g.smax_ij[l] - pij * pij - qij * qij;
+  const double c14 = g.smax_ji[l] * g.smax_ji[l] - pji * pji - qji * qji;
+  primal[1] = fabs(c11);
+  primal[2] = fabs(c12);
+  primal[3] = fmax(fmax(0.0, -c13), fmax(0.0, -c14));
+  const double p11 = x.pi[l], p12 = x.pi[L + l], p13 = x.pi[2 * L + l], p14 = x.pi[3 * L + l];
+  const double ypf = w.nu[f], yqf = w.nu[B + f], ypt = w.nu[t], yqt = w.nu[B + t];
+  const double gR = -ypf * gij + yqf * bij - ypt * gji + yqt * bji + 2.0 * p11 * wR + p12 * s +
+                    p13 * (-2.0 * pij * gij + 2.0 * qij * bij) + p14 * (-2.0 * pji * gji + 2.0 * qji * bji);
+  const double gI = -ypf * bij - yqf * gij + ypt * bji + yqt * gji + 2.0 * p11 * wI - p12 * c +
+                    p13 * (-2.0 * pij * bij - 2.0 * qij * gij) + p14 * (2.0 * pji * bji + 2.0 * qji * gji);
+  dual = fmax(fabs(gR), fabs(gI));
+}
+
+ACOPF_HD void residual_bus(const acopf_grid& g, const acopf_iterate& x, const Workspace& w, int i,
+                           double primal[5], double& dual) {
+  const int L = w.n_line, B = w.n_bus;
+  const double wi = x.w[i];
+  const double yp = w.nu[i], yq = w.nu[B + i];
+  double rp = -g.pd[i] - g.gsh[i] * wi, rq = -g.qd[i] + g.bsh[i] * wi;
+  double gw = -g.gsh[i] * yp + g.bsh[i] * yq, gth = 0.0;
+  for (int e = w.bus_gen_ptr[i]; e < w.bus_gen_ptr[i + 1]; ++e) {
+    const int k = w.bus_gen[e];
+    rp += x.pg[k];
+    rq += x.qg[k];
+  }
+  for (int e = w.bus_end_ptr[i]; e < w.bus_end_ptr[i + 1]; ++e) {
+    const int code = w.bus_end[e];
+    const int l = code >> 1, side = code & 1;
+    const int o = side ? g.line_from[l] : g.line_to[l];
+    const double wo = x.w[o], wR = x.wR[l], wI = x.wI[l];
+    const double p11 = x.pi[l], p12 = x.pi[L + l], p13 = x.pi[2 * L + l], p14 = x.pi[3 * L + l];
+    const double ph = side ? (x.th[o] - x.th[i]) : (x.th[i] - x.th[o]);
+    const double K = wR * cos(ph) + wI * sin(ph);
+    if (side == 0) {
+      const double gii = g.gii[l], bii = g.bii[l];
+      const double p = gii * wi + g.gij[l] * wR + g.bij[l] * wI, q = -bii * wi - g.bij[l] * wR + g.gij[l] * wI;
+      rp -= p;
+      rq -= q;
+      gw += -yp * gii + yq * bii - p11 * wo + p13 * (-2.0 * p * gii + 2.0 * q * bii);
+      gth += p12 * K;
+    } else {
+      const double gjj = g.gjj[l], bjj = g.bjj[l];
+      const double p = gjj * wi + g.gji[l] * wR - g.bji[l] * wI, q = -bjj * wi - g.bji[l] * wR - g.gji[l] * wI;
+      rp -= p;
+      rq -= q;
+      gw += -yp * gjj + yq * bjj - p11 * wo + p14 * (-2.0 * p * gjj + 2.0 * q * bjj);
+      gth -= p12 * K;
+    }
+  }
+  const double v2lo = g.vmin[i] * g.vmin[i], v2hi = g.vmax[i] * g.vmax[i];
+  primal[0] = fmax(fabs(rp), fabs(rq));
+  const double thv = fmax(fmax(0.0, -(x.th[i] + kTwoPi)), fmax(0.0, x.th[i] - kTwoPi));
+  primal[4] = fmax(fmax(fmax(0.0, v2lo - wi), fmax(0.0, wi - v2hi)), thv);
+  dual = fmax(proj_grad(gw, wi, v2lo, v2hi), (i == g.ref_bus) ? 0.0 : fabs(gth));
+}
+
+ACOPF_HD void residual_gen(const acopf_grid& g, const acopf_iterate& x, const Workspace& w, int k,
+                           double& bound, double& dual, double& gradf) {
+  const int B = w.n_bus;
+  const int i = g.gen_bus[k];
+  const double p = x.pg[k], q = x.qg[k];
+  const double fp = 2.0 * g.cost2[k] * p + g.cost1[k];
+  bound = fmax(fmax(fmax(0.0, g.pmin[k] - p), fmax(0.0, p - g.pmax[k])),
+               fmax(fmax(0.0, g.qmin[k] - q), fmax(0.0, q - g.qmax[k])));
+  dual = fmax(proj_grad(fp + w.nu[i], p, g.pmin[k], g.pmax[k]), proj_grad(w.nu[B + i], q, g.qmin[k], g.qmax[k]));
+  gradf = fabs(fp);
+}
+
+}  // namespace acopf

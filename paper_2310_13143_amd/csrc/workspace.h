@@ -49,6 +49,23 @@ struct SyncState {
   double r_norm, s_norm;
 };
 
+// Outcome of one trust-region SQP step (Algorithm 1), decided on the device.
+struct SqpDecision {
+  double f_x, f_xd, h_x, h_xd, m_d, quad;   // objective, merit h, model pieces
+  double ared, pred, step_inf;
+  double delta_in, delta_out;
+  int accepted;
+  int pad;
+};
+
+// Residual report (maxima; order independent).
+struct ResidualReport {
+  double balance, c11, c12, limit, bounds, dual, gradf;
+};
+
+constexpr int kMeritFields = 8;     // f_x, f_xd, quad_gen, h_x, h_xd, m_d, quad_line, step max
+constexpr int kResidFields = 7;     // balance, c11, c12, limit, bounds, dual, gradf
+
 struct Workspace {
   int32_t n_bus, n_line, n_gen, max_partials;
   // topology
@@ -74,7 +91,11 @@ struct Workspace {
   // reductions
   double* partials;        // [2][max_partials]
   unsigned int* arrive;    // [max_partials * kArriveStride] grid-barrier arrival epochs
+  double* merit_partials;  // [kMeritFields][max_partials]
+  double* resid_partials;  // [kResidFields][max_partials]
   SyncState* sync;
+  SqpDecision* decision;
+  ResidualReport* report;
 };
 
 // Arrival flags of different blocks sit on different 128-byte lines.
@@ -123,7 +144,11 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, W
   t.line_mask = (int32_t*)take((size_t)nl * I);
   t.partials = (double*)take((size_t)2 * maxp * D);
   t.arrive = (unsigned int*)take((size_t)maxp * kArriveStride * sizeof(unsigned int));
+  t.merit_partials = (double*)take((size_t)kMeritFields * maxp * D);
+  t.resid_partials = (double*)take((size_t)kResidFields * maxp * D);
   t.sync = (SyncState*)take(sizeof(SyncState));
+  t.decision = (SqpDecision*)take(sizeof(SqpDecision));
+  t.report = (ResidualReport*)take(sizeof(ResidualReport));
   if (w) *w = t;
   return off;
 }

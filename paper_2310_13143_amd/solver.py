@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import AdmmParams, AdmmResult, AdmmState, Grid, Iterate, check
+from ._abi import (AdmmParams, AdmmResult, AdmmState, Grid, Iterate, ResidualsReport, SqpParams, SqpState,
+                   check)
 
 
 def _stream_handle(device) -> int:
@@ -136,3 +137,31 @@ class DeviceGrid:
         check(self.lib.acopf_step(ctypes.byref(self.cgrid), ctypes.byref(cx), self.ws, ctypes.byref(cd),
                                   self.stream))
         return d
+
+    def sqp_step(self, x: dict, delta: float, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
+                 grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start: bool = False,
+                 max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
+                 block_size: int = 0, d: dict | None = None) -> dict:
+        """One trust-region SQP iteration on the device; x is updated in place
+        when the step is accepted.  Returns the host-side decision record."""
+        if d is None:
+            d = self.empty_iterate()
+        self._d = d
+        f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+        self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
+        p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), int(bool(warm_start)),
+                      AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size), 0))
+        st = SqpState()
+        st.delta = float(delta)
+        cx, cd = self.c_iterate(x), self.c_iterate(d)
+        check(self.lib.acopf_sqp_step(ctypes.byref(self.cgrid), ctypes.byref(cx), ctypes.byref(cd),
+                                      self._rho_g.data_ptr(), self._rho_l.data_ptr(), ctypes.byref(p), self.ws,
+                                      self.stream, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in SqpState._fields_}
+
+    def residuals(self, x: dict) -> dict:
+        r = ResidualsReport()
+        cx = self.c_iterate(x)
+        check(self.lib.acopf_residuals(ctypes.byref(self.cgrid), ctypes.byref(cx), self.ws, self.stream,
+                                       ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in ResidualsReport._fields_}

@@ -109,4 +109,48 @@ void emu_state_ptrs(void* base, int nb, int nl, int ng, double** out) {
   out[4] = w.lam_g; out[5] = w.dw; out[6] = w.dth; out[7] = w.nu;
 }
 
+// Merit sums of an SQP step (order: f_x, f_xd, quad_gen, h_x, h_xd, m_d,
+// quad_line, step max) from a workspace holding the QP of x.
+void emu_merit(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d, void* base, double* out) {
+  Workspace w;
+  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, &w);
+  for (int k = 0; k < 8; ++k) out[k] = 0.0;
+  for (int l = 0; l < g->n_line; ++l) {
+    double o[4];
+    merit_line(*g, *x, w, *d, l, o);
+    out[3] += o[0]; out[4] += o[1]; out[5] += o[2]; out[6] += o[3];
+  }
+  for (int k = 0; k < g->n_gen; ++k) {
+    double o[3];
+    merit_gen(*g, *x, *d, k, o);
+    out[0] += o[0]; out[1] += o[1]; out[2] += o[2];
+    out[7] = fmax(out[7], fmax(fabs(d->pg[k]), fabs(d->qg[k])));
+  }
+  for (int i = 0; i < g->n_bus; ++i) out[7] = fmax(out[7], fmax(fabs(d->w[i]), fabs(d->th[i])));
+}
+
+// Residual maxima (balance, c11, c12, limit, bounds, dual, gradf) at x with
+// the workspace's balance multipliers.
+void emu_residuals(const acopf_grid* g, const acopf_iterate* x, void* base, double* out) {
+  Workspace w;
+  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, &w);
+  for (int k = 0; k < 7; ++k) out[k] = 0.0;
+  for (int l = 0; l < g->n_line; ++l) {
+    double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
+    residual_line(*g, *x, w, l, pr, du);
+    out[1] = fmax(out[1], pr[1]); out[2] = fmax(out[2], pr[2]); out[3] = fmax(out[3], pr[3]);
+    out[5] = fmax(out[5], du);
+  }
+  for (int i = 0; i < g->n_bus; ++i) {
+    double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
+    residual_bus(*g, *x, w, i, pr, du);
+    out[0] = fmax(out[0], pr[0]); out[4] = fmax(out[4], pr[4]); out[5] = fmax(out[5], du);
+  }
+  for (int k = 0; k < g->n_gen; ++k) {
+    double b, du, gf;
+    residual_gen(*g, *x, w, k, b, du, gf);
+    out[4] = fmax(out[4], b); out[5] = fmax(out[5], du); out[6] = fmax(out[6], gf);
+  }
+}
+
 }  // extern "C"

@@ -36,7 +36,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     """Sizes and member offsets of the ctypes mirrors equal the C compiler's."""
     import subprocess
     checks = {"acopf_grid": _abi.Grid, "acopf_iterate": _abi.Iterate, "acopf_admm_params": _abi.AdmmParams,
-              "acopf_admm_result": _abi.AdmmResult, "acopf_admm_state": _abi.AdmmState}
+              "acopf_admm_result": _abi.AdmmResult, "acopf_admm_state": _abi.AdmmState,
+              "acopf_sqp_params": _abi.SqpParams, "acopf_sqp_state": _abi.SqpState,
+              "acopf_residuals_report": _abi.ResidualsReport}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "acopf_admm.h"', "int main(void) {"]
     for cname, py in checks.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

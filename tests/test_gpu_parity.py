@@ -237,3 +237,37 @@ def test_error_paths():
     with pytest.raises(AcopfError) as e:
         DeviceGrid(bad)
     assert e.value.code == -1
+
+
+def test_sqp_iterations_match_oracle():
+    """Trust-region SQP (Algorithm 1) on the device against the oracle's SQP,
+    iteration by iteration, with a fixed sweep budget per QP (no early stop,
+    so both sides run the same ADMM iterations): acceptance decisions, trust
+    radii, iterates, multipliers and the residual report."""
+    print("[gpu] sqp ring14", flush=True)
+    g = grid_14()
+    x0, _ = start_point(g)
+    params = sqp.SqpParams(max_iter=6, max_sweeps=300, eps_pri=0.0, eps_dual=0.0, delta0=0.05, tol_step=0.0,
+                           tol_primal=0.0, tol_dual=0.0)
+    ref = sqp.solve(g, params, x0=x0)
+    dg = _dev()(g)
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, None)
+    rho_g, rho_l = dg.rho_scalar(params.rho)
+    delta = params.delta0
+    for k, rec in enumerate(ref.records):
+        out = dg.sqp_step(x, delta, rho_g, rho_l, mu=params.mu_merit, delta_max=params.delta_max,
+                          warm_start=k > 0, max_sweeps=params.max_sweeps, eps=0.0)
+        assert out["admm_sweeps"] == params.max_sweeps
+        assert bool(out["accepted"]) == rec.accepted, k
+        scale = 1.0 + abs(rec.pred)
+        assert abs(out["ared"] - rec.ared) <= 1e-6 * (1.0 + abs(rec.ared)), (k, out["ared"], rec.ared)
+        assert abs(out["pred"] - rec.pred) <= 1e-6 * scale, (k, out["pred"], rec.pred)
+        assert abs(out["delta"] - rec.delta) <= 1e-12 * rec.delta, k
+        delta = out["delta"]
+        res = dg.residuals(x)
+        assert abs(res["primal"] - rec.primal) <= 1e-6 * (1.0 + rec.primal), (k, res, rec.primal)
+        assert abs(res["dual"] - rec.dual) <= 1e-6 * (1.0 + rec.dual), (k, res, rec.dual)
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    for name in ("pg", "qg", "w", "th", "wR", "wI"):
+        assert rel_err(xf[name], getattr(ref.x, name)) <= TOL, name
+    assert rel_err(xf["pi"].reshape(4, -1).T, ref.pi) <= 1e-7

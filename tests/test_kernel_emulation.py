@@ -157,6 +157,26 @@ def test_sweeps_and_step_match_oracle(emu, case):
     close(d_arrays[5], dref.wI)
     close(d_arrays[0], dref.pg)
     close(d_arrays[6].reshape(4, -1).T, pref, tol=1e-7)
+    # merit and model of the SQP acceptance test (Section II-C)
+    mer = np.zeros(8)
+    emu.emu_merit(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.byref(cd), ctypes.c_void_p(base), ptr(mer))
+    mu = 1e5
+    ared = (mer[0] + mu * mer[3]) - (mer[1] + mu * mer[4])
+    pred = -(mer[2] + mer[6]) + mu * (mer[3] - mer[5])
+    xt = x.plus(dref)
+    ared_ref = acopf.merit(g, x, mu) - acopf.merit(g, xt, mu)
+    pred_ref = sqp.predicted_reduction(g, x, Q, dref, mu)
+    scale = acopf.merit(g, x, mu)
+    assert abs(ared - ared_ref) <= 1e-9 * abs(scale) and abs(pred - pred_ref) <= 1e-9 * abs(scale)
+    assert abs(mer[7] - sqp.step_norm(dref)) <= 1e-12
+    # residual report at x with the ADMM's balance multipliers and pi
+    res = np.zeros(7)
+    emu.emu_residuals(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.c_void_p(base), ptr(res))
+    pr = acopf.primal_infeasibility(g, x)
+    for k, name in enumerate(("balance", "c11", "c12", "limit", "bounds")):
+        assert abs(res[k] - pr[name]) <= 1e-12 * (1 + pr[name]), name
+    du = acopf.dual_infeasibility(g, x, st.nu[:, 0], st.nu[:, 1], pi)
+    assert abs(res[5] / max(1.0, res[6]) - du) <= 1e-9 * (1 + du)
 
 
 def _layout(emu, g, base):
