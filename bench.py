@@ -36,15 +36,16 @@ def sweep_bytes(n_bus: int, n_line: int, n_gen: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rgg2000", choices=["ring14", "rgg300", "rgg2000", "rgg10000", "rgg70000"])
     ap.add_argument("--sweeps", type=int, default=2000)
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--rho", type=float, default=2e4)
     ap.add_argument("--delta", type=float, default=0.05)
-    ap.add_argument("--mode", default="persistent", choices=["persistent", "launches"])
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--mode", default="launches", choices=["persistent", "launches"])
+    ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--max-blocks", type=int, default=0, help="persistent grid size cap (0 = fill the device)")
     ap.add_argument("--cpu-sweeps", type=int, default=20, help="oracle sweeps timed for the CPU baseline (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -68,7 +69,7 @@ def main():
 
     state = {"delta": args.delta, "k": 0}
     sqp_kw = dict(mu=1e5, delta_max=10.0, max_sweeps=args.sweeps, eps=args.eps, sweep_mode=mode,
-                  block_size=args.block)
+                  block_size=args.block, max_blocks=args.max_blocks)
 
     def one_step():
         out = dg.sqp_step(x, state["delta"], rho_g, rho_l, warm_start=state["k"] > 0, **sqp_kw)

@@ -141,7 +141,7 @@ class DeviceGrid:
     def sqp_step(self, x: dict, delta: float, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
                  grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start: bool = False,
                  max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
-                 block_size: int = 0, d: dict | None = None) -> dict:
+                 block_size: int = 0, max_blocks: int = 0, d: dict | None = None) -> dict:
         """One trust-region SQP iteration on the device; x is updated in place
         when the step is accepted.  Returns the host-side decision record."""
         if d is None:
@@ -150,7 +150,8 @@ class DeviceGrid:
         f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), int(bool(warm_start)),
-                      AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size), 0))
+                      AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size),
+                                 int(max_blocks)))
         st = SqpState()
         st.delta = float(delta)
         cx, cd = self.c_iterate(x), self.c_iterate(d)
