@@ -1,0 +1,188 @@
+"""Learned warm start for the ADMM solve (not in the paper): a small
+per-component MLP that predicts initial multipliers of a component's
+couplings from local data, trained on multipliers the method itself
+produces.  Plain FP64 NumPy restatement of the network the HIP path trains
+in FP32.
+
+Network: x -> relu(W1 x + b1) -> relu(W2 h1 + b2) -> W3 h2 + b3, loss the
+mean squared error over samples and outputs, optimiser Adam (Kingma and Ba,
+2015) with bias correction.
+
+Features (per component, from the grid, the loads and the SQP iterate):
+  line (16): p_d, q_d at both ends; g_ij, b_ij, g_ii, b_ii, g_jj, b_jj
+             scaled by 1/100; w_i, w_j, wR, wI; sin of the angle
+             difference; s_max_ij;
+  gen (8):   p_d, q_d of its bus; cost2 / 1e4; cost1 / 1e3; p_g, q_g;
+             p_max, q_max.
+Targets: the component's coupling multipliers (8 per line, 2 per generator)
+divided by 1e3.
+
+Test infrastructure only (see the package docstring).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+import numpy as np
+
+LAM_SCALE = 1e3
+N_LINE_FEAT = 16
+N_GEN_FEAT = 8
+
+
+def line_features(grid, x) -> np.ndarray:
+    f, t = grid.f, grid.t
+    ph = x.th[f] - x.th[t]
+    cols = [grid.pd[f], grid.qd[f], grid.pd[t], grid.qd[t],
+            grid.gij / 100, grid.bij / 100, grid.gii / 100, grid.bii / 100, grid.gjj / 100, grid.bjj / 100,
+            x.w[f], x.w[t], x.wR, x.wI, np.sin(ph), grid.smax_ij]
+    return np.stack(cols, 1)
+
+
+def gen_features(grid, x) -> np.ndarray:
+    b = grid.gbus
+    cols = [grid.pd[b], grid.qd[b], grid.cost2 / 1e4, grid.cost1 / 1e3, x.pg, x.qg, grid.pmax, grid.qmax]
+    return np.stack(cols, 1)
+
+
+@dataclass
+class Params:
+    W1: np.ndarray
+    b1: np.ndarray
+    W2: np.ndarray
+    b2: np.ndarray
+    W3: np.ndarray
+    b3: np.ndarray
+
+    def flat(self) -> np.ndarray:
+        return np.concatenate([a.ravel() for a in (self.W1, self.b1, self.W2, self.b2, self.W3, self.b3)])
+
+    @staticmethod
+    def unflat(v, n_in, n_h, n_out) -> "Params":
+        shapes = [(n_h, n_in), (n_h,), (n_h, n_h), (n_h,), (n_out, n_h), (n_out,)]
+        out, o = [], 0
+        for s in shapes:
+            n = int(np.prod(s))
+            out.append(np.asarray(v[o:o + n], dtype=np.float64).reshape(s))
+            o += n
+        return Params(*out)
+
+
+def n_params(n_in, n_h, n_out) -> int:
+    return n_h * n_in + n_h + n_h * n_h + n_h + n_out * n_h + n_out
+
+
+def forward(p: Params, X: np.ndarray):
+    z1 = X @ p.W1.T + p.b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ p.W2.T + p.b2
+    h2 = np.maximum(z2, 0.0)
+    y = h2 @ p.W3.T + p.b3
+    return y, (X, z1, h1, z2, h2)
+
+
+def loss(p: Params, X, T) -> float:
+    y, _ = forward(p, X)
+    return float(np.mean((y - T) ** 2))
+
+
+def gradients(p: Params, X, T) -> Params:
+    """Gradient of the mean squared error by back-propagation."""
+    y, (X, z1, h1, z2, h2) = forward(p, X)
+    n, m = T.shape
+    d3 = 2.0 * (y - T) / (n * m)
+    gW3 = d3.T @ h2
+    gb3 = d3.sum(0)
+    d2 = (d3 @ p.W3) * (z2 > 0)
+    gW2 = d2.T @ h1
+    gb2 = d2.sum(0)
+    d1 = (d2 @ p.W2) * (z1 > 0)
+    gW1 = d1.T @ X
+    gb1 = d1.sum(0)
+    return Params(gW1, gb1, gW2, gb2, gW3, gb3)
+
+
+def adam_step(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update of the flat parameter vector (t counts from 1)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Training targets and the decoding of network outputs into an ADMM start.
+#
+# Line output row layout: 8 multipliers (coupling order p_ij, q_ij, p_ji,
+# q_ji, w_i, th_i, w_j, th_j) divided by LAM_SCALE, then 8 log penalty
+# factors; generator rows: 2 multipliers (p, q) / LAM_SCALE, then 2 log
+# penalty factors.  The penalty factor of a coupling is the residual-
+# balancing ratio over a traced solve: rho* = rho * clip(sqrt(rho sum|r_c| /
+# sum|s_c|), 0.1, 10), where r_c = x_c - xbar_c and s_c = rho (xbar_c^new -
+# xbar_c^old) are the coupling's primal and dual residuals of each sweep
+# (Section IV-B5); the factor raises rho where the primal residual dominates
+# and lowers it where the dual one does (residual balancing, Boyd et al.,
+# 2011, Section 3.4.1).
+
+RHO_CLIP = 10.0
+
+
+def _xbar_line(grid, st):
+    f, t = grid.f, grid.t
+    return np.concatenate([st.xbar_f, np.stack([st.dw[f], st.dth[f], st.dw[t], st.dth[t]], 1)], 1)
+
+
+def trace_sums(grid, rho, start, states):
+    """Per-coupling sums of |r_c| and |s_c| over the sweeps of a solve, from
+    its start state and the recorded state after every sweep.  Returns
+    (sum_r_g (G, 2), sum_s_g (G, 2), sum_r_l (L, 8), sum_s_l (L, 8))."""
+    G, L = grid.n_gen, grid.n_line
+    rg, sg = np.zeros((G, 2)), np.zeros((G, 2))
+    rl, sl = np.zeros((L, 8)), np.zeros((L, 8))
+    prev_g, prev_l = start.xbar_g, _xbar_line(grid, start)
+    for st in states:
+        xb_l = _xbar_line(grid, st)
+        rg += np.abs(st.xg - st.xbar_g)
+        rl += np.abs(st.xl - xb_l)
+        sg += np.abs(rho.g * (st.xbar_g - prev_g))
+        sl += np.abs(rho.l * (xb_l - prev_l))
+        prev_g, prev_l = st.xbar_g, xb_l
+    return rg, sg, rl, sl
+
+
+def log_rho_factor(rho, sum_r, sum_s):
+    """log of clip(sqrt(rho sum|r| / sum|s|), 1/RHO_CLIP, RHO_CLIP); a
+    coupling whose two sums vanish keeps its penalty (factor 1), one with
+    only sum|s| = 0 gets the upper clip."""
+    num = rho * sum_r
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(sum_s > 0, num / np.where(sum_s > 0, sum_s, 1.0), np.where(num > 0, np.inf, 1.0))
+    fac = np.clip(np.sqrt(ratio), 1.0 / RHO_CLIP, RHO_CLIP)
+    return np.log(fac)
+
+
+def targets(rho, lam_g, lam_l, sums):
+    """Training targets of one traced solve: (line rows (L, 16), gen rows (G, 4))."""
+    rg, sg, rl, sl = sums
+    tl = np.concatenate([lam_l / LAM_SCALE, log_rho_factor(rho.l, rl, sl)], 1)
+    tg = np.concatenate([lam_g / LAM_SCALE, log_rho_factor(rho.g, rg, sg)], 1)
+    return tl, tg
+
+
+def decode(out_l, out_g, rho_l0, rho_g0, lam_l_plain, lam_g_plain, use_rho):
+    """ADMM start from network outputs: multipliers out * LAM_SCALE, penalties
+    rho0 exp(out) with out clipped to +-log(RHO_CLIP).  A non-finite output
+    falls back to the plain start of that coupling (the previous solve's
+    multiplier, the base penalty).  Returns (lam_l, lam_g, rho_l, rho_g)."""
+    def lam(out, plain):
+        v = np.asarray(out, dtype=np.float64) * LAM_SCALE
+        return np.where(np.isfinite(v), v, plain)
+
+    def rho(out, r0):
+        o = np.asarray(out, dtype=np.float64)
+        c = np.clip(o, -np.log(RHO_CLIP), np.log(RHO_CLIP))
+        v = r0 * np.exp(c)
+        return np.where(np.isfinite(o) & bool(use_rho), v, r0)
+
+    return (lam(out_l[:, :8], lam_l_plain), lam(out_g[:, :2], lam_g_plain),
+            rho(out_l[:, 8:], rho_l0), rho(out_g[:, 2:], rho_g0))
