@@ -117,14 +117,18 @@ def adam_step(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # q_ji, w_i, th_i, w_j, th_j) divided by LAM_SCALE, then 8 log penalty
 # factors; generator rows: 2 multipliers (p, q) / LAM_SCALE, then 2 log
 # penalty factors.  The penalty factor of a coupling is the residual-
-# balancing ratio over a traced solve: rho* = rho * clip(sqrt(rho sum|r_c| /
-# sum|s_c|), 0.1, 10), where r_c = x_c - xbar_c and s_c = rho (xbar_c^new -
-# xbar_c^old) are the coupling's primal and dual residuals of each sweep
-# (Section IV-B5); the factor raises rho where the primal residual dominates
-# and lowers it where the dual one does (residual balancing, Boyd et al.,
-# 2011, Section 3.4.1).
+# balancing ratio over a traced solve, rho* = rho * clip(sqrt((rho sum|r_c|
+# + RHO_REG) / (sum|s_c| + RHO_REG)), 0.1, 10), where r_c = x_c - xbar_c and
+# s_c = rho (xbar_c^new - xbar_c^old) are the coupling's primal and dual
+# residuals of each sweep (Section IV-B5); the factor raises rho where the
+# primal residual dominates and lowers it where the dual one does (residual
+# balancing, Boyd et al., 2011, Section 3.4.1).  RHO_REG (multiplier units,
+# far below the sums of a coupling that moves) makes couplings with
+# vanishing sums, such as the fixed reference angle, get factor 1 whatever
+# rounding noise their sums hold.
 
 RHO_CLIP = 10.0
+RHO_REG = 1e-6
 
 
 def _xbar_line(grid, st):
@@ -151,14 +155,10 @@ def trace_sums(grid, rho, start, states):
 
 
 def log_rho_factor(rho, sum_r, sum_s):
-    """log of clip(sqrt(rho sum|r| / sum|s|), 1/RHO_CLIP, RHO_CLIP); a
-    coupling whose two sums vanish keeps its penalty (factor 1), one with
-    only sum|s| = 0 gets the upper clip."""
-    num = rho * sum_r
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ratio = np.where(sum_s > 0, num / np.where(sum_s > 0, sum_s, 1.0), np.where(num > 0, np.inf, 1.0))
-    fac = np.clip(np.sqrt(ratio), 1.0 / RHO_CLIP, RHO_CLIP)
-    return np.log(fac)
+    """log of clip(sqrt((rho sum|r| + RHO_REG) / (sum|s| + RHO_REG)),
+    1/RHO_CLIP, RHO_CLIP)."""
+    ratio = (rho * sum_r + RHO_REG) / (sum_s + RHO_REG)
+    return np.log(np.clip(np.sqrt(ratio), 1.0 / RHO_CLIP, RHO_CLIP))
 
 
 def targets(rho, lam_g, lam_l, sums):
