@@ -39,7 +39,8 @@ typedef enum {
 
 typedef enum {
   ACOPF_ADMM_CONVERGED = 0,       /* ||r||_2 <= eps_pri and ||s||_2 <= eps_dual */
-  ACOPF_ADMM_MAX_SWEEPS = 1       /* stopped at max_sweeps */
+  ACOPF_ADMM_MAX_SWEEPS = 1,      /* stopped at max_sweeps */
+  ACOPF_ADMM_FAILED = 2           /* not solved: the scenario's QP build or factorisation failed (status) */
 } acopf_admm_outcome;
 
 typedef enum { ACOPF_HESSIAN_PSD = 0, ACOPF_HESSIAN_RAW = 1 } acopf_hessian_mode;
@@ -53,9 +54,14 @@ typedef enum { ACOPF_SWEEP_PERSISTENT = 0, ACOPF_SWEEP_LAUNCHES = 1 } acopf_swee
  * s_bar (not squared).  Generator cost f(p) = cost2 p^2 + cost1 p.  Shunt
  * g_sh + j b_sh enters the balance as in (opfc5, opfc6).  Every bus must be
  * the end of at least one branch.
+ *
+ * A batch of independent scenarios (n_scen > 1) packs the scenarios' arrays
+ * one after another; acopf_setup_batch gives their index ranges and
+ * reference buses (ref_bus is then unused).  n_scen 0 or 1 = one grid.
  */
 typedef struct {
   int32_t n_bus, n_line, n_gen, ref_bus;
+  int32_t n_scen, reserved;
   const double *vmin, *vmax, *pd, *qd, *gsh, *bsh;                   /* [n_bus]  */
   const int32_t *line_from, *line_to;                                /* [n_line] */
   const double *gii, *bii, *gij, *bij, *gji, *bji, *gjj, *bjj;       /* [n_line] */
@@ -81,6 +87,9 @@ typedef struct {
   int32_t sweep_mode;   /* acopf_sweep_mode                                       */
   int32_t block_size;   /* threads per block, multiple of 64, <= 256; 0 = 256     */
   int32_t max_blocks;   /* persistent grid size cap; 0 = as many as fit resident  */
+  int32_t trace;        /* 1 = also sum |r_c| and |s_c| of every coupling over the
+                           sweeps (reset at the start of the solve; exported by
+                           acopf_admm_state_get; launch-per-phase mode only)   */
 } acopf_admm_params;
 
 typedef struct {
@@ -89,6 +98,8 @@ typedef struct {
   double r_norm, s_norm;     /* ||r||_2, ||s||_2 of the last sweep                   */
   int32_t infeasible_lines;  /* line subproblems without a feasible point, last sweep */
   int32_t blocks;            /* grid size the sweeps ran with                        */
+  int32_t status;            /* 0, or ACOPF_ERR_NUMERIC / ACOPF_ERR_NONCONVEX_LINE when the
+                                scenario's QP could not be built or factored (not solved) */
 } acopf_admm_result;
 
 /* Layout of an ADMM state held by the caller (export / warm start), line-
@@ -98,15 +109,21 @@ typedef struct {
  *       xl, lam_l, rho_l [8 * n_line], index c * n_line + l; xbar_f [4 * n_line] (flow copies)
  *   per bus: dw, dth [n_bus], nu [2 * n_bus] (balance multipliers, P rows then Q rows)
  *   per line: mu [2 * n_line] (multipliers of the two limit rows in the last line solve)
- * x is the generator/line side, xbar the bus side of a coupling. */
+ * x is the generator/line side, xbar the bus side of a coupling.  A traced
+ * solve (acopf_admm_params.trace) also sums, per coupling, |r_c| = |x_c -
+ * xbar_c| and |s_c| = |rho_c (xbar_c - xbar_c of the sweep before)| over
+ * its sweeps (Section IV-B5 residuals, per coupling). */
 typedef struct {
   double *xg, *xbar_g, *lam_g, *rho_g;
   double *xl, *xbar_f, *lam_l, *rho_l;
   double *dw, *dth, *nu, *mu;
+  double *sum_r_g, *sum_s_g;   /* [2 * n_gen]  sums of |r_c|, |s_c| of the last traced solve */
+  double *sum_r_l, *sum_s_l;   /* [8 * n_line] */
 } acopf_admm_state;
 
-/* Bytes of device workspace for one grid (QP data, ADMM state, topology). */
-size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen);
+/* Bytes of device workspace for one grid or batch (QP data, ADMM state,
+ * topology, reduction scratch); 0 for invalid sizes. */
+size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen, int32_t n_scen);
 
 /* Validate the grid and build the bus incidence tables in the workspace.
  * Copies the three index arrays to the host once (synchronous).  Must be
@@ -115,7 +132,23 @@ size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen);
 acopf_status acopf_setup(const acopf_grid* grid, void* workspace, size_t workspace_bytes,
                          void* stream);
 
-/* Build the QP subproblem (QPsub) at iterate x with trust radius delta:
+/* Batched setup: scenario s owns buses [bus_offset[s], bus_offset[s+1]),
+ * lines [line_offset[s], ...) and generators [gen_offset[s], ...) of the
+ * packed arrays (host arrays of n_scen + 1 entries starting at 0 and ending
+ * at the totals), and ref_bus[s] (host, global index) is its reference bus.
+ * Lines and generators may only reference buses of their own scenario.
+ * Every later call then works on all scenarios at once, each with its own
+ * trust radius, stop test and SQP decision (a single grid is a batch of one). */
+acopf_status acopf_setup_batch(const acopf_grid* grid, const int32_t* bus_offset, const int32_t* line_offset,
+                               const int32_t* gen_offset, const int32_t* ref_bus, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* Set the per-scenario trust radii (device array of n_scen entries, > 0). */
+acopf_status acopf_set_delta(const acopf_grid* grid, const double* delta, void* workspace, void* stream);
+
+/* Build the QP subproblem (QPsub) at iterate x with trust radius delta
+ * (delta > 0: every scenario; delta == 0: each scenario's radius held in the
+ * workspace, see acopf_set_delta and acopf_sqp_step_batch):
  * elimination of d_wR, d_wI (eq. elim), line Hessian of (eq. lag) reduced
  * by A_ij (Section IV-B2; PSD-projected in ACOPF_HESSIAN_PSD mode), flow
  * map, linearised limits (opfqpc13, opfqpc14), boxes (opfqpc1-4 with the
@@ -146,7 +179,18 @@ acopf_status acopf_admm_init(const acopf_grid* grid, const double* rho_g, const 
 acopf_status acopf_admm_solve(const acopf_grid* grid, const acopf_admm_params* params,
                               void* workspace, void* stream, acopf_admm_result* result);
 
-/* Copy the last solve's result to host memory (synchronises the stream). */
+/* Per-scenario results of the last solve (host array of n_scen entries;
+ * synchronises the stream).  A scenario whose QP build met non-finite data
+ * or a vanishing pivot, or whose line matrix could not be factored, is not
+ * solved (outcome ACOPF_ADMM_FAILED, its status set); the other scenarios
+ * are unaffected.  For a single grid (n_scen <= 1) such a failure is also
+ * returned (ACOPF_ERR_NUMERIC, ACOPF_ERR_NONCONVEX_LINE); a batch returns
+ * ACOPF_OK and reports failures per scenario.  ACOPF_ERR_BARRIER is always
+ * returned. */
+acopf_status acopf_admm_result_batch(const acopf_grid* grid, void* workspace, void* stream,
+                                     acopf_admm_result* results);
+
+/* Copy the last solve's result (scenario 0) to host memory (synchronises the stream). */
 acopf_status acopf_admm_result_get(const acopf_grid* grid, void* workspace, void* stream,
                                    acopf_admm_result* result);
 
@@ -164,10 +208,18 @@ acopf_status acopf_admm_state_get(const acopf_grid* grid, void* workspace,
 acopf_status acopf_step(const acopf_grid* grid, const acopf_iterate* x, void* workspace,
                         const acopf_iterate* d, void* stream);
 
+/* Multipliers an SQP iteration's ADMM solve starts from (the primal
+ * values always start at zero). */
+typedef enum {
+  ACOPF_START_ZERO = 0,      /* all zero                                              */
+  ACOPF_START_PREVIOUS = 1,  /* the previous solve's in this workspace (zero after setup) */
+  ACOPF_START_GIVEN = 2      /* acopf_sqp_params.lam_g0 / lam_l0 (e.g. acopf_warm_decode) */
+} acopf_start;
+
 /* One iteration of the basic trust-region SQP (Section II, Algorithm 1):
  * build the QP at x with radius state->delta, solve it by ADMM (params
- * admm; warm_start = 1 starts from the multipliers of the previous solve in
- * this workspace, 0 from zero), form the step d (caller scratch in the
+ * admm, starting multipliers per warm_start, penalties rho_g, rho_l in the
+ * layout of acopf_admm_state), form the step d (caller scratch in the
  * iterate layout) and multiplier estimates, evaluate the l1 merit
  * phi_1 = f + mu h and its model q (Section II-C), accept the step iff
  * ared > 0 and pred > 0, and update the radius: doubled (up to delta_max)
@@ -180,8 +232,10 @@ typedef struct {
   double delta_max;      /* trust-radius cap                              */
   double grow_ratio;     /* radius growth threshold on ared / pred        */
   int32_t hessian_mode;  /* acopf_hessian_mode                            */
-  int32_t warm_start;    /* 1 = previous solve's multipliers, 0 = zero    */
+  int32_t warm_start;    /* acopf_start                                   */
   acopf_admm_params admm;
+  const double* lam_g0;  /* ACOPF_START_GIVEN: starting multipliers,      */
+  const double* lam_l0;  /* layout of acopf_admm_state (device)           */
 } acopf_sqp_params;
 
 typedef struct {
@@ -194,11 +248,22 @@ typedef struct {
   double merit;          /* phi_1 at the returned iterate                 */
   double admm_r, admm_s; /* final ADMM residual norms                     */
   double admm_ms;        /* duration of the ADMM sweeps (HIP events on the stream) */
+  int32_t status;        /* the scenario's acopf_admm_result.status; a failed QP
+                            counts as a rejected step (radius halved)      */
+  int32_t reserved;
 } acopf_sqp_state;
 
 acopf_status acopf_sqp_step(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
                             const double* rho_g, const double* rho_l, const acopf_sqp_params* params,
                             void* workspace, void* stream, acopf_sqp_state* state);
+
+/* The same step for every scenario of a batch, each with its own radius
+ * (held in the workspace; set it with acopf_set_delta) and its own
+ * decision.  states (host, n_scen entries) may be NULL: then nothing is
+ * copied back and the call does not synchronise the stream. */
+acopf_status acopf_sqp_step_batch(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
+                                  const double* rho_g, const double* rho_l, const acopf_sqp_params* params,
+                                  void* workspace, void* stream, acopf_sqp_state* states);
 
 /* Infeasibility report of the ACOPF (eq. acopf) at x (synchronises; host
  * result): infinity norms of the power-balance residuals, of (opfc11),
@@ -212,6 +277,59 @@ typedef struct {
 
 acopf_status acopf_residuals(const acopf_grid* grid, const acopf_iterate* x, void* workspace, void* stream,
                              acopf_residuals_report* out);
+
+/* The report per scenario of a batch (host array of n_scen entries). */
+acopf_status acopf_residuals_batch(const acopf_grid* grid, const acopf_iterate* x, void* workspace, void* stream,
+                                   acopf_residuals_report* out);
+
+/*
+ * Learned warm start (an extension: the paper starts ADMM from a fixed or
+ * the previous point).  A per-component network (acopf_mlp.h) maps local
+ * features of each line and generator at the SQP iterate to the starting
+ * multipliers of its couplings and a factor on each coupling's penalty.
+ *
+ * Line features (ACOPF_LINE_FEATURES, in order): p_d, q_d of the from bus,
+ * p_d, q_d of the to bus; g_ij, b_ij, g_ii, b_ii, g_jj, b_jj divided by 100;
+ * w_i, w_j, wR, wI; sin(th_i - th_j); smax_ij.  Generator features
+ * (ACOPF_GEN_FEATURES): p_d, q_d of its bus; cost2 / 1e4; cost1 / 1e3; pg,
+ * qg; pmax, qmax.  Outputs (ACOPF_LINE_OUTPUTS per line: 8 multipliers in
+ * coupling order divided by ACOPF_WARM_LAM_SCALE, then 8 log penalty
+ * factors; ACOPF_GEN_OUTPUTS per generator: the same for its 2 couplings).
+ * The target penalty factor of a coupling is the residual balance of a
+ * traced solve, clip(sqrt((rho sum|r_c| + ACOPF_WARM_RHO_REG) / (sum|s_c| +
+ * ACOPF_WARM_RHO_REG)), 1/ACOPF_WARM_RHO_CLIP, ACOPF_WARM_RHO_CLIP): the
+ * regulariser gives factor 1 to couplings that never move (the reference
+ * angle), whatever rounding noise their sums hold.  All feature, target and output arrays are FP32,
+ * feature-major: feature f of component c at a[f * ld + c].
+ */
+#define ACOPF_LINE_FEATURES 16
+#define ACOPF_GEN_FEATURES 8
+#define ACOPF_LINE_OUTPUTS 16
+#define ACOPF_GEN_OUTPUTS 4
+#define ACOPF_WARM_LAM_SCALE 1e3
+#define ACOPF_WARM_RHO_CLIP 10.0
+#define ACOPF_WARM_RHO_REG 1e-6
+
+/* Features of every line and generator at iterate x. */
+acopf_status acopf_features(const acopf_grid* grid, const acopf_iterate* x, float* line_x, int64_t ld_line,
+                            float* gen_x, int64_t ld_gen, void* stream);
+
+/* Training targets from the last solve in the workspace: its final
+ * multipliers and, from its trace sums (a solve with trace = 1), the
+ * target log penalty factors. */
+acopf_status acopf_warm_targets(const acopf_grid* grid, void* workspace, float* line_t, int64_t ld_line,
+                                float* gen_t, int64_t ld_gen, void* stream);
+
+/* Starting point from network outputs: multipliers lam = y *
+ * ACOPF_WARM_LAM_SCALE; penalties rho0 exp(y) with y clipped to
+ * +-log(ACOPF_WARM_RHO_CLIP) if use_rho, else rho0 (rho_l0 for lines, rho_g0
+ * for generators, > 0).  A non-finite output keeps the plain start of its
+ * coupling: the multiplier held in the workspace (the previous solve's) or
+ * the base penalty.  Outputs (device, layout of acopf_admm_state) feed
+ * acopf_admm_init or acopf_sqp_step with ACOPF_START_GIVEN. */
+acopf_status acopf_warm_decode(const acopf_grid* grid, void* workspace, const float* line_y, int64_t ld_line,
+                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t use_rho,
+                               double* lam_l, double* lam_g, double* rho_l, double* rho_g, void* stream);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libacopf_admm.so")
-SOURCES = [os.path.join(HERE, "csrc", "acopf_admm.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "acopf_admm.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

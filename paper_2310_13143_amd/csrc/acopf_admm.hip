@@ -4,11 +4,15 @@
 // One thread per component: the line update (the only non-closed-form
 // subproblem) runs one 4-variable QP per lane; buses gather the couplings of
 // their incident line ends and generators through CSR tables.  A sweep is
-// phase A (lines) -> grid barrier -> phase B (generators, buses,
-// multipliers, residual partials) -> grid barrier, the last block to arrive
-// summing the partials in a fixed order and deciding the stop.  The
-// persistent kernel keeps every block resident for all sweeps; the
-// "launches" mode runs the same phases as three kernels per sweep.
+// phase A (lines) -> phase B (generators, buses, multipliers, residual
+// partials) -> sweep end (fixed-order sums of the partials, stop test).
+//
+// A batch packs independent scenarios one after another.  In the
+// launch-per-phase mode every block of a phase belongs to one scenario (a
+// block table built on the device), so block partials are per scenario and
+// each scenario stops on its own residuals; blocks of stopped scenarios exit
+// at once.  The persistent mode (one cooperative launch for all sweeps, grid
+// barriers between phases) serves a single scenario.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,27 +22,28 @@
 #include <vector>
 
 #include "components.h"
+#include "errors.h"
 
 using namespace acopf;
 
-namespace {
-
-thread_local std::string g_last_error = "no error";
-
-acopf_status fail(acopf_status s, const std::string& msg) {
-  g_last_error = msg;
-  return s;
+std::string& acopf::last_error() {
+  thread_local std::string msg = "no error";
+  return msg;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t _e = (expr);                                                            \
-    if (_e != hipSuccess)                                                              \
-      return fail(ACOPF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));    \
-  } while (0)
+namespace {
 
 constexpr int kDefaultBlock = 256;
 constexpr long long kSpinLimit = 1LL << 25;
+// Largest single-scenario bus-phase grid whose last block also ends the sweep.
+constexpr int kFoldMaxBlocks = 64;
+// Sweeps enqueued between two looks at the stop flag (launch mode).
+constexpr int kSweepChunk = 64;
+// Learned warm start: multiplier scale and penalty-factor clip of the
+// network's outputs.
+constexpr double kLamScale = ACOPF_WARM_LAM_SCALE;
+constexpr double kRhoClip = ACOPF_WARM_RHO_CLIP;
+constexpr double kRhoReg = ACOPF_WARM_RHO_REG;
 
 __device__ __forceinline__ int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gstride() { return gridDim.x * blockDim.x; }
@@ -57,14 +62,68 @@ __device__ double block_sum(double v, double* lds) {
   return t;
 }
 
-// ---------------------------------------------------------------- QP build
-__global__ void k_build_lines(acopf_grid g, acopf_iterate x, double delta, int mode, Workspace w) {
-  for (int l = gtid(); l < g.n_line; l += gstride())
-    if (!build_line(g, x, delta, mode, w, l)) atomicAdd(&w.sync->numeric_error, 1);
+__device__ double block_max(double v, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int k = 0; k < nw; ++k) m = fmax(m, lds[k]);
+  __syncthreads();
+  return m;
 }
 
-__global__ void k_build_gens(acopf_grid g, acopf_iterate x, double delta, Workspace w) {
-  for (int k = gtid(); k < g.n_gen; k += gstride()) build_gen(g, x, delta, w, k);
+// Scenario owning block b of a phase whose per-scenario first blocks are
+// blk_off[0..ns]; -1 past the last block.
+__device__ __forceinline__ int scen_of_block(const int32_t* blk_off, int ns, int b) {
+  if (b >= blk_off[ns]) return -1;
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Scenario owning component i of a kind whose per-scenario first indices are
+// off[0..ns] (binary search).
+__device__ __forceinline__ int scen_of_index(const int32_t* off, int ns, int i) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A failed QP build or factorisation of a line marks its scenario (the
+// most negative status wins) and the batch-wide flag.
+__device__ void fail_line(const Workspace& w, int l, int status, int* flag) {
+  atomicAdd(flag, 1);
+  atomicMin(&w.scen[scen_of_index(w.scen_line_off, w.n_scen, l)].status, status);
+}
+
+// ---------------------------------------------------------------- QP build
+__global__ void k_set_delta(Workspace w, double delta) {
+  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].delta = delta;
+}
+
+__global__ void k_copy_delta(Workspace w, const double* delta) {
+  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].delta = delta[s];
+}
+
+__global__ void k_build_lines(acopf_grid g, acopf_iterate x, int mode, Workspace w) {
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    const double delta = w.scen[w.bus_scen[g.line_from[l]]].delta;
+    if (!build_line(g, x, delta, mode, w, l)) fail_line(w, l, ACOPF_ERR_NUMERIC, &w.sync->numeric_error);
+  }
+}
+
+__global__ void k_build_gens(acopf_grid g, acopf_iterate x, Workspace w) {
+  for (int k = gtid(); k < g.n_gen; k += gstride())
+    build_gen(g, x, w.scen[w.bus_scen[g.gen_bus[k]]].delta, w, k);
 }
 
 __global__ void k_build_buses(acopf_grid g, acopf_iterate x, Workspace w) {
@@ -86,26 +145,7 @@ __global__ void k_copy(double* dst, const double* src, long long n) {
 
 __global__ void k_prep_lines(Workspace w) {
   for (int l = gtid(); l < w.n_line; l += gstride())
-    if (!prep_line(w, l)) atomicAdd(&w.sync->nonconvex, 1);
-}
-
-__global__ void k_reset_sync(Workspace w, int blocks) {
-  for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
-  if (gtid() == 0) {
-    SyncState* s = w.sync;
-    s->go = 0u;
-    s->converged = 0;
-    s->blocks = blocks;
-    s->count = 0;
-    s->gen = 0;
-    s->done = 0;
-    s->sweeps = 0;
-    s->barrier_error = 0;
-    s->infeasible[0] = 0;
-    s->infeasible[1] = 0;
-    s->r_norm = 0.0;
-    s->s_norm = 0.0;
-  }
+    if (!prep_line(w, l)) fail_line(w, l, ACOPF_ERR_NONCONVEX_LINE, &w.sync->nonconvex);
 }
 
 __global__ void k_clear_flags(Workspace w) {
@@ -113,65 +153,128 @@ __global__ void k_clear_flags(Workspace w) {
     w.sync->numeric_error = 0;
     w.sync->nonconvex = 0;
   }
+  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].status = 0;
 }
 
-// ---------------------------------------------------------------- sweeps
-__device__ __forceinline__ void phase_lines(const acopf_grid& g, const Workspace& w, int* infeasible) {
-  for (int l = gtid(); l < g.n_line; l += gstride())
-    if (update_line(g, w, l) != 0) atomicAdd(infeasible, 1);
-}
-
-__device__ __forceinline__ void phase_buses(const acopf_grid& g, const Workspace& w, double* lds) {
-  double r2 = 0.0, s2 = 0.0;
-  for (int i = gtid(); i < g.n_bus; i += gstride()) update_bus(g, w, i, r2, s2);
-  r2 = block_sum(r2, lds);
-  s2 = block_sum(s2, lds);
-  if (threadIdx.x == 0) {
-    w.partials[blockIdx.x] = r2;
-    w.partials[w.max_partials + blockIdx.x] = s2;
+// Start of a solve: per-scenario stop state, barrier flags, block tables of
+// both phases for block size bs.
+__global__ void k_reset_solve(Workspace w, int blocks, int bs) {
+  for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
+  for (int s = gtid(); s < w.n_scen; s += gstride()) {
+    ScenState* sc = &w.scen[s];
+    sc->done = sc->status != 0 ? 1 : 0;  // a failed QP is not solved
+    sc->sweeps = 0;
+    sc->converged = 0;
+    sc->infeasible[0] = 0;
+    sc->infeasible[1] = 0;
+    sc->r_norm = 0.0;
+    sc->s_norm = 0.0;
+  }
+  if (gtid() == 0) {
+    SyncState* sy = w.sync;
+    int failed = 0;
+    for (int s = 0; s < w.n_scen; ++s) failed += w.scen[s].status != 0 ? 1 : 0;
+    sy->count = 0;
+    sy->go = 0u;
+    sy->done = failed == w.n_scen ? 1 : 0;
+    sy->n_done = failed;
+    sy->barrier_error = 0;
+    sy->blocks = blocks;
+    int lb = 0, bb = 0;
+    for (int s = 0; s < w.n_scen; ++s) {
+      w.line_blk_off[s] = lb;
+      w.bus_blk_off[s] = bb;
+      lb += (w.scen_line_off[s + 1] - w.scen_line_off[s] + bs - 1) / bs;
+      bb += (w.scen_bus_off[s + 1] - w.scen_bus_off[s] + bs - 1) / bs;
+    }
+    w.line_blk_off[w.n_scen] = lb;
+    w.bus_blk_off[w.n_scen] = bb;
   }
 }
 
-// Sum of the per-block partials (fixed order), stop decision, sweep count.
-__device__ void finish_sweep(const Workspace& w, int nparts, int max_sweeps, double eps_pri,
-                             double eps_dual, double* lds) {
+// ---------------------------------------------------------------- sweeps
+// Sum of scenario s's partials [p0, p1) (fixed order), stop decision.
+__device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int max_sweeps, double eps_pri,
+                                double eps_dual, double* lds) {
   double r2 = 0.0, s2 = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+  for (int b = p0 + (int)threadIdx.x; b < p1; b += blockDim.x) {
     r2 += w.partials[b];
     s2 += w.partials[w.max_partials + b];
   }
   r2 = block_sum(r2, lds);
   s2 = block_sum(s2, lds);
   if (threadIdx.x == 0) {
-    SyncState* s = w.sync;
-    const int k = s->sweeps + 1;
-    s->sweeps = k;
+    ScenState* sc = &w.scen[s];
+    const int k = sc->sweeps + 1;
+    sc->sweeps = k;
     const double r = sqrt(r2), sn = sqrt(s2);
-    s->r_norm = r;
-    s->s_norm = sn;
+    sc->r_norm = r;
+    sc->s_norm = sn;
     const bool conv = (eps_pri > 0.0 || eps_dual > 0.0) && r <= eps_pri && sn <= eps_dual;
-    s->converged = conv ? 1 : 0;
-    s->done = (conv || k >= max_sweeps || s->barrier_error) ? 1 : 0;
-    s->infeasible[k & 1] = 0;  // counter of the next sweep
+    sc->converged = conv ? 1 : 0;
+    sc->infeasible[k & 1] = 0;  // counter of the next sweep
+    if (conv || k >= max_sweeps || w.sync->barrier_error) {
+      sc->done = 1;
+      if (atomicAdd(&w.sync->n_done, 1) + 1 == w.n_scen) w.sync->done = 1;
+    }
   }
 }
 
+__device__ __forceinline__ bool batch_done(const Workspace& w) {
+  return __hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 __global__ void __launch_bounds__(256) k_line_phase(acopf_grid g, Workspace w) {
-  if (__hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const int k = w.sync->sweeps;
-  phase_lines(g, w, &w.sync->infeasible[k & 1]);
+  if (batch_done(w)) return;
+  const int s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
+  if (s < 0 || w.scen[s].done) return;
+  const int l = w.scen_line_off[s] + (blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x;
+  if (l < w.scen_line_off[s + 1] && update_line(g, w, l) != 0)
+    atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
-__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w) {
+// Bus phase of the launch-per-phase mode.  With `fold` (a single scenario
+// with a small grid) the last block to finish, by atomic ticket, ends the
+// sweep; each block then pays a device-scope fence, which only pays off for
+// small grids.  Otherwise k_finish_phase ends the sweep as a third launch.
+template <bool kTrace>
+__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w, int fold, int max_sweeps,
+                                                   double eps_pri, double eps_dual) {
   __shared__ double lds[16];
-  if (__hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  phase_buses(g, w, lds);
+  __shared__ int s_last;
+  if (batch_done(w)) return;
+  const int s = scen_of_block(w.bus_blk_off, w.n_scen, blockIdx.x);
+  if (s < 0 || w.scen[s].done) return;
+  const int i = w.scen_bus_off[s] + (blockIdx.x - w.bus_blk_off[s]) * blockDim.x + threadIdx.x;
+  double r2 = 0.0, s2 = 0.0;
+  if (i < w.scen_bus_off[s + 1]) update_bus<kTrace>(g, w, i, r2, s2);
+  r2 = block_sum(r2, lds);
+  s2 = block_sum(s2, lds);
+  if (threadIdx.x == 0) {
+    w.partials[blockIdx.x] = r2;
+    w.partials[w.max_partials + blockIdx.x] = s2;
+  }
+  if (!fold) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int ticket = atomicAdd(&w.sync->count, 1u);
+    s_last = (ticket == (unsigned int)w.bus_blk_off[w.n_scen] - 1u) ? 1 : 0;
+    if (s_last) __threadfence();
+  }
+  __syncthreads();
+  if (s_last) {
+    finish_scenario(w, 0, 0, w.bus_blk_off[1], max_sweeps, eps_pri, eps_dual, lds);
+    if (threadIdx.x == 0) w.sync->count = 0;
+  }
 }
 
-__global__ void k_finish_phase(Workspace w, int nparts, int max_sweeps, double eps_pri, double eps_dual) {
+// One block per scenario.
+__global__ void k_finish_phase(Workspace w, int max_sweeps, double eps_pri, double eps_dual) {
   __shared__ double lds[16];
-  if (w.sync->done) return;
-  finish_sweep(w, nparts, max_sweeps, eps_pri, eps_dual, lds);
+  const int s = blockIdx.x;
+  if (w.sync->done || w.scen[s].done) return;
+  finish_scenario(w, s, w.bus_blk_off[s], w.bus_blk_off[s + 1], max_sweeps, eps_pri, eps_dual, lds);
 }
 
 // Grid barrier for a cooperative launch (all blocks resident).  Each block
@@ -204,7 +307,6 @@ __device__ void grid_barrier(const Workspace& w, unsigned int epoch, F&& last) {
     __syncthreads();
     return;
   }
-  // block 0: wait for every other block
   for (unsigned int b = 1 + threadIdx.x; b < gridDim.x; b += blockDim.x) {
     long long spins = 0;
     while (__hip_atomic_load(&w.arrive[b * kArriveStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -227,16 +329,27 @@ __device__ void grid_barrier(const Workspace& w, unsigned int epoch, F&& last) {
   __syncthreads();
 }
 
+// Persistent sweep loop of a single scenario.
 __global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspace w, int max_sweeps,
                                                           double eps_pri, double eps_dual) {
   __shared__ double lds[16];
   __shared__ int s_stop;
   SyncState* sy = w.sync;
+  ScenState* sc = &w.scen[0];
+  if (__hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;  // failed QP: same for all blocks
   for (int k = 0; k < max_sweeps; ++k) {
-    phase_lines(g, w, &sy->infeasible[k & 1]);
+    for (int l = gtid(); l < g.n_line; l += gstride())
+      if (update_line(g, w, l) != 0) atomicAdd(&sc->infeasible[k & 1], 1);
     grid_barrier(w, 2u * k + 1u, [] {});
-    phase_buses(g, w, lds);
-    grid_barrier(w, 2u * k + 2u, [&] { finish_sweep(w, gridDim.x, max_sweeps, eps_pri, eps_dual, lds); });
+    double r2 = 0.0, s2 = 0.0;
+    for (int i = gtid(); i < g.n_bus; i += gstride()) update_bus(g, w, i, r2, s2);
+    r2 = block_sum(r2, lds);
+    s2 = block_sum(s2, lds);
+    if (threadIdx.x == 0) {
+      w.partials[blockIdx.x] = r2;
+      w.partials[w.max_partials + blockIdx.x] = s2;
+    }
+    grid_barrier(w, 2u * k + 2u, [&] { finish_scenario(w, 0, 0, gridDim.x, max_sweeps, eps_pri, eps_dual, lds); });
     if (threadIdx.x == 0) {
       const int done = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int berr = __hip_atomic_load(&sy->barrier_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -264,183 +377,166 @@ __global__ void k_step_nodes(acopf_grid g, Workspace w, acopf_iterate d) {
 }
 
 // ---------------------------------------------------------------- SQP step
-// Block-wise sums of the merit pieces and the maximum step component.
-__global__ void __launch_bounds__(256) k_merit(acopf_grid g, acopf_iterate x, Workspace w, acopf_iterate d) {
-  __shared__ double lds[16];
-  double acc[kMeritFields];
-#pragma unroll
-  for (int k = 0; k < kMeritFields; ++k) acc[k] = 0.0;
-  for (int l = gtid(); l < g.n_line; l += gstride()) {
+// Per-component merit pieces: lines (h at x, h at x + d, m(d), model
+// quadratic), generators (f at x, f at x + d, model terms, |step|), buses
+// (|step|).
+__global__ void k_merit_parts(acopf_grid g, acopf_iterate x, Workspace w, acopf_iterate d) {
+  const int L = g.n_line, G = g.n_gen;
+  for (int l = gtid(); l < L; l += gstride()) {
     double o[4];
     merit_line(g, x, w, d, l, o);
-    acc[3] += o[0];
-    acc[4] += o[1];
-    acc[5] += o[2];
-    acc[6] += o[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w.line_comp[k * L + l] = o[k];
   }
-  double smax = 0.0;
-  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+  for (int k = gtid(); k < G; k += gstride()) {
     double o[3];
     merit_gen(g, x, d, k, o);
-    acc[0] += o[0];
-    acc[1] += o[1];
-    acc[2] += o[2];
-    smax = fmax(smax, fmax(fabs(d.pg[k]), fabs(d.qg[k])));
+    w.gen_comp[k] = o[0];
+    w.gen_comp[G + k] = o[1];
+    w.gen_comp[2 * G + k] = o[2];
+    w.gen_comp[3 * G + k] = fmax(fabs(d.pg[k]), fabs(d.qg[k]));
   }
-  for (int i = gtid(); i < g.n_bus; i += gstride()) smax = fmax(smax, fmax(fabs(d.w[i]), fabs(d.th[i])));
-#pragma unroll
-  for (int k = 0; k < kMeritFields - 1; ++k) acc[k] = block_sum(acc[k], lds);
-  // block maximum of the step (order independent)
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = smax;
-  __syncthreads();
-  double m = 0.0;
-  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kMeritFields - 1; ++k) w.merit_partials[k * w.max_partials + blockIdx.x] = acc[k];
-    w.merit_partials[(kMeritFields - 1) * w.max_partials + blockIdx.x] = m;
-  }
+  for (int i = gtid(); i < g.n_bus; i += gstride()) w.bus_comp[i] = fmax(fabs(d.w[i]), fabs(d.th[i]));
 }
 
-// Acceptance test and trust-radius update of Algorithm 1 (one block).
-__global__ void k_decide(Workspace w, int nparts, double mu, double delta, double delta_max, double grow) {
+// Acceptance test and trust-radius update of Algorithm 1, one block per
+// scenario (fixed-order sums over the scenario's components).
+__global__ void k_decide(Workspace w, double mu, double delta_max, double grow) {
   __shared__ double lds[16];
-  double acc[kMeritFields];
-#pragma unroll
-  for (int k = 0; k < kMeritFields; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < kMeritFields - 1; ++k) acc[k] += w.merit_partials[k * w.max_partials + b];
-    acc[kMeritFields - 1] = fmax(acc[kMeritFields - 1], w.merit_partials[(kMeritFields - 1) * w.max_partials + b]);
+  const int s = blockIdx.x, L = w.n_line, G = w.n_gen;
+  const int l0 = w.scen_line_off[s], l1 = w.scen_line_off[s + 1];
+  const int g0 = w.scen_gen_off[s], g1 = w.scen_gen_off[s + 1];
+  const int b0 = w.scen_bus_off[s], b1 = w.scen_bus_off[s + 1];
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  double smax = 0.0;
+  for (int l = l0 + (int)threadIdx.x; l < l1; l += blockDim.x) {
+    a[3] += w.line_comp[l];
+    a[4] += w.line_comp[L + l];
+    a[5] += w.line_comp[2 * L + l];
+    a[6] += w.line_comp[3 * L + l];
   }
+  for (int k = g0 + (int)threadIdx.x; k < g1; k += blockDim.x) {
+    a[0] += w.gen_comp[k];
+    a[1] += w.gen_comp[G + k];
+    a[2] += w.gen_comp[2 * G + k];
+    smax = fmax(smax, w.gen_comp[3 * G + k]);
+  }
+  for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) smax = fmax(smax, w.bus_comp[i]);
 #pragma unroll
-  for (int k = 0; k < kMeritFields - 1; ++k) acc[k] = block_sum(acc[k], lds);
-  double smax = acc[kMeritFields - 1];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = smax;
-  __syncthreads();
-  double m = 0.0;
-  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
+  for (int k = 0; k < 7; ++k) a[k] = block_sum(a[k], lds);
+  smax = block_max(smax, lds);
   if (threadIdx.x == 0) {
-    SqpDecision* dc = w.decision;
-    dc->f_x = acc[0];
-    dc->f_xd = acc[1];
-    dc->h_x = acc[3];
-    dc->h_xd = acc[4];
-    dc->m_d = acc[5];
-    dc->quad = acc[2] + acc[6];
-    const double ared = (acc[0] + mu * acc[3]) - (acc[1] + mu * acc[4]);
-    const double pred = -(acc[2] + acc[6]) + mu * (acc[3] - acc[5]);
+    SqpDecision* dc = &w.decision[s];
+    const double delta = w.scen[s].delta;
+    dc->f_x = a[0];
+    dc->f_xd = a[1];
+    dc->h_x = a[3];
+    dc->h_xd = a[4];
+    dc->m_d = a[5];
+    dc->quad = a[2] + a[6];
+    const double ared = (a[0] + mu * a[3]) - (a[1] + mu * a[4]);
+    const double pred = -(a[2] + a[6]) + mu * (a[3] - a[5]);
     dc->ared = ared;
     dc->pred = pred;
-    dc->step_inf = m;
+    dc->step_inf = smax;
     dc->delta_in = delta;
-    const bool acc_ok = ared > 0.0 && pred > 0.0;
+    const bool failed = w.scen[s].status != 0;
+    const bool ok = !failed && ared > 0.0 && pred > 0.0;
     double dn = delta;
-    if (acc_ok) {
-      if (m >= 0.99 * delta && ared >= grow * pred) dn = fmin(2.0 * delta, delta_max);
+    if (ok) {
+      if (smax >= 0.99 * delta && ared >= grow * pred) dn = fmin(2.0 * delta, delta_max);
+    } else if (failed) {
+      dn = 0.5 * delta;  // a QP that could not be built or factored counts as a rejected step
     } else {
-      dn = 0.5 * fmin(delta, m);
+      dn = 0.5 * fmin(delta, smax);
     }
     dc->delta_out = dn;
-    dc->accepted = acc_ok ? 1 : 0;
+    dc->accepted = ok ? 1 : 0;
+    w.scen[s].delta = dn;
   }
 }
 
-// x <- x + d and pi <- new estimates, if the step was accepted.
+// x <- x + d and pi <- new estimates in every scenario whose step was accepted.
 __global__ void k_apply(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspace w) {
-  if (!w.decision->accepted) return;
+  const int L = g.n_line;
   for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    if (!w.decision[w.bus_scen[g.gen_bus[k]]].accepted) continue;
     x.pg[k] += d.pg[k];
     x.qg[k] += d.qg[k];
   }
   for (int i = gtid(); i < g.n_bus; i += gstride()) {
+    if (!w.decision[w.bus_scen[i]].accepted) continue;
     x.w[i] += d.w[i];
     x.th[i] += d.th[i];
   }
-  for (int l = gtid(); l < g.n_line; l += gstride()) {
+  for (int l = gtid(); l < L; l += gstride()) {
+    if (!w.decision[w.bus_scen[g.line_from[l]]].accepted) continue;
     x.wR[l] += d.wR[l];
     x.wI[l] += d.wI[l];
-    x.pi[l] = d.pi[l];
-    x.pi[g.n_line + l] = d.pi[g.n_line + l];
-    x.pi[2 * g.n_line + l] = d.pi[2 * g.n_line + l];
-    x.pi[3 * g.n_line + l] = d.pi[3 * g.n_line + l];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x.pi[k * L + l] = d.pi[k * L + l];
   }
 }
 
 // ---------------------------------------------------------------- residuals
-__device__ double block_max(double v, double* lds) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double m = 0.0;
-  for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) m = fmax(m, lds[k]);
-  __syncthreads();
-  return m;
-}
-
-__global__ void __launch_bounds__(256) k_residuals(acopf_grid g, acopf_iterate x, Workspace w) {
-  __shared__ double lds[16];
-  double acc[kResidFields];
-#pragma unroll
-  for (int k = 0; k < kResidFields; ++k) acc[k] = 0.0;
-  for (int l = gtid(); l < g.n_line; l += gstride()) {
+__global__ void k_residual_parts(acopf_grid g, acopf_iterate x, Workspace w) {
+  const int L = g.n_line, G = g.n_gen, B = g.n_bus;
+  for (int l = gtid(); l < L; l += gstride()) {
     double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
     residual_line(g, x, w, l, pr, du);
-    acc[1] = fmax(acc[1], pr[1]);
-    acc[2] = fmax(acc[2], pr[2]);
-    acc[3] = fmax(acc[3], pr[3]);
-    acc[5] = fmax(acc[5], du);
+    w.line_comp[l] = pr[1];
+    w.line_comp[L + l] = pr[2];
+    w.line_comp[2 * L + l] = pr[3];
+    w.line_comp[3 * L + l] = du;
   }
-  for (int i = gtid(); i < g.n_bus; i += gstride()) {
+  for (int i = gtid(); i < B; i += gstride()) {
     double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;
     residual_bus(g, x, w, i, pr, du);
-    acc[0] = fmax(acc[0], pr[0]);
-    acc[4] = fmax(acc[4], pr[4]);
-    acc[5] = fmax(acc[5], du);
+    w.bus_comp[i] = pr[0];
+    w.bus_comp[B + i] = pr[4];
+    w.bus_comp[2 * B + i] = du;
   }
-  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+  for (int k = gtid(); k < G; k += gstride()) {
     double bnd, du, gf;
     residual_gen(g, x, w, k, bnd, du, gf);
-    acc[4] = fmax(acc[4], bnd);
-    acc[5] = fmax(acc[5], du);
-    acc[6] = fmax(acc[6], gf);
-  }
-#pragma unroll
-  for (int k = 0; k < kResidFields; ++k) acc[k] = block_max(acc[k], lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kResidFields; ++k) w.resid_partials[k * w.max_partials + blockIdx.x] = acc[k];
+    w.gen_comp[k] = bnd;
+    w.gen_comp[G + k] = du;
+    w.gen_comp[2 * G + k] = gf;
   }
 }
 
-__global__ void k_residuals_final(Workspace w, int nparts) {
+// One block per scenario: maxima over the scenario's components.
+__global__ void k_residual_reduce(Workspace w) {
   __shared__ double lds[16];
-  double acc[kResidFields];
-#pragma unroll
-  for (int k = 0; k < kResidFields; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < kResidFields; ++k) acc[k] = fmax(acc[k], w.resid_partials[k * w.max_partials + b]);
+  const int s = blockIdx.x, L = w.n_line, G = w.n_gen, B = w.n_bus;
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};  // balance, c11, c12, limit, bounds, dual, gradf
+  for (int l = w.scen_line_off[s] + (int)threadIdx.x; l < w.scen_line_off[s + 1]; l += blockDim.x) {
+    a[1] = fmax(a[1], w.line_comp[l]);
+    a[2] = fmax(a[2], w.line_comp[L + l]);
+    a[3] = fmax(a[3], w.line_comp[2 * L + l]);
+    a[5] = fmax(a[5], w.line_comp[3 * L + l]);
+  }
+  for (int i = w.scen_bus_off[s] + (int)threadIdx.x; i < w.scen_bus_off[s + 1]; i += blockDim.x) {
+    a[0] = fmax(a[0], w.bus_comp[i]);
+    a[4] = fmax(a[4], w.bus_comp[B + i]);
+    a[5] = fmax(a[5], w.bus_comp[2 * B + i]);
+  }
+  for (int k = w.scen_gen_off[s] + (int)threadIdx.x; k < w.scen_gen_off[s + 1]; k += blockDim.x) {
+    a[4] = fmax(a[4], w.gen_comp[k]);
+    a[5] = fmax(a[5], w.gen_comp[G + k]);
+    a[6] = fmax(a[6], w.gen_comp[2 * G + k]);
   }
 #pragma unroll
-  for (int k = 0; k < kResidFields; ++k) acc[k] = block_max(acc[k], lds);
+  for (int k = 0; k < 7; ++k) a[k] = block_max(a[k], lds);
   if (threadIdx.x == 0) {
-    ResidualReport* r = w.report;
-    r->balance = acc[0];
-    r->c11 = acc[1];
-    r->c12 = acc[2];
-    r->limit = acc[3];
-    r->bounds = acc[4];
-    r->dual = acc[5];
-    r->gradf = acc[6];
+    ResidualReport* r = &w.report[s];
+    r->balance = a[0];
+    r->c11 = a[1];
+    r->c12 = a[2];
+    r->limit = a[3];
+    r->bounds = a[4];
+    r->dual = a[5];
+    r->gradf = a[6];
   }
 }
 
@@ -457,6 +553,7 @@ struct EventPair {
     if (b) (void)hipEventDestroy(b);
   }
 };
+
 int blocks_for(long long n, int bs) {
   long long b = (n + bs - 1) / bs;
   if (b < 1) b = 1;
@@ -464,11 +561,88 @@ int blocks_for(long long n, int bs) {
   return (int)b;
 }
 
+// ---------------------------------------------------------------- learned warm start
+// Features of every line and generator (FP32, feature-major with leading
+// dimensions ldl, ldg).
+__global__ void k_features(acopf_grid g, acopf_iterate x, float* fl, long long ldl, float* fg, long long ldg) {
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    const int i = g.line_from[l], j = g.line_to[l];
+    const double v[ACOPF_LINE_FEATURES] = {g.pd[i], g.qd[i], g.pd[j], g.qd[j],
+                                           g.gij[l] / 100.0, g.bij[l] / 100.0, g.gii[l] / 100.0, g.bii[l] / 100.0,
+                                           g.gjj[l] / 100.0, g.bjj[l] / 100.0, x.w[i], x.w[j], x.wR[l], x.wI[l],
+                                           sin(x.th[i] - x.th[j]), g.smax_ij[l]};
+#pragma unroll
+    for (int f = 0; f < ACOPF_LINE_FEATURES; ++f) fl[f * ldl + l] = (float)v[f];
+  }
+  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    const int b = g.gen_bus[k];
+    const double v[ACOPF_GEN_FEATURES] = {g.pd[b], g.qd[b], g.cost2[k] / 1e4, g.cost1[k] / 1e3,
+                                          x.pg[k], x.qg[k], g.pmax[k], g.qmax[k]};
+#pragma unroll
+    for (int f = 0; f < ACOPF_GEN_FEATURES; ++f) fg[f * ldg + k] = (float)v[f];
+  }
+}
+
+// log clip(sqrt((rho sum_r + reg) / (sum_s + reg)), 1 / clip, clip).
+__device__ double log_rho_factor(double rho, double sum_r, double sum_s) {
+  const double fac = sqrt((rho * sum_r + kRhoReg) / (sum_s + kRhoReg));
+  return log(fmin(fmax(fac, 1.0 / kRhoClip), kRhoClip));
+}
+
+__global__ void k_targets(Workspace w, float* tl, long long ldl, float* tg, long long ldg) {
+  const int L = w.n_line, G = w.n_gen;
+  for (int l = gtid(); l < L; l += gstride()) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int q = c * L + l;
+      tl[c * ldl + l] = (float)(w.lam_l[q] / kLamScale);
+      tl[(8 + c) * ldl + l] = (float)log_rho_factor(w.rho_l[q], w.tr_r_l[q], w.tr_s_l[q]);
+    }
+  }
+  for (int k = gtid(); k < G; k += gstride()) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = c * G + k;
+      tg[c * ldg + k] = (float)(w.lam_g[q] / kLamScale);
+      tg[(2 + c) * ldg + k] = (float)log_rho_factor(w.rho_g[q], w.tr_r_g[q], w.tr_s_g[q]);
+    }
+  }
+}
+
+// ADMM start from network outputs; a non-finite output keeps the plain
+// start of its coupling (the workspace's multiplier, the base penalty).
+__global__ void k_decode(Workspace w, const float* yl, long long ldl, const float* yg, long long ldg, double rho_l0,
+                         double rho_g0, int use_rho, double* lam_l, double* lam_g, double* rho_l, double* rho_g) {
+  const int L = w.n_line, G = w.n_gen;
+  const double lmax = log(kRhoClip);
+  for (int l = gtid(); l < L; l += gstride()) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int q = c * L + l;
+      const double a = (double)yl[c * ldl + l] * kLamScale;
+      lam_l[q] = isfinite(a) ? a : w.lam_l[q];
+      const double o = (double)yl[(8 + c) * ldl + l];
+      rho_l[q] = (use_rho && isfinite(o)) ? rho_l0 * exp(fmin(fmax(o, -lmax), lmax)) : rho_l0;
+    }
+  }
+  for (int k = gtid(); k < G; k += gstride()) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = c * G + k;
+      const double a = (double)yg[c * ldg + k] * kLamScale;
+      lam_g[q] = isfinite(a) ? a : w.lam_g[q];
+      const double o = (double)yg[(2 + c) * ldg + k];
+      rho_g[q] = (use_rho && isfinite(o)) ? rho_g0 * exp(fmin(fmax(o, -lmax), lmax)) : rho_g0;
+    }
+  }
+}
+
+int n_scen_of(const acopf_grid* g) { return g->n_scen > 1 ? g->n_scen : 1; }
+
 bool grid_ok(const acopf_grid* g) {
-  return g && g->n_bus > 0 && g->n_line > 0 && g->n_gen >= 0 && g->ref_bus >= 0 &&
-         g->ref_bus < g->n_bus && g->vmin && g->vmax && g->pd && g->qd && g->gsh && g->bsh &&
-         g->line_from && g->line_to && g->gii && g->bii && g->gij && g->bij && g->gji && g->bji &&
-         g->gjj && g->bjj && g->smax_ij && g->smax_ji &&
+  return g && g->n_bus > 0 && g->n_line > 0 && g->n_gen >= 0 && g->n_scen >= 0 && n_scen_of(g) <= g->n_bus &&
+         g->vmin && g->vmax && g->pd && g->qd && g->gsh && g->bsh && g->line_from && g->line_to && g->gii &&
+         g->bii && g->gij && g->bij && g->gji && g->bji && g->gjj && g->bjj && g->smax_ij && g->smax_ji &&
          (g->n_gen == 0 || (g->gen_bus && g->pmin && g->pmax && g->qmin && g->qmax && g->cost2 && g->cost1));
 }
 
@@ -478,54 +652,59 @@ bool iterate_ok(const acopf_iterate* x) {
 
 Workspace ws_of(const acopf_grid* g, void* base) {
   Workspace w;
-  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, &w);
+  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, n_scen_of(g), &w);
   return w;
 }
 
-acopf_status read_sync(void* ws_base, const acopf_grid* g, hipStream_t s, SyncState* out) {
-  Workspace w = ws_of(g, ws_base);
+acopf_status read_sync(const Workspace& w, hipStream_t s, SyncState* out) {
   HIP_TRY(hipMemcpyAsync(out, w.sync, sizeof(SyncState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return ACOPF_OK;
 }
 
-}  // namespace
-
-// ================================================================== C ABI
-extern "C" {
-
-const char* acopf_last_error(void) { return g_last_error.c_str(); }
-
-size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen) {
-  if (n_bus <= 0 || n_line <= 0 || n_gen < 0) return 0;
-  return layout_workspace(nullptr, n_bus, n_line, n_gen, nullptr);
-}
-
-acopf_status acopf_setup(const acopf_grid* g, void* workspace, size_t bytes, void* stream) {
-  if (!grid_ok(g)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: incomplete grid description");
-  if (!workspace) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: null workspace");
-  const size_t need = acopf_workspace_bytes(g->n_bus, g->n_line, g->n_gen);
+acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int32_t* line_off_h,
+                        const int32_t* gen_off_h, const int32_t* ref_h, void* workspace, size_t bytes,
+                        void* stream) {
+  const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen, ns = n_scen_of(g);
+  const size_t need = layout_workspace(nullptr, nb, nl, ng, ns, nullptr);
   if (bytes < need)
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: workspace of " + std::to_string(bytes) +
-                                           " bytes, need " + std::to_string(need));
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: workspace of " + std::to_string(bytes) + " bytes, need " +
+                                           std::to_string(need));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
+  // scenario tables
+  for (int k = 0; k < ns; ++k) {
+    if (bus_off_h[k + 1] <= bus_off_h[k] || line_off_h[k + 1] <= line_off_h[k] || gen_off_h[k + 1] < gen_off_h[k])
+      return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: scenario " + std::to_string(k) + " has an empty or reversed range");
+    if (ref_h[k] < bus_off_h[k] || ref_h[k] >= bus_off_h[k + 1])
+      return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: reference bus of scenario " + std::to_string(k) + " out of range");
+  }
+  if (bus_off_h[0] != 0 || line_off_h[0] != 0 || gen_off_h[0] != 0 || bus_off_h[ns] != nb ||
+      line_off_h[ns] != nl || gen_off_h[ns] != ng)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: scenario ranges do not cover the arrays");
   std::vector<int32_t> from(nl), to(nl), gb(ng);
   HIP_TRY(hipMemcpyAsync(from.data(), g->line_from, nl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(to.data(), g->line_to, nl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   if (ng > 0) HIP_TRY(hipMemcpyAsync(gb.data(), g->gen_bus, ng * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  std::vector<int32_t> deg(nb, 0), gdeg(nb, 0);
-  for (int l = 0; l < nl; ++l) {
-    if (from[l] < 0 || from[l] >= nb || to[l] < 0 || to[l] >= nb || from[l] == to[l])
-      return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: line " + std::to_string(l) + " has a bad end bus");
-    deg[from[l]]++;
-    deg[to[l]]++;
+  std::vector<int32_t> scen(nb), flags(nb, 0);
+  for (int k = 0; k < ns; ++k) {
+    for (int i = bus_off_h[k]; i < bus_off_h[k + 1]; ++i) scen[i] = k;
+    flags[ref_h[k]] |= BUS_REF;
   }
-  for (int k = 0; k < ng; ++k) {
-    if (gb[k] < 0 || gb[k] >= nb)
-      return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: generator " + std::to_string(k) + " has a bad bus");
-    gdeg[gb[k]]++;
+  std::vector<int32_t> deg(nb, 0), gdeg(nb, 0);
+  for (int k = 0; k < ns; ++k) {
+    for (int l = line_off_h[k]; l < line_off_h[k + 1]; ++l) {
+      const int f = from[l], t = to[l];
+      if (f < bus_off_h[k] || f >= bus_off_h[k + 1] || t < bus_off_h[k] || t >= bus_off_h[k + 1] || f == t)
+        return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: line " + std::to_string(l) + " has a bad end bus");
+      deg[f]++;
+      deg[t]++;
+    }
+    for (int q = gen_off_h[k]; q < gen_off_h[k + 1]; ++q) {
+      if (gb[q] < bus_off_h[k] || gb[q] >= bus_off_h[k + 1])
+        return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: generator " + std::to_string(q) + " has a bad bus");
+      gdeg[gb[q]]++;
+    }
   }
   for (int i = 0; i < nb; ++i)
     if (deg[i] == 0) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: bus " + std::to_string(i) + " has no line");
@@ -540,43 +719,41 @@ acopf_status acopf_setup(const acopf_grid* g, void* workspace, size_t bytes, voi
     ends[fill[from[l]]++] = 2 * l;
     ends[fill[to[l]]++] = 2 * l + 1;
   }
-  for (int k = 0; k < ng; ++k) gens[gfill[gb[k]]++] = k;
+  for (int q = 0; q < ng; ++q) gens[gfill[gb[q]]++] = q;
   Workspace w = ws_of(g, workspace);
   HIP_TRY(hipMemcpy(w.bus_end_ptr, eptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.bus_end, ends.data(), 2 * (size_t)nl * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.bus_gen_ptr, gptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   if (ng > 0) HIP_TRY(hipMemcpy(w.bus_gen, gens.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.bus_scen, scen.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.bus_flags, flags.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.scen_bus_off, bus_off_h, (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.scen_line_off, line_off_h, (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.scen_gen_off, gen_off_h, (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   SyncState zero;
   std::memset(&zero, 0, sizeof(zero));
   HIP_TRY(hipMemcpy(w.sync, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  std::vector<ScenState> sz(ns);
+  std::memset(sz.data(), 0, ns * sizeof(ScenState));
+  for (auto& e : sz) e.delta = 1.0;
+  HIP_TRY(hipMemcpy(w.scen, sz.data(), ns * sizeof(ScenState), hipMemcpyHostToDevice));
+  // multipliers start at zero (the previous-iterate start of a first solve)
+  // and so do the trace sums
+  const size_t D = sizeof(double);
+  if (ng > 0) HIP_TRY(hipMemset(w.lam_g, 0, 2 * (size_t)ng * D));
+  HIP_TRY(hipMemset(w.lam_l, 0, 8 * (size_t)nl * D));
+  if (ng > 0) HIP_TRY(hipMemset(w.tr_r_g, 0, 2 * (size_t)ng * D));
+  if (ng > 0) HIP_TRY(hipMemset(w.tr_s_g, 0, 2 * (size_t)ng * D));
+  HIP_TRY(hipMemset(w.tr_r_l, 0, 8 * (size_t)nl * D));
+  HIP_TRY(hipMemset(w.tr_s_l, 0, 8 * (size_t)nl * D));
   return ACOPF_OK;
 }
 
-acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double delta, int32_t mode,
-                            void* workspace, void* stream) {
-  if (!grid_ok(g) || !iterate_ok(x) || !workspace)
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: null argument");
-  if (!(delta > 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: trust radius must be > 0");
-  if (mode != ACOPF_HESSIAN_PSD && mode != ACOPF_HESSIAN_RAW)
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: unknown Hessian mode");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = ws_of(g, workspace);
-  const int bs = kDefaultBlock;
-  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w);
-  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, delta, (int)mode, w);
-  if (g->n_gen > 0)
-    hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, delta, w);
-  hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
-  HIP_TRY(hipGetLastError());
-  return ACOPF_OK;
-}
-
-static acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const double* rho_l,
-                            const double* lam_g, const double* lam_l, bool keep_lam, void* workspace,
-                            void* stream) {
+acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const double* rho_l, const double* lam_g,
+                            const double* lam_l, bool keep_lam, void* workspace, void* stream) {
   if (!grid_ok(g) || !workspace || !rho_l || (g->n_gen > 0 && !rho_g))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_init: null argument");
-  if ((lam_g == nullptr) != (lam_l == nullptr))
+  if ((lam_l == nullptr && lam_g != nullptr) || (lam_l != nullptr && lam_g == nullptr && g->n_gen > 0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_init: give both warm-start multiplier arrays or neither");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
@@ -610,7 +787,64 @@ static acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, con
   hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, w.line_mask,
                      (long long)g->n_line, 0);
   hipLaunchKernelGGL(k_prep_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, w);
-  hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, 0);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* acopf_last_error(void) { return last_error().c_str(); }
+
+size_t acopf_workspace_bytes(int32_t n_bus, int32_t n_line, int32_t n_gen, int32_t n_scen) {
+  if (n_bus <= 0 || n_line <= 0 || n_gen < 0 || n_scen < 0 || n_scen > n_bus) return 0;
+  return layout_workspace(nullptr, n_bus, n_line, n_gen, n_scen > 1 ? n_scen : 1, nullptr);
+}
+
+acopf_status acopf_setup(const acopf_grid* g, void* workspace, size_t bytes, void* stream) {
+  if (!grid_ok(g)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: incomplete grid description");
+  if (!workspace) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: null workspace");
+  if (n_scen_of(g) != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: use acopf_setup_batch for n_scen > 1");
+  if (g->ref_bus < 0 || g->ref_bus >= g->n_bus) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup: bad reference bus");
+  const int32_t bo[2] = {0, g->n_bus}, lo[2] = {0, g->n_line}, go[2] = {0, g->n_gen}, rf[1] = {g->ref_bus};
+  return setup_impl(g, bo, lo, go, rf, workspace, bytes, stream);
+}
+
+acopf_status acopf_setup_batch(const acopf_grid* g, const int32_t* bus_offset, const int32_t* line_offset,
+                               const int32_t* gen_offset, const int32_t* ref_bus, void* workspace, size_t bytes,
+                               void* stream) {
+  if (!grid_ok(g)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup_batch: incomplete grid description");
+  if (!workspace || !bus_offset || !line_offset || !gen_offset || !ref_bus)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_setup_batch: null argument");
+  return setup_impl(g, bus_offset, line_offset, gen_offset, ref_bus, workspace, bytes, stream);
+}
+
+acopf_status acopf_set_delta(const acopf_grid* g, const double* delta, void* workspace, void* stream) {
+  if (!grid_ok(g) || !workspace || !delta) return fail(ACOPF_ERR_INVALID_ARG, "acopf_set_delta: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  hipLaunchKernelGGL(k_copy_delta, dim3(blocks_for(w.n_scen, 256)), dim3(256), 0, s, w, delta);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double delta, int32_t mode,
+                            void* workspace, void* stream) {
+  if (!grid_ok(g) || !iterate_ok(x) || !workspace)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: null argument");
+  if (!(delta >= 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: trust radius must be >= 0");
+  if (mode != ACOPF_HESSIAN_PSD && mode != ACOPF_HESSIAN_RAW)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: unknown Hessian mode");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int bs = kDefaultBlock;
+  if (delta > 0.0) hipLaunchKernelGGL(k_set_delta, dim3(blocks_for(w.n_scen, bs)), dim3(bs), 0, s, w, delta);
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w);
+  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, (int)mode, w);
+  if (g->n_gen > 0) hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w);
+  hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -620,38 +854,68 @@ acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const dou
   return admm_init_impl(g, rho_g, rho_l, lam_g, lam_l, false, workspace, stream);
 }
 
-acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, void* workspace,
-                              void* stream, acopf_admm_result* result) {
+acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, void* workspace, void* stream,
+                              acopf_admm_result* result) {
   if (!grid_ok(g) || !p || !workspace) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: null argument");
   if (p->max_sweeps < 0 || !(p->eps_pri >= 0.0) || !(p->eps_dual >= 0.0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: bad parameters");
   const int bs = p->block_size > 0 ? p->block_size : kDefaultBlock;
-  if (bs % 64 != 0 || bs > 256) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: block_size must be a multiple of 64, <= 256");
+  if (bs % 64 != 0 || bs > 256)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: block_size must be a multiple of 64, <= 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
-  // errors recorded by the QP build and the factorisation
-  SyncState st;
-  acopf_status rs = read_sync(workspace, g, s, &st);
-  if (rs != ACOPF_OK) return rs;
-  if (st.numeric_error) return fail(ACOPF_ERR_NUMERIC, "acopf_admm_solve: the QP build met a vanishing elimination pivot or non-finite data");
-  if (st.nonconvex) return fail(ACOPF_ERR_NONCONVEX_LINE, "acopf_admm_solve: a line subproblem matrix is not positive definite");
+  const int ns = w.n_scen;
+  const int reset_blocks = blocks_for(std::max(w.max_partials, ns), 256);
   if (p->max_sweeps == 0) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, 0);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, 0, bs);
     HIP_TRY(hipGetLastError());
     if (result) return acopf_admm_result_get(g, workspace, stream, result);
     return ACOPF_OK;
   }
-  if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES) {
-    const int nbl = blocks_for(g->n_line, bs), nbb = blocks_for(g->n_bus, bs);
-    if (nbb > w.max_partials) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: too many bus blocks");
-    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, nbb);
-    for (int k = 0; k < p->max_sweeps; ++k) {
-      hipLaunchKernelGGL(k_line_phase, dim3(nbl), dim3(bs), 0, s, *g, w);
-      hipLaunchKernelGGL(k_bus_phase, dim3(nbb), dim3(bs), 0, s, *g, w);
-      hipLaunchKernelGGL(k_finish_phase, dim3(1), dim3(256), 0, s, w, nbb, p->max_sweeps, p->eps_pri, p->eps_dual);
+  if (p->trace != 0 && p->trace != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: trace must be 0 or 1");
+  if (p->trace && p->sweep_mode != ACOPF_SWEEP_LAUNCHES)
+    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: traced solves run in the launch-per-phase mode");
+  if (p->trace) {
+    const int bz = kDefaultBlock;
+    const long long G2 = 2LL * g->n_gen, L8 = 8LL * g->n_line;
+    if (G2 > 0) {
+      hipLaunchKernelGGL(k_fill, dim3(blocks_for(G2, bz)), dim3(bz), 0, s, w.tr_r_g, G2, 0.0);
+      hipLaunchKernelGGL(k_fill, dim3(blocks_for(G2, bz)), dim3(bz), 0, s, w.tr_s_g, G2, 0.0);
     }
-    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(L8, bz)), dim3(bz), 0, s, w.tr_r_l, L8, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(L8, bz)), dim3(bz), 0, s, w.tr_s_l, L8, 0.0);
+  }
+  if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES) {
+    // upper bounds of the per-scenario block counts (excess blocks exit)
+    const long long nbl = (g->n_line + bs - 1) / bs + ns, nbb = (g->n_bus + bs - 1) / bs + ns;
+    if (nbb > w.max_partials || nbl > 65535 || nbb > 65535)
+      return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: grid too large for the block size");
+    const int fold = (ns == 1 && nbb - 1 <= kFoldMaxBlocks) ? 1 : 0;
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs);
+    for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
+      const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
+      for (int k = k0; k < k1; ++k) {
+        hipLaunchKernelGGL(k_line_phase, dim3((unsigned)nbl), dim3(bs), 0, s, *g, w);
+        if (p->trace)
+          hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)nbb), dim3(bs), 0, s, *g, w, fold, p->max_sweeps,
+                             p->eps_pri, p->eps_dual);
+        else
+          hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)nbb), dim3(bs), 0, s, *g, w, fold, p->max_sweeps,
+                             p->eps_pri, p->eps_dual);
+        if (!fold)
+          hipLaunchKernelGGL(k_finish_phase, dim3(ns), dim3(256), 0, s, w, p->max_sweeps, p->eps_pri, p->eps_dual);
+      }
+      HIP_TRY(hipGetLastError());
+      if (k1 < p->max_sweeps && (p->eps_pri > 0.0 || p->eps_dual > 0.0)) {
+        // look at the stop flag before enqueueing more sweeps
+        SyncState st;
+        acopf_status rc = read_sync(w, s, &st);
+        if (rc != ACOPF_OK) return rc;
+        if (st.done) break;
+      }
+    }
   } else if (p->sweep_mode == ACOPF_SWEEP_PERSISTENT) {
+    if (ns != 1) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: the persistent mode serves one scenario");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     int cus = 0, coop = 0;
@@ -666,7 +930,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     if (p->max_blocks > 0) nblk = std::min<long long>(nblk, p->max_blocks);
     nblk = std::min<long long>(nblk, w.max_partials);
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_reset_sync, dim3(blocks_for(w.max_partials, 256)), dim3(256), 0, s, w, (int)nblk);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nblk, bs);
     acopf_grid gg = *g;
     int ms = p->max_sweeps;
     double ep = p->eps_pri, ed = p->eps_dual;
@@ -679,27 +943,44 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   return ACOPF_OK;
 }
 
-acopf_status acopf_admm_result_get(const acopf_grid* g, void* workspace, void* stream,
-                                   acopf_admm_result* result) {
-  if (!grid_ok(g) || !workspace || !result)
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_result_get: null argument");
+acopf_status acopf_admm_result_batch(const acopf_grid* g, void* workspace, void* stream, acopf_admm_result* out) {
+  if (!grid_ok(g) || !workspace || !out) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_result: null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
+  std::vector<ScenState> sc(w.n_scen);
   SyncState st;
+  HIP_TRY(hipMemcpyAsync(sc.data(), w.scen, w.n_scen * sizeof(ScenState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&st, w.sync, sizeof(SyncState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  result->sweeps = st.sweeps;
-  result->r_norm = st.r_norm;
-  result->s_norm = st.s_norm;
-  result->infeasible_lines = st.sweeps > 0 ? st.infeasible[(st.sweeps - 1) & 1] : 0;
-  result->blocks = st.blocks;
-  result->outcome = st.converged ? ACOPF_ADMM_CONVERGED : ACOPF_ADMM_MAX_SWEEPS;
+  for (int k = 0; k < w.n_scen; ++k) {
+    out[k].sweeps = sc[k].sweeps;
+    out[k].outcome = sc[k].status != 0 ? ACOPF_ADMM_FAILED
+                     : sc[k].converged ? ACOPF_ADMM_CONVERGED : ACOPF_ADMM_MAX_SWEEPS;
+    out[k].r_norm = sc[k].r_norm;
+    out[k].s_norm = sc[k].s_norm;
+    out[k].infeasible_lines = sc[k].sweeps > 0 ? sc[k].infeasible[(sc[k].sweeps - 1) & 1] : 0;
+    out[k].blocks = st.blocks;
+    out[k].status = sc[k].status;
+  }
   if (st.barrier_error) return fail(ACOPF_ERR_BARRIER, "acopf_admm_solve: grid barrier timed out");
+  if (w.n_scen > 1) return ACOPF_OK;  // failures of a batch are per-scenario outcomes
+  if (st.numeric_error)
+    return fail(ACOPF_ERR_NUMERIC, "acopf_admm_solve: the QP build met a vanishing elimination pivot or non-finite data");
+  if (st.nonconvex)
+    return fail(ACOPF_ERR_NONCONVEX_LINE, "acopf_admm_solve: a line subproblem matrix is not positive definite");
   return ACOPF_OK;
 }
 
-acopf_status acopf_admm_state_get(const acopf_grid* g, void* workspace, const acopf_admm_state* o,
-                                  void* stream) {
+acopf_status acopf_admm_result_get(const acopf_grid* g, void* workspace, void* stream, acopf_admm_result* result) {
+  if (!grid_ok(g) || !workspace || !result) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_result_get: null argument");
+  Workspace w = ws_of(g, workspace);
+  std::vector<acopf_admm_result> all(w.n_scen);
+  acopf_status rc = acopf_admm_result_batch(g, workspace, stream, all.data());
+  *result = all[0];
+  return rc;
+}
+
+acopf_status acopf_admm_state_get(const acopf_grid* g, void* workspace, const acopf_admm_state* o, void* stream) {
   if (!grid_ok(g) || !workspace || !o) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_state_get: null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
@@ -721,6 +1002,10 @@ acopf_status acopf_admm_state_get(const acopf_grid* g, void* workspace, const ac
   HIP_TRY(cp(o->dth, w.dth, g->n_bus));
   HIP_TRY(cp(o->nu, w.nu, 2 * (size_t)g->n_bus));
   HIP_TRY(cp(o->mu, w.mu, 2 * (size_t)g->n_line));
+  HIP_TRY(cp(o->sum_r_g, w.tr_r_g, G2));
+  HIP_TRY(cp(o->sum_s_g, w.tr_s_g, G2));
+  HIP_TRY(cp(o->sum_r_l, w.tr_r_l, L8));
+  HIP_TRY(cp(o->sum_s_l, w.tr_s_l, L8));
   return ACOPF_OK;
 }
 
@@ -737,23 +1022,26 @@ acopf_status acopf_step(const acopf_grid* g, const acopf_iterate* x, void* works
   return ACOPF_OK;
 }
 
-acopf_status acopf_sqp_step(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d,
-                            const double* rho_g, const double* rho_l, const acopf_sqp_params* p, void* workspace,
-                            void* stream, acopf_sqp_state* state) {
-  if (!grid_ok(g) || !iterate_ok(x) || !iterate_ok(d) || !p || !workspace || !state)
+acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d,
+                                  const double* rho_g, const double* rho_l, const acopf_sqp_params* p,
+                                  void* workspace, void* stream, acopf_sqp_state* states) {
+  if (!grid_ok(g) || !iterate_ok(x) || !iterate_ok(d) || !p || !workspace)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: null argument");
-  if (!(state->delta > 0.0) || !(p->mu > 0.0) || !(p->delta_max > 0.0))
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: trust radius, penalty and radius cap must be > 0");
+  if (!(p->mu > 0.0) || !(p->delta_max > 0.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: penalty and radius cap must be > 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
-  acopf_status rc = acopf_qp_build(g, x, state->delta, p->hessian_mode, workspace, stream);
+  acopf_status rc = acopf_qp_build(g, x, 0.0, p->hessian_mode, workspace, stream);
   if (rc != ACOPF_OK) return rc;
-  rc = admm_init_impl(g, rho_g, rho_l, nullptr, nullptr, p->warm_start != 0, workspace, stream);
-  if (rc != ACOPF_OK) return rc;
-  // the solve checks the build's error flags first (a synchronising read),
-  // so the events bracket the sweep launches only
-  SyncState pre;
-  rc = read_sync(workspace, g, s, &pre);
+  if (p->warm_start < ACOPF_START_ZERO || p->warm_start > ACOPF_START_GIVEN)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown warm-start mode");
+  if (p->warm_start == ACOPF_START_GIVEN && (!p->lam_l0 || (g->n_gen > 0 && !p->lam_g0)))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: ACOPF_START_GIVEN needs lam_g0 and lam_l0");
+  if (p->warm_start == ACOPF_START_GIVEN)
+    rc = admm_init_impl(g, rho_g, rho_l, p->lam_g0, p->lam_l0, false, workspace, stream);
+  else
+    rc = admm_init_impl(g, rho_g, rho_l, nullptr, nullptr, p->warm_start == ACOPF_START_PREVIOUS, workspace,
+                        stream);
   if (rc != ACOPF_OK) return rc;
   EventPair ev;
   HIP_TRY(ev.create());
@@ -764,54 +1052,128 @@ acopf_status acopf_sqp_step(const acopf_grid* g, const acopf_iterate* x, const a
   rc = acopf_step(g, x, workspace, d, stream);
   if (rc != ACOPF_OK) return rc;
   const int bs = 256;
-  const int nb = std::min(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs), w.max_partials);
-  hipLaunchKernelGGL(k_merit, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, w, nb, p->mu, state->delta, p->delta_max, p->grow_ratio);
-  hipLaunchKernelGGL(k_apply, dim3(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs)), dim3(bs), 0, s,
-                     *g, *x, *d, w);
+  const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
+  hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
+  hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio);
+  hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w);
   HIP_TRY(hipGetLastError());
-  SqpDecision dc;
-  HIP_TRY(hipMemcpyAsync(&dc, w.decision, sizeof(dc), hipMemcpyDeviceToHost, s));
-  acopf_admm_result ar;
-  rc = acopf_admm_result_get(g, workspace, stream, &ar);
+  if (!states) return ACOPF_OK;
+  std::vector<SqpDecision> dc(w.n_scen);
+  HIP_TRY(hipMemcpyAsync(dc.data(), w.decision, w.n_scen * sizeof(SqpDecision), hipMemcpyDeviceToHost, s));
+  std::vector<acopf_admm_result> ar(w.n_scen);
+  rc = acopf_admm_result_batch(g, workspace, stream, ar.data());
   if (rc != ACOPF_OK) return rc;
-  state->accepted = dc.accepted;
-  state->ared = dc.ared;
-  state->pred = dc.pred;
-  state->step_inf = dc.step_inf;
-  state->delta = dc.delta_out;
-  state->objective = dc.accepted ? dc.f_xd : dc.f_x;
-  state->merit = dc.accepted ? dc.f_xd + p->mu * dc.h_xd : dc.f_x + p->mu * dc.h_x;
-  state->admm_sweeps = ar.sweeps;
-  state->admm_r = ar.r_norm;
-  state->admm_s = ar.s_norm;
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
-  state->admm_ms = ms;
+  for (int k = 0; k < w.n_scen; ++k) {
+    acopf_sqp_state* st = &states[k];
+    st->delta = dc[k].delta_out;
+    st->accepted = dc[k].accepted;
+    st->ared = dc[k].ared;
+    st->pred = dc[k].pred;
+    st->step_inf = dc[k].step_inf;
+    st->objective = dc[k].accepted ? dc[k].f_xd : dc[k].f_x;
+    st->merit = dc[k].accepted ? dc[k].f_xd + p->mu * dc[k].h_xd : dc[k].f_x + p->mu * dc[k].h_x;
+    st->admm_sweeps = ar[k].sweeps;
+    st->admm_r = ar[k].r_norm;
+    st->admm_s = ar[k].s_norm;
+    st->admm_ms = ms;
+    st->status = ar[k].status;
+  }
   return ACOPF_OK;
 }
 
-acopf_status acopf_residuals(const acopf_grid* g, const acopf_iterate* x, void* workspace, void* stream,
-                             acopf_residuals_report* out) {
+acopf_status acopf_sqp_step(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d,
+                            const double* rho_g, const double* rho_l, const acopf_sqp_params* p, void* workspace,
+                            void* stream, acopf_sqp_state* state) {
+  if (!grid_ok(g) || !state || !workspace) return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: null argument");
+  if (n_scen_of(g) != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: use acopf_sqp_step_batch for batches");
+  if (!(state->delta > 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: trust radius must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  hipLaunchKernelGGL(k_set_delta, dim3(1), dim3(64), 0, s, w, state->delta);
+  HIP_TRY(hipGetLastError());
+  return acopf_sqp_step_batch(g, x, d, rho_g, rho_l, p, workspace, stream, state);
+}
+
+acopf_status acopf_residuals_batch(const acopf_grid* g, const acopf_iterate* x, void* workspace, void* stream,
+                                   acopf_residuals_report* out) {
   if (!grid_ok(g) || !iterate_ok(x) || !workspace || !out)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_residuals: null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
   const int bs = 256;
-  const int nb = std::min(blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs), w.max_partials);
-  hipLaunchKernelGGL(k_residuals, dim3(nb), dim3(bs), 0, s, *g, *x, w);
-  hipLaunchKernelGGL(k_residuals_final, dim3(1), dim3(256), 0, s, w, nb);
+  const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
+  hipLaunchKernelGGL(k_residual_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w);
+  hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(256), 0, s, w);
   HIP_TRY(hipGetLastError());
-  ResidualReport r;
-  HIP_TRY(hipMemcpyAsync(&r, w.report, sizeof(r), hipMemcpyDeviceToHost, s));
+  std::vector<ResidualReport> r(w.n_scen);
+  HIP_TRY(hipMemcpyAsync(r.data(), w.report, w.n_scen * sizeof(ResidualReport), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  out->balance = r.balance;
-  out->c11 = r.c11;
-  out->c12 = r.c12;
-  out->limit = r.limit;
-  out->bounds = r.bounds;
-  out->primal = std::max(std::max(std::max(r.balance, r.c11), std::max(r.c12, r.limit)), r.bounds);
-  out->dual = r.dual / std::max(1.0, r.gradf);
+  for (int k = 0; k < w.n_scen; ++k) {
+    out[k].balance = r[k].balance;
+    out[k].c11 = r[k].c11;
+    out[k].c12 = r[k].c12;
+    out[k].limit = r[k].limit;
+    out[k].bounds = r[k].bounds;
+    out[k].primal = std::max(std::max(std::max(r[k].balance, r[k].c11), std::max(r[k].c12, r[k].limit)), r[k].bounds);
+    out[k].dual = r[k].dual / std::max(1.0, r[k].gradf);
+  }
+  return ACOPF_OK;
+}
+
+acopf_status acopf_residuals(const acopf_grid* g, const acopf_iterate* x, void* workspace, void* stream,
+                             acopf_residuals_report* out) {
+  if (!grid_ok(g) || !out) return fail(ACOPF_ERR_INVALID_ARG, "acopf_residuals: null argument");
+  if (n_scen_of(g) != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_residuals: use acopf_residuals_batch for batches");
+  return acopf_residuals_batch(g, x, workspace, stream, out);
+}
+
+acopf_status acopf_features(const acopf_grid* g, const acopf_iterate* x, float* line_x, int64_t ld_line,
+                            float* gen_x, int64_t ld_gen, void* stream) {
+  if (!grid_ok(g) || !iterate_ok(x) || !line_x || (g->n_gen > 0 && !gen_x))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_features: null argument");
+  if (ld_line < g->n_line || (g->n_gen > 0 && ld_gen < g->n_gen))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_features: leading dimension below the component count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = std::max(g->n_line, g->n_gen);
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(n, 256)), dim3(256), 0, s, *g, *x, line_x, (long long)ld_line,
+                     gen_x, (long long)ld_gen);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_warm_targets(const acopf_grid* g, void* workspace, float* line_t, int64_t ld_line, float* gen_t,
+                                int64_t ld_gen, void* stream) {
+  if (!grid_ok(g) || !workspace || !line_t || (g->n_gen > 0 && !gen_t))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_targets: null argument");
+  if (ld_line < g->n_line || (g->n_gen > 0 && ld_gen < g->n_gen))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_targets: leading dimension below the component count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int n = std::max(g->n_line, g->n_gen);
+  hipLaunchKernelGGL(k_targets, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, line_t, (long long)ld_line, gen_t,
+                     (long long)ld_gen);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_warm_decode(const acopf_grid* g, void* workspace, const float* line_y, int64_t ld_line,
+                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t use_rho,
+                               double* lam_l, double* lam_g, double* rho_l, double* rho_g, void* stream) {
+  if (!grid_ok(g) || !workspace || !line_y || !lam_l || !rho_l ||
+      (g->n_gen > 0 && (!gen_y || !lam_g || !rho_g)))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_decode: null argument");
+  if (ld_line < g->n_line || (g->n_gen > 0 && ld_gen < g->n_gen))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_decode: leading dimension below the component count");
+  if (!(rho_l0 > 0.0) || !(rho_g0 > 0.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_decode: base penalties must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int n = std::max(g->n_line, g->n_gen);
+  hipLaunchKernelGGL(k_decode, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, line_y, (long long)ld_line, gen_y,
+                     (long long)ld_gen, rho_l0, rho_g0, (int)(use_rho != 0), lam_l, lam_g, rho_l, rho_g);
+  HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
 

@@ -138,7 +138,7 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
       double wh = fmin(delta, vh * vh - x.w[i]);
       double tl = fmax(-delta, -kTwoPi - x.th[i]);
       double th = fmin(delta, kTwoPi - x.th[i]);
-      if (i == g.ref_bus) { tl = 0.0; th = 0.0; }
+      if (w.bus_flags[i] & BUS_REF) { tl = 0.0; th = 0.0; }
       lo[2 * e] = fmin(wl, wh);
       hi[2 * e] = wh;
       lo[2 * e + 1] = fmin(tl, th);
@@ -354,7 +354,14 @@ ACOPF_HD void update_gen(const Workspace& w, int k) {
 // generator or flow copy with balance coefficient a_c = +-1,
 //   xbar_c = x_c + (lam_c - a_c nu) / rho_c,   lam_c + rho_c (x_c - xbar_c) = a_c nu,
 // so the multiplier update of these couplings is written as a_c nu.
+// kTrace: also add |r_c| and |s_c| of every coupling at the bus to the
+// workspace's trace sums.
+template <bool kTrace = false>
 ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2) {
+  // Line ends are visited in chunks of kChunk: the chunk's CSR entries are
+  // loaded together, then all of its coupling values, so a bus of degree d
+  // waits on 2 ceil(d / kChunk) memory round trips per pass instead of 2 d.
+  constexpr int kChunk = 4;
   const int G = w.n_gen, L = w.n_line;
   const int g0 = w.bus_gen_ptr[i], g1 = w.bus_gen_ptr[i + 1];
   const int e0 = w.bus_end_ptr[i], e1 = w.bus_end_ptr[i + 1];
@@ -368,20 +375,50 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
     rp += w.xg[k] + w.lam_g[k] * ip;
     rq += w.xg[G + k] + w.lam_g[G + k] * iq;
   }
-  for (int e = e0; e < e1; ++e) {
-    const int code = w.bus_end[e];
-    const int l = code >> 1, side = code & 1;
-    const int kp = 2 * side, kq = kp + 1, kw = 4 + 2 * side, kt = kw + 1;
-    const double ip = 1.0 / w.rho_l[kp * L + l], iq = 1.0 / w.rho_l[kq * L + l];
-    const double rhw = w.rho_l[kw * L + l], rht = w.rho_l[kt * L + l];
-    spp += ip;
-    sqq += iq;
-    rp -= w.xl[kp * L + l] + w.lam_l[kp * L + l] * ip;
-    rq -= w.xl[kq * L + l] + w.lam_l[kq * L + l] * iq;
-    qw += rhw;
-    cw += rhw * w.xl[kw * L + l] + w.lam_l[kw * L + l];
-    qt += rht;
-    ct += rht * w.xl[kt * L + l] + w.lam_l[kt * L + l];
+  for (int e = e0; e < e1; e += kChunk) {
+    int l[kChunk], sd[kChunk];
+    bool on[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      on[j] = e + j < e1;
+      const int code = on[j] ? w.bus_end[e + j] : 0;
+      l[j] = code >> 1;
+      sd[j] = code & 1;
+    }
+    double v[kChunk][12];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const int kp = 2 * sd[j], kw = 4 + 2 * sd[j];
+#pragma unroll
+      for (int m = 0; m < 12; ++m) v[j][m] = 0.0;
+      if (on[j]) {
+        v[j][0] = w.rho_l[kp * L + l[j]];
+        v[j][1] = w.rho_l[(kp + 1) * L + l[j]];
+        v[j][2] = w.rho_l[kw * L + l[j]];
+        v[j][3] = w.rho_l[(kw + 1) * L + l[j]];
+        v[j][4] = w.xl[kp * L + l[j]];
+        v[j][5] = w.xl[(kp + 1) * L + l[j]];
+        v[j][6] = w.xl[kw * L + l[j]];
+        v[j][7] = w.xl[(kw + 1) * L + l[j]];
+        v[j][8] = w.lam_l[kp * L + l[j]];
+        v[j][9] = w.lam_l[(kp + 1) * L + l[j]];
+        v[j][10] = w.lam_l[kw * L + l[j]];
+        v[j][11] = w.lam_l[(kw + 1) * L + l[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      if (!on[j]) continue;
+      const double ip = 1.0 / v[j][0], iq = 1.0 / v[j][1];
+      spp += ip;
+      sqq += iq;
+      rp -= v[j][4] + v[j][8] * ip;
+      rq -= v[j][5] + v[j][9] * iq;
+      qw += v[j][2];
+      cw += v[j][2] * v[j][6] + v[j][10];
+      qt += v[j][3];
+      ct += v[j][3] * v[j][7] + v[j][11];
+    }
   }
   const double gsh = g.gsh[i], bsh = g.bsh[i];
   const double iqw = 1.0 / qw;
@@ -394,7 +431,7 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
   const double nup = (sqq * rp - spq * rq) * idet;
   const double nuq = (spp * rq - spq * rp) * idet;
   const double dw_new = (cw + gsh * nup - bsh * nuq) * iqw;
-  const double dth_new = (i == g.ref_bus) ? 0.0 : ct / qt;
+  const double dth_new = (w.bus_flags[i] & BUS_REF) ? 0.0 : ct / qt;
   const double dw_old = w.dw[i], dth_old = w.dth[i];
   double rr = 0.0, ss = 0.0;
   for (int e = g0; e < g1; ++e) {
@@ -410,32 +447,79 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
       w.xbar_g[idx] = xb;
       rr += (xv - xb) * (xv - xb);
       ss += ds * ds;
+      if (kTrace) {
+        w.tr_r_g[idx] += fabs(xv - xb);
+        w.tr_s_g[idx] += fabs(ds);
+      }
     }
   }
-  for (int e = e0; e < e1; ++e) {
-    const int code = w.bus_end[e];
-    const int l = code >> 1, side = code & 1;
+  for (int e = e0; e < e1; e += kChunk) {
+    int l[kChunk], sd[kChunk];
+    bool on[kChunk];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {  // flow copies p, q (balance coefficient -1)
-      const int idx = (2 * side + j) * L + l;
-      const double rho = w.rho_l[idx], xv = w.xl[idx], lam = w.lam_l[idx];
-      const double lam_new = -((j == 0) ? nup : nuq);
-      const double xb = xv + (lam - lam_new) / rho;
-      const double ds = rho * (xb - w.xbar_f[idx]);
-      w.lam_l[idx] = lam_new;
-      w.xbar_f[idx] = xb;
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+    for (int j = 0; j < kChunk; ++j) {
+      on[j] = e + j < e1;
+      const int code = on[j] ? w.bus_end[e + j] : 0;
+      l[j] = code >> 1;
+      sd[j] = code & 1;
+    }
+    double v[kChunk][14];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const int kp = 2 * sd[j], kw = 4 + 2 * sd[j];
+#pragma unroll
+      for (int m = 0; m < 14; ++m) v[j][m] = 1.0;
+      if (on[j]) {
+        v[j][0] = w.rho_l[kp * L + l[j]];
+        v[j][1] = w.rho_l[(kp + 1) * L + l[j]];
+        v[j][2] = w.rho_l[kw * L + l[j]];
+        v[j][3] = w.rho_l[(kw + 1) * L + l[j]];
+        v[j][4] = w.xl[kp * L + l[j]];
+        v[j][5] = w.xl[(kp + 1) * L + l[j]];
+        v[j][6] = w.xl[kw * L + l[j]];
+        v[j][7] = w.xl[(kw + 1) * L + l[j]];
+        v[j][8] = w.lam_l[kp * L + l[j]];
+        v[j][9] = w.lam_l[(kp + 1) * L + l[j]];
+        v[j][10] = w.lam_l[kw * L + l[j]];
+        v[j][11] = w.lam_l[(kw + 1) * L + l[j]];
+        v[j][12] = w.xbar_f[kp * L + l[j]];
+        v[j][13] = w.xbar_f[(kp + 1) * L + l[j]];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {  // voltage copies w, th
-      const int idx = (4 + 2 * side + j) * L + l;
-      const double rho = w.rho_l[idx], xv = w.xl[idx], lam = w.lam_l[idx];
-      const double xb = (j == 0) ? dw_new : dth_new;
-      const double ds = rho * (xb - ((j == 0) ? dw_old : dth_old));
-      w.lam_l[idx] = lam + rho * (xv - xb);
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+    for (int j = 0; j < kChunk; ++j) {
+      if (!on[j]) continue;
+      const int kp = 2 * sd[j], kw = 4 + 2 * sd[j];
+      // flow copies p, q (balance coefficient -1): new multiplier -nu
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const double rho = v[j][m], xv = v[j][4 + m], lam = v[j][8 + m];
+        const double lam_new = -((m == 0) ? nup : nuq);
+        const double xb = xv + (lam - lam_new) / rho;
+        const double ds = rho * (xb - v[j][12 + m]);
+        w.lam_l[(kp + m) * L + l[j]] = lam_new;
+        w.xbar_f[(kp + m) * L + l[j]] = xb;
+        rr += (xv - xb) * (xv - xb);
+        ss += ds * ds;
+        if (kTrace) {
+          w.tr_r_l[(kp + m) * L + l[j]] += fabs(xv - xb);
+          w.tr_s_l[(kp + m) * L + l[j]] += fabs(ds);
+        }
+      }
+      // voltage copies w, th
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const double rho = v[j][2 + m], xv = v[j][6 + m], lam = v[j][10 + m];
+        const double xb = (m == 0) ? dw_new : dth_new;
+        const double ds = rho * (xb - ((m == 0) ? dw_old : dth_old));
+        w.lam_l[(kw + m) * L + l[j]] = lam + rho * (xv - xb);
+        rr += (xv - xb) * (xv - xb);
+        ss += ds * ds;
+        if (kTrace) {
+          w.tr_r_l[(kw + m) * L + l[j]] += fabs(xv - xb);
+          w.tr_s_l[(kw + m) * L + l[j]] += fabs(ds);
+        }
+      }
     }
   }
   w.dw[i] = dw_new;
@@ -646,7 +730,7 @@ ACOPF_HD void residual_bus(const acopf_grid& g, const acopf_iterate& x, const Wo
   primal[0] = fmax(fabs(rp), fabs(rq));
   const double thv = fmax(fmax(0.0, -(x.th[i] + kTwoPi)), fmax(0.0, x.th[i] - kTwoPi));
   primal[4] = fmax(fmax(fmax(0.0, v2lo - wi), fmax(0.0, wi - v2hi)), thv);
-  dual = fmax(proj_grad(gw, wi, v2lo, v2hi), (i == g.ref_bus) ? 0.0 : fabs(gth));
+  dual = fmax(proj_grad(gw, wi, v2lo, v2hi), (w.bus_flags[i] & BUS_REF) ? 0.0 : fabs(gth));
 }
 
 ACOPF_HD void residual_gen(const acopf_grid& g, const acopf_iterate& x, const Workspace& w, int k,

@@ -1,8 +1,11 @@
-// Device workspace of one grid: topology tables, QP data, ADMM state and
-// reduction scratch, carved out of one caller-allocated buffer.  All arrays
-// are structure-of-arrays with one entry per component so that consecutive
-// threads touch consecutive addresses; field k of an array with n entries
-// per field lives at [k * n + index].
+// Device workspace of one batch of grids (a single grid is a batch of one):
+// topology tables, QP data, ADMM state and reduction scratch, carved out of
+// one caller-allocated buffer.  The scenarios of a batch are packed one after
+// another (buses, lines and generators of scenario s occupy contiguous index
+// ranges) and never reference each other's components.  All arrays are
+// structure-of-arrays with one entry per component so that consecutive
+// threads touch consecutive addresses; field k of an array with n entries per
+// field lives at [k * n + index].
 #pragma once
 
 #include <stddef.h>
@@ -10,7 +13,7 @@
 
 namespace acopf {
 
-// Number of per-line FP64 fields written by the QP build.
+// Per-line FP64 fields written by the QP build.
 enum LineField {
   LF_M = 0,        // 10: reduced Hessian (packed upper triangle)
   LF_Q = 10,       // 4: linear term A^T H b
@@ -33,20 +36,30 @@ enum LineField {
 
 enum GenField { GF_FP = 0, GF_FPP, GF_PLO, GF_PHI, GF_QLO, GF_QHI, GF_COUNT };
 
+enum BusFlag { BUS_REF = 1 };
+
+// Whole-batch synchronisation and error state.
 struct SyncState {
-  unsigned int count;      // grid-barrier arrivals
-  unsigned int gen;        // grid-barrier generation
-  int done;                // stop flag of the current solve
-  int sweeps;              // sweeps completed
+  unsigned int count;      // bus-phase blocks finished (folded sweep end)
+  unsigned int go;         // grid-barrier release epoch (persistent kernel)
+  int done;                // every scenario has stopped
+  int n_done;              // scenarios stopped so far
   int barrier_error;       // a barrier wait timed out
   int numeric_error;       // non-finite data / vanishing pivot in the QP build
   int nonconvex;           // raw mode: a line matrix failed its Cholesky
-  int infeasible[2];       // infeasible line subproblems, by sweep parity
-  int converged;           // the stop test held at the last sweep
   int blocks;              // grid size of the last solve
-  unsigned int go;         // grid-barrier release epoch (persistent kernel)
-  int pad;
-  double r_norm, s_norm;
+};
+
+// Per-scenario ADMM and SQP state.
+struct ScenState {
+  int done;                // stopped (converged or at the sweep cap)
+  int sweeps;              // sweeps completed
+  int converged;           // the stop test held at the last sweep
+  int infeasible[2];       // infeasible line subproblems, by sweep parity
+  int status;              // 0, or the acopf_status of a failed QP build / factorisation
+  int pad[2];
+  double r_norm, s_norm;   // residual norms of the last sweep
+  double delta;            // trust radius of the current SQP iteration
 };
 
 // Outcome of one trust-region SQP step (Algorithm 1), decided on the device.
@@ -63,16 +76,23 @@ struct ResidualReport {
   double balance, c11, c12, limit, bounds, dual, gradf;
 };
 
-constexpr int kMeritFields = 8;     // f_x, f_xd, quad_gen, h_x, h_xd, m_d, quad_line, step max
-constexpr int kResidFields = 7;     // balance, c11, c12, limit, bounds, dual, gradf
+// Arrival flags of different blocks sit on different 128-byte lines.
+constexpr int kArriveStride = 32;
 
 struct Workspace {
-  int32_t n_bus, n_line, n_gen, max_partials;
+  int32_t n_bus, n_line, n_gen, n_scen, max_partials;
   // topology
   int32_t* bus_end_ptr;    // [n_bus + 1]
   int32_t* bus_end;        // [2 n_line] entry 2 l + side (0 from end, 1 to end)
   int32_t* bus_gen_ptr;    // [n_bus + 1]
   int32_t* bus_gen;        // [n_gen]
+  int32_t* bus_scen;       // [n_bus] scenario of each bus
+  int32_t* bus_flags;      // [n_bus] BusFlag bits
+  int32_t* scen_bus_off;   // [n_scen + 1]
+  int32_t* scen_line_off;  // [n_scen + 1]
+  int32_t* scen_gen_off;   // [n_scen + 1]
+  int32_t* line_blk_off;   // [n_scen + 1] first block of each scenario in the line phase
+  int32_t* bus_blk_off;    // [n_scen + 1] same for the bus phase
   // QP data
   double* line;            // [LF_COUNT][n_line]
   double* gen;             // [GF_COUNT][n_gen]
@@ -88,41 +108,55 @@ struct Workspace {
   double *dw, *dth, *nu;                 // [n_bus], [n_bus], [2][n_bus]
   double *mu;                            // [2][n_line]
   int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
+  // per-coupling sums of |r_c| and |s_c| over the sweeps of a traced solve
+  double *tr_r_g, *tr_s_g;               // [2][n_gen]
+  double *tr_r_l, *tr_s_l;               // [8][n_line]
   // reductions
   double* partials;        // [2][max_partials]
   unsigned int* arrive;    // [max_partials * kArriveStride] grid-barrier arrival epochs
-  double* merit_partials;  // [kMeritFields][max_partials]
-  double* resid_partials;  // [kResidFields][max_partials]
+  double* line_comp;       // [4][n_line] per-component merit / residual pieces
+  double* gen_comp;        // [4][n_gen]
+  double* bus_comp;        // [3][n_bus]
   SyncState* sync;
-  SqpDecision* decision;
-  ResidualReport* report;
+  ScenState* scen;         // [n_scen]
+  SqpDecision* decision;   // [n_scen]
+  ResidualReport* report;  // [n_scen]
 };
-
-// Arrival flags of different blocks sit on different 128-byte lines.
-constexpr int kArriveStride = 32;
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+inline int32_t max_partials_for(int32_t nb, int32_t nl, int32_t ns) {
+  // bus-phase blocks of 64 threads (plus one partial block per scenario)
+  // and the largest persistent grid
+  int32_t need = (nb > nl ? nb : nl) / 64 + 2 * ns + 64;
+  return need > 4096 ? need : 4096;
+}
+
 // Lays the workspace out from base (or, with base == nullptr, only counts
 // its size).  Returns the number of bytes used.
-inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, Workspace* w) {
+inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, int32_t ns, Workspace* w) {
   size_t off = 0;
   char* b = static_cast<char*>(base);
   auto take = [&](size_t bytes) -> void* {
     void* p = b ? (void*)(b + off) : nullptr;
-    off += align_up(bytes);
+    off += align_up(bytes > 0 ? bytes : 1);
     return p;
   };
   const size_t D = sizeof(double), I = sizeof(int32_t);
-  int32_t maxp = 4096;
-  int32_t need = (nb > nl ? nb : nl) / 64 + 64;
-  if (need > maxp) maxp = need;
+  const int32_t maxp = max_partials_for(nb, nl, ns);
   Workspace t;
-  t.n_bus = nb; t.n_line = nl; t.n_gen = ng; t.max_partials = maxp;
+  t.n_bus = nb; t.n_line = nl; t.n_gen = ng; t.n_scen = ns; t.max_partials = maxp;
   t.bus_end_ptr = (int32_t*)take((size_t)(nb + 1) * I);
   t.bus_end = (int32_t*)take((size_t)2 * nl * I);
   t.bus_gen_ptr = (int32_t*)take((size_t)(nb + 1) * I);
-  t.bus_gen = (int32_t*)take((size_t)(ng > 0 ? ng : 1) * I);
+  t.bus_gen = (int32_t*)take((size_t)ng * I);
+  t.bus_scen = (int32_t*)take((size_t)nb * I);
+  t.bus_flags = (int32_t*)take((size_t)nb * I);
+  t.scen_bus_off = (int32_t*)take((size_t)(ns + 1) * I);
+  t.scen_line_off = (int32_t*)take((size_t)(ns + 1) * I);
+  t.scen_gen_off = (int32_t*)take((size_t)(ns + 1) * I);
+  t.line_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
+  t.bus_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.line = (double*)take((size_t)LF_COUNT * nl * D);
   t.gen = (double*)take((size_t)GF_COUNT * ng * D);
   t.bus_pdk = (double*)take((size_t)nb * D);
@@ -142,13 +176,19 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, W
   t.nu = (double*)take((size_t)2 * nb * D);
   t.mu = (double*)take((size_t)2 * nl * D);
   t.line_mask = (int32_t*)take((size_t)nl * I);
+  t.tr_r_g = (double*)take((size_t)2 * ng * D);
+  t.tr_s_g = (double*)take((size_t)2 * ng * D);
+  t.tr_r_l = (double*)take((size_t)8 * nl * D);
+  t.tr_s_l = (double*)take((size_t)8 * nl * D);
   t.partials = (double*)take((size_t)2 * maxp * D);
   t.arrive = (unsigned int*)take((size_t)maxp * kArriveStride * sizeof(unsigned int));
-  t.merit_partials = (double*)take((size_t)kMeritFields * maxp * D);
-  t.resid_partials = (double*)take((size_t)kResidFields * maxp * D);
+  t.line_comp = (double*)take((size_t)4 * nl * D);
+  t.gen_comp = (double*)take((size_t)4 * ng * D);
+  t.bus_comp = (double*)take((size_t)3 * nb * D);
   t.sync = (SyncState*)take(sizeof(SyncState));
-  t.decision = (SqpDecision*)take(sizeof(SqpDecision));
-  t.report = (ResidualReport*)take(sizeof(ResidualReport));
+  t.scen = (ScenState*)take((size_t)ns * sizeof(ScenState));
+  t.decision = (SqpDecision*)take((size_t)ns * sizeof(SqpDecision));
+  t.report = (ResidualReport*)take((size_t)ns * sizeof(ResidualReport));
   if (w) *w = t;
   return off;
 }

@@ -20,35 +20,64 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+def _col_ptr(t: torch.Tensor, col: int) -> int:
+    """Address of column col of a row-major 2-D tensor."""
+    return t.data_ptr() + int(col) * t.element_size()
+
+
+def _pack(grids):
+    """Concatenate the arrays of several grids (a batch of independent
+    scenarios) and offset their bus indices; returns (arrays, offsets)."""
+    nb = np.cumsum([0] + [int(g.n_bus) for g in grids])
+    nl = np.cumsum([0] + [int(g.n_line) for g in grids])
+    ng = np.cumsum([0] + [int(g.n_gen) for g in grids])
+    arrays = {}
+    for n in _abi.GRID_BUS_FIELDS + _abi.GRID_LINE_FIELDS + _abi.GRID_GEN_FIELDS:
+        arrays[n] = np.concatenate([np.asarray(getattr(g, n), dtype=np.float64) for g in grids])
+    arrays["line_from"] = np.concatenate([np.asarray(g.f) + nb[k] for k, g in enumerate(grids)])
+    arrays["line_to"] = np.concatenate([np.asarray(g.t) + nb[k] for k, g in enumerate(grids)])
+    arrays["gen_bus"] = np.concatenate([np.asarray(g.gbus) + nb[k] for k, g in enumerate(grids)])
+    refs = np.array([int(g.ref) + nb[k] for k, g in enumerate(grids)], dtype=np.int32)
+    return arrays, (nb.astype(np.int32), nl.astype(np.int32), ng.astype(np.int32), refs)
+
+
 class DeviceGrid:
-    """The network arrays of a grid (any object with the attributes of
-    ``acopf_grid``) resident on one device, plus its workspace."""
+    """The network arrays of a grid, or of a batch of independent scenario
+    grids packed one after another (pass a list), resident on one device,
+    plus its workspace.  Grids are objects with the attributes of
+    ``acopf_grid`` (n_bus, n_line, n_gen, ref, f, t, gbus and the data)."""
 
     def __init__(self, grid, device: str = "cuda:0"):
         self.lib = _abi.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the ADMM solver runs on a HIP device only")
-        self.n_bus, self.n_line, self.n_gen = int(grid.n_bus), int(grid.n_line), int(grid.n_gen)
-        self.ref = int(grid.ref)
-        t = {}
+        grids = list(grid) if isinstance(grid, (list, tuple)) else [grid]
+        self.n_scen = len(grids)
+        arrays, (bo, lo, go, refs) = _pack(grids)
+        self.offsets = {"bus": bo, "line": lo, "gen": go}
+        self.n_bus, self.n_line, self.n_gen = int(bo[-1]), int(lo[-1]), int(go[-1])
+        self.ref = int(refs[0])
         f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
         i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32)).to(self.device)
-        for n in _abi.GRID_BUS_FIELDS + _abi.GRID_LINE_FIELDS + _abi.GRID_GEN_FIELDS:
-            t[n] = f64(getattr(grid, n))
-        t["line_from"] = i32(grid.f)
-        t["line_to"] = i32(grid.t)
-        t["gen_bus"] = i32(grid.gbus)
+        t = {n: f64(arrays[n]) for n in _abi.GRID_BUS_FIELDS + _abi.GRID_LINE_FIELDS + _abi.GRID_GEN_FIELDS}
+        for n in _abi.GRID_LINE_INT + _abi.GRID_GEN_INT:
+            t[n] = i32(arrays[n])
         self.tensors = t
-        self.cgrid = Grid(self.n_bus, self.n_line, self.n_gen, self.ref,
+        self.cgrid = Grid(self.n_bus, self.n_line, self.n_gen, self.ref, self.n_scen, 0,
                           *[t[n].data_ptr() for n in _abi.GRID_BUS_FIELDS + _abi.GRID_LINE_INT
                             + _abi.GRID_LINE_FIELDS + _abi.GRID_GEN_INT + _abi.GRID_GEN_FIELDS])
-        nbytes = self.lib.acopf_workspace_bytes(self.n_bus, self.n_line, self.n_gen)
+        nbytes = self.lib.acopf_workspace_bytes(self.n_bus, self.n_line, self.n_gen, self.n_scen)
         if nbytes == 0:
             raise ValueError("bad grid sizes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ws = ctypes.c_void_p(self.workspace.data_ptr())
-        check(self.lib.acopf_setup(ctypes.byref(self.cgrid), self.ws, nbytes, self.stream))
+        if self.n_scen == 1:
+            check(self.lib.acopf_setup(ctypes.byref(self.cgrid), self.ws, nbytes, self.stream))
+        else:
+            self._offs = [np.ascontiguousarray(a, dtype=np.int32) for a in (bo, lo, go, refs)]
+            check(self.lib.acopf_setup_batch(ctypes.byref(self.cgrid), *[a.ctypes.data for a in self._offs],
+                                             self.ws, nbytes, self.stream))
 
     @property
     def stream(self):
@@ -100,9 +129,9 @@ class DeviceGrid:
 
     def admm_solve(self, max_sweeps: int, eps_pri: float = 0.0, eps_dual: float = 0.0,
                    sweep_mode: int = _abi.SWEEP_PERSISTENT, block_size: int = 0, max_blocks: int = 0,
-                   sync: bool = True):
+                   sync: bool = True, trace: bool = False):
         p = AdmmParams(int(max_sweeps), float(eps_pri), float(eps_dual), int(sweep_mode), int(block_size),
-                       int(max_blocks))
+                       int(max_blocks), int(bool(trace)))
         res = AdmmResult()
         check(self.lib.acopf_admm_solve(ctypes.byref(self.cgrid), ctypes.byref(p), self.ws, self.stream,
                                         ctypes.byref(res) if sync else None))
@@ -113,17 +142,30 @@ class DeviceGrid:
         check(self.lib.acopf_admm_result_get(ctypes.byref(self.cgrid), self.ws, self.stream, ctypes.byref(res)))
         return self._result_dict(res)
 
+    def admm_results(self) -> list:
+        """Per-scenario results of the last solve."""
+        res = (AdmmResult * self.n_scen)()
+        check(self.lib.acopf_admm_result_batch(ctypes.byref(self.cgrid), self.ws, self.stream, res))
+        return [self._result_dict(r) for r in res]
+
+    def set_delta(self, delta):
+        """Per-scenario trust radii (scalar or one value per scenario)."""
+        d = torch.as_tensor(np.broadcast_to(np.asarray(delta, dtype=np.float64), (self.n_scen,)).copy()).to(self.device)
+        self._delta = d
+        check(self.lib.acopf_set_delta(ctypes.byref(self.cgrid), d.data_ptr(), self.ws, self.stream))
+
     @staticmethod
     def _result_dict(res: AdmmResult) -> dict:
         return {"sweeps": res.sweeps, "outcome": res.outcome, "r": res.r_norm, "s": res.s_norm,
-                "infeasible_lines": res.infeasible_lines, "blocks": res.blocks,
+                "infeasible_lines": res.infeasible_lines, "blocks": res.blocks, "status": res.status,
                 "converged": res.outcome == _abi.ADMM_CONVERGED}
 
     def admm_state(self) -> dict:
         """Copy of the ADMM state as device tensors in the line-major layout."""
         G, L, B = self.n_gen, self.n_line, self.n_bus
         sizes = {"xg": 2 * G, "xbar_g": 2 * G, "lam_g": 2 * G, "rho_g": 2 * G, "xl": 8 * L, "xbar_f": 4 * L,
-                 "lam_l": 8 * L, "rho_l": 8 * L, "dw": B, "dth": B, "nu": 2 * B, "mu": 2 * L}
+                 "lam_l": 8 * L, "rho_l": 8 * L, "dw": B, "dth": B, "nu": 2 * B, "mu": 2 * L,
+                 "sum_r_g": 2 * G, "sum_s_g": 2 * G, "sum_r_l": 8 * L, "sum_s_l": 8 * L}
         out = {k: torch.empty(n, dtype=torch.float64, device=self.device) for k, n in sizes.items()}
         st = AdmmState(*[out[n].data_ptr() for n in _abi.STATE_FIELDS])
         check(self.lib.acopf_admm_state_get(ctypes.byref(self.cgrid), self.ws, ctypes.byref(st), self.stream))
@@ -138,20 +180,34 @@ class DeviceGrid:
                                   self.stream))
         return d
 
+    def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam):
+        start = int(warm_start) if not isinstance(warm_start, bool) else int(warm_start)
+        p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), start, admm)
+        if start == _abi.START_GIVEN:
+            if lam is None:
+                raise ValueError("warm_start=START_GIVEN needs lam=(lam_g, lam_l)")
+            f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+            self._lam0 = (f64(lam[0]), f64(lam[1]))
+            p.lam_g0, p.lam_l0 = self._lam0[0].data_ptr(), self._lam0[1].data_ptr()
+        return p
+
     def sqp_step(self, x: dict, delta: float, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
-                 grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start: bool = False,
+                 grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                  max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
-                 block_size: int = 0, max_blocks: int = 0, d: dict | None = None) -> dict:
+                 block_size: int = 0, max_blocks: int = 0, d: dict | None = None, lam=None,
+                 trace: bool = False) -> dict:
         """One trust-region SQP iteration on the device; x is updated in place
-        when the step is accepted.  Returns the host-side decision record."""
+        when the step is accepted.  warm_start: False/True (zero / previous
+        multipliers) or one of _abi.START_*; lam = (lam_g, lam_l) for
+        START_GIVEN.  Returns the host-side decision record."""
         if d is None:
             d = self.empty_iterate()
         self._d = d
         f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
-        p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), int(bool(warm_start)),
-                      AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size),
-                                 int(max_blocks)))
+        p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
+                             AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size),
+                                        int(max_blocks), int(bool(trace))), lam)
         st = SqpState()
         st.delta = float(delta)
         cx, cd = self.c_iterate(x), self.c_iterate(d)
@@ -160,9 +216,105 @@ class DeviceGrid:
                                       self.stream, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in SqpState._fields_}
 
+    def sqp_step_batch(self, x: dict, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
+                       grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
+                       max_sweeps: int = 20000, eps: float = 1e-4, block_size: int = 0, d: dict | None = None,
+                       sync: bool = True, lam=None, trace: bool = False):
+        """One SQP iteration for every scenario of the batch (radii held on
+        the device, see set_delta); per-scenario decisions if sync."""
+        if d is None:
+            d = self.empty_iterate()
+        self._d = d
+        f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+        self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
+        p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
+                             AdmmParams(int(max_sweeps), float(eps), float(eps), _abi.SWEEP_LAUNCHES,
+                                        int(block_size), 0, int(bool(trace))), lam)
+        sts = (SqpState * self.n_scen)() if sync else None
+        cx, cd = self.c_iterate(x), self.c_iterate(d)
+        check(self.lib.acopf_sqp_step_batch(ctypes.byref(self.cgrid), ctypes.byref(cx), ctypes.byref(cd),
+                                            self._rho_g.data_ptr(), self._rho_l.data_ptr(), ctypes.byref(p),
+                                            self.ws, self.stream, sts))
+        if not sync:
+            return None
+        return [{k: getattr(st, k) for k, _ in SqpState._fields_} for st in sts]
+
+    # ------------------------------------------------------------ learned warm start
+    def features(self, x: dict, out=None, cols=(0, 0)):
+        """Line and generator features at x (FP32, feature-major).  With out =
+        (line_x, gen_x) (2-D tensors, row stride = leading dimension) they are
+        written from columns cols = (line column, gen column); otherwise new
+        tensors are returned."""
+        if out is None:
+            out = (torch.empty(_abi.LINE_FEATURES, self.n_line, dtype=torch.float32, device=self.device),
+                   torch.empty(_abi.GEN_FEATURES, max(self.n_gen, 1), dtype=torch.float32, device=self.device))
+        fl, fg = out
+        cx = self.c_iterate(x)
+        check(self.lib.acopf_features(ctypes.byref(self.cgrid), ctypes.byref(cx), _col_ptr(fl, cols[0]),
+                                      fl.stride(0), _col_ptr(fg, cols[1]), fg.stride(0), self.stream))
+        return fl, fg
+
+    def warm_targets(self, out=None, cols=(0, 0)):
+        """Training targets of the last (traced) solve, FP32 feature-major
+        (columns as in features)."""
+        if out is None:
+            out = (torch.empty(_abi.LINE_OUTPUTS, self.n_line, dtype=torch.float32, device=self.device),
+                   torch.empty(_abi.GEN_OUTPUTS, max(self.n_gen, 1), dtype=torch.float32, device=self.device))
+        tl, tg = out
+        check(self.lib.acopf_warm_targets(ctypes.byref(self.cgrid), self.ws, _col_ptr(tl, cols[0]), tl.stride(0),
+                                          _col_ptr(tg, cols[1]), tg.stride(0), self.stream))
+        return tl, tg
+
+    def warm_decode(self, yl, yg, rho_l0: float, rho_g0: float, use_rho: bool = True):
+        """ADMM start (lam_g, lam_l, rho_g, rho_l; FP64, layout of the ADMM
+        state) from network outputs yl [16][n_line], yg [4][n_gen]."""
+        G, L = self.n_gen, self.n_line
+        z = lambda n: torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        lam_g, lam_l, rho_g, rho_l = z(2 * G), z(8 * L), z(2 * G), z(8 * L)
+        check(self.lib.acopf_warm_decode(ctypes.byref(self.cgrid), self.ws, yl.data_ptr(), yl.stride(0),
+                                         yg.data_ptr(), yg.stride(0), float(rho_l0), float(rho_g0),
+                                         int(bool(use_rho)), lam_l.data_ptr(), lam_g.data_ptr(),
+                                         rho_l.data_ptr(), rho_g.data_ptr(), self.stream))
+        return lam_g[:2 * G], lam_l, rho_g[:2 * G], rho_l
+
+    def residuals_batch(self, x: dict) -> list:
+        r = (ResidualsReport * self.n_scen)()
+        cx = self.c_iterate(x)
+        check(self.lib.acopf_residuals_batch(ctypes.byref(self.cgrid), ctypes.byref(cx), self.ws, self.stream, r))
+        return [{k: getattr(e, k) for k, _ in ResidualsReport._fields_} for e in r]
+
     def residuals(self, x: dict) -> dict:
         r = ResidualsReport()
         cx = self.c_iterate(x)
         check(self.lib.acopf_residuals(ctypes.byref(self.cgrid), ctypes.byref(cx), self.ws, self.stream,
                                        ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in ResidualsReport._fields_}
+
+
+_TUNED = {}
+
+
+def autotune_block(dg: DeviceGrid, x: dict, delta: float = 0.05, rho: float = 2e4, sweeps: int = 50,
+                   candidates=(64, 128, 256)) -> int:
+    """Block size of the sweep kernels (launch mode) that runs fastest on this
+    grid or batch, timed with HIP events over a few sweeps of the QP at x;
+    cached per (buses, lines, scenarios) for the process."""
+    key = (dg.n_bus, dg.n_line, dg.n_scen)
+    if key in _TUNED:
+        return _TUNED[key]
+    stream = torch.cuda.current_stream(dg.device)
+    dg.qp_build(x, delta)
+    best, best_ms = candidates[0], float("inf")
+    for bs in candidates:
+        dg.admm_init(*dg.rho_scalar(rho))
+        dg.admm_solve(5, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=bs, sync=False)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dg.admm_solve(sweeps, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=bs, sync=False)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        if ms < best_ms:
+            best, best_ms = bs, ms
+    _TUNED[key] = best
+    return best

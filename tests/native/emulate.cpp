@@ -36,14 +36,20 @@ void emu_psd_project(int n, double* m) {
 
 // Full solve emulation: setup tables, QP build, init, `sweeps` sweeps, step.
 // The workspace is a host buffer of acopf_workspace_bytes-equivalent size.
-size_t emu_workspace_bytes(int nb, int nl, int ng) { return layout_workspace(nullptr, nb, nl, ng, nullptr); }
+size_t emu_workspace_bytes(int nb, int nl, int ng) { return layout_workspace(nullptr, nb, nl, ng, 1, nullptr); }
 
 int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode, const double* rho_g,
             const double* rho_l, const double* lam_g, const double* lam_l, int sweeps, void* ws_base,
             const acopf_iterate* d, double* rs_out) {
   const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
   Workspace w;
-  layout_workspace(ws_base, nb, nl, ng, &w);
+  layout_workspace(ws_base, nb, nl, ng, 1, &w);
+  // one scenario: tables of acopf_setup
+  w.scen_bus_off[0] = 0; w.scen_bus_off[1] = nb;
+  w.scen_line_off[0] = 0; w.scen_line_off[1] = nl;
+  w.scen_gen_off[0] = 0; w.scen_gen_off[1] = ng;
+  for (int i = 0; i < nb; ++i) { w.bus_scen[i] = 0; w.bus_flags[i] = (i == g->ref_bus) ? BUS_REF : 0; }
+  w.scen[0].delta = delta;
   // incidence tables (same construction as acopf_setup)
   std::vector<int> deg(nb, 0), gdeg(nb, 0);
   for (int l = 0; l < nl; ++l) { deg[g->line_from[l]]++; deg[g->line_to[l]]++; }
@@ -104,7 +110,7 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
 // xl, lam_l, xbar_f, xg, lam_g, dw, dth, nu.
 void emu_state_ptrs(void* base, int nb, int nl, int ng, double** out) {
   Workspace w;
-  layout_workspace(base, nb, nl, ng, &w);
+  layout_workspace(base, nb, nl, ng, 1, &w);
   out[0] = w.xl; out[1] = w.lam_l; out[2] = w.xbar_f; out[3] = w.xg;
   out[4] = w.lam_g; out[5] = w.dw; out[6] = w.dth; out[7] = w.nu;
 }
@@ -113,7 +119,7 @@ void emu_state_ptrs(void* base, int nb, int nl, int ng, double** out) {
 // quad_line, step max) from a workspace holding the QP of x.
 void emu_merit(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate* d, void* base, double* out) {
   Workspace w;
-  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, &w);
+  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, 1, &w);
   for (int k = 0; k < 8; ++k) out[k] = 0.0;
   for (int l = 0; l < g->n_line; ++l) {
     double o[4];
@@ -133,7 +139,7 @@ void emu_merit(const acopf_grid* g, const acopf_iterate* x, const acopf_iterate*
 // the workspace's balance multipliers.
 void emu_residuals(const acopf_grid* g, const acopf_iterate* x, void* base, double* out) {
   Workspace w;
-  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, &w);
+  layout_workspace(base, g->n_bus, g->n_line, g->n_gen, 1, &w);
   for (int k = 0; k < 7; ++k) out[k] = 0.0;
   for (int l = 0; l < g->n_line; ++l) {
     double pr[5] = {0, 0, 0, 0, 0}, du = 0.0;

@@ -12,9 +12,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "acopf_admm.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(acopf_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(acopf_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_exports():
@@ -27,9 +31,10 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(lib, name), name
     lib.acopf_workspace_bytes.restype = ctypes.c_size_t
-    lib.acopf_workspace_bytes.argtypes = [ctypes.c_int32] * 3
-    assert lib.acopf_workspace_bytes(14, 20, 5) > 0
-    assert lib.acopf_workspace_bytes(0, 20, 5) == 0
+    lib.acopf_workspace_bytes.argtypes = [ctypes.c_int32] * 4
+    assert lib.acopf_workspace_bytes(14, 20, 5, 1) > 0
+    assert lib.acopf_workspace_bytes(0, 20, 5, 1) == 0
+    assert lib.acopf_workspace_bytes(28, 40, 10, 2) > lib.acopf_workspace_bytes(14, 20, 5, 1)
 
 
 def test_struct_layouts_match_the_header(tmp_path):

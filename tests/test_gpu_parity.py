@@ -271,3 +271,144 @@ def test_sqp_iterations_match_oracle():
     for name in ("pg", "qg", "w", "th", "wR", "wI"):
         assert rel_err(xf[name], getattr(ref.x, name)) <= TOL, name
     assert rel_err(xf["pi"].reshape(4, -1).T, ref.pi) <= 1e-7
+
+
+def _batch_cases():
+    from synth.grids import perturb_loads
+    base = grid_14()
+    return [perturb_loads(base, 64000 + k) for k in range(3)] + \
+        [tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04)]
+
+
+def _slice_state(st, dg, k, G, L, B):
+    bo, lo, go = dg.offsets["bus"], dg.offsets["line"], dg.offsets["gen"]
+    sl = lambda a, n, o, f: a.reshape(f, n)[:, o[k]:o[k + 1]]
+    return {"xl": sl(st["xl"], L, lo, 8), "lam_l": sl(st["lam_l"], L, lo, 8), "xbar_f": sl(st["xbar_f"], L, lo, 4),
+            "xg": sl(st["xg"], G, go, 2), "lam_g": sl(st["lam_g"], G, go, 2), "dw": st["dw"][bo[k]:bo[k + 1]],
+            "dth": st["dth"][bo[k]:bo[k + 1]], "nu": sl(st["nu"], B, bo, 2)}
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_batch_matches_solo_runs_and_oracle(eps):
+    """Scenarios solved together in one batch (block tables per scenario,
+    per-scenario stop) reproduce their solo GPU runs bit for bit and the
+    oracle within 1e-8; with eps > 0 each scenario stops at its own sweep."""
+    print(f"[gpu] batch eps={eps}", flush=True)
+    grids = _batch_cases()
+    DeviceGrid = _dev()
+    pts = [start_point(g, pi_scale=20.0, seed=k) for k, g in enumerate(grids)]
+    nsw = 400
+    dg = DeviceGrid(grids)
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    pi = np.concatenate([p[1] for p in pts])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), pi)
+    dg.qp_build(xb, 0.05)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    dg.admm_solve(nsw, eps, eps, sweep_mode=1, block_size=64)
+    res = dg.admm_results()
+    st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    for k, g in enumerate(grids):
+        x, pik = pts[k]
+        solo = DeviceGrid(g)
+        xs = solo.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pik)
+        solo.qp_build(xs, 0.05)
+        solo.admm_init(*solo.rho_scalar(2e4))
+        rs = solo.admm_solve(nsw, eps, eps, sweep_mode=1, block_size=64)
+        ss = {k2: v.cpu().numpy() for k2, v in solo.admm_state().items()}
+        part = _slice_state(st, dg, k, dg.n_gen, dg.n_line, dg.n_bus)
+        for name, a in part.items():
+            b = ss[name].reshape(a.shape) if a.ndim == 2 else ss[name]
+            assert np.array_equal(a, b), (k, name)
+        assert res[k]["sweeps"] == rs["sweeps"] and res[k]["r"] == rs["r"] and res[k]["s"] == rs["s"]
+        Q = qpm.build_qp(g, x, pik, 0.05)
+        ref = admm.solve(g, Q, admm.Rho.scalar(g, 2e4), nsw, eps, eps)
+        assert abs(res[k]["sweeps"] - ref.sweeps) <= 1
+        if res[k]["sweeps"] == ref.sweeps:
+            G, L = g.n_gen, g.n_line
+            assert rel_err(part["xl"].T, ref.state.xl) <= TOL and rel_err(part["dw"], ref.state.dw) <= TOL
+            assert rel_err(part["lam_g"].T, ref.state.lam_g) <= TOL
+
+
+def test_batch_isolates_a_failed_scenario():
+    """A scenario whose QP cannot be built (non-finite iterate) is reported
+    per scenario and not solved; the others match their solo runs bit for
+    bit, in the ADMM solve and in the SQP step (the failed one is rejected
+    with its radius halved)."""
+    print("[gpu] batch with a failed scenario", flush=True)
+    from paper_2310_13143_amd import _abi
+    grids = _batch_cases()
+    DeviceGrid = _dev()
+    pts = [start_point(g, pi_scale=20.0, seed=k) for k, g in enumerate(grids)]
+    bad = 1
+    pts[bad][0].w = pts[bad][0].w.copy()
+    pts[bad][0].w[2] = np.nan
+    dg = DeviceGrid(grids)
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    pi = np.concatenate([p[1] for p in pts])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), pi)
+    dg.qp_build(xb, 0.05)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    dg.admm_solve(100, 1e-6, 1e-6, sweep_mode=1, block_size=64, sync=False)
+    res = dg.admm_results()  # a batch reports failures per scenario, no exception
+    assert res[bad]["status"] == -4 and res[bad]["outcome"] == _abi.ADMM_FAILED and res[bad]["sweeps"] == 0
+    st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    for k, g in enumerate(grids):
+        if k == bad:
+            continue
+        assert res[k]["status"] == 0 and res[k]["outcome"] != _abi.ADMM_FAILED
+        x, pik = pts[k]
+        solo = DeviceGrid(g)
+        xs = solo.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pik)
+        solo.qp_build(xs, 0.05)
+        solo.admm_init(*solo.rho_scalar(2e4))
+        rs = solo.admm_solve(100, 1e-6, 1e-6, sweep_mode=1, block_size=64)
+        ss = {k2: v.cpu().numpy() for k2, v in solo.admm_state().items()}
+        for name, a in _slice_state(st, dg, k, dg.n_gen, dg.n_line, dg.n_bus).items():
+            b = ss[name].reshape(a.shape) if a.ndim == 2 else ss[name]
+            assert np.array_equal(a, b), (k, name)
+        assert res[k]["sweeps"] == rs["sweeps"]
+    # SQP step of the batch: the failed scenario is rejected, radius halved
+    dg.set_delta(0.05)
+    rho_g, rho_l = dg.rho_scalar(2e4)
+    outs = dg.sqp_step_batch(xb, rho_g, rho_l, max_sweeps=100, eps=0.0, block_size=64)
+    assert outs[bad]["status"] == -4 and outs[bad]["accepted"] == 0 and outs[bad]["delta"] == 0.025
+    assert all(outs[k]["status"] == 0 for k in range(len(grids)) if k != bad)
+    # a single grid still raises
+    from paper_2310_13143_amd import AcopfError
+    x, pik = pts[bad]
+    solo = DeviceGrid(grids[bad])
+    xs = solo.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pik)
+    solo.qp_build(xs, 0.05)
+    solo.admm_init(*solo.rho_scalar(2e4))
+    with pytest.raises(AcopfError) as e:
+        solo.admm_solve(10, sweep_mode=1, block_size=64)
+    assert e.value.code == -4
+
+
+def test_batch_sqp_matches_oracle_per_scenario():
+    """Batched SQP iterations: every scenario follows its own oracle SQP."""
+    print("[gpu] batch sqp", flush=True)
+    grids = _batch_cases()[:3]
+    params = sqp.SqpParams(max_iter=4, max_sweeps=200, eps_pri=0.0, eps_dual=0.0, delta0=0.05, tol_step=0.0,
+                           tol_primal=0.0, tol_dual=0.0)
+    refs, pts = [], []
+    for g in grids:
+        x0, _ = start_point(g)
+        pts.append(x0)
+        refs.append(sqp.solve(g, params, x0=x0))
+    dg = _dev()(grids)
+    cat = lambda name: np.concatenate([getattr(p, name) for p in pts])
+    x = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
+    dg.set_delta(params.delta0)
+    rho_g, rho_l = dg.rho_scalar(params.rho)
+    for it in range(params.max_iter):
+        outs = dg.sqp_step_batch(x, rho_g, rho_l, mu=params.mu_merit, warm_start=it > 0,
+                                 max_sweeps=params.max_sweeps, eps=0.0, block_size=64)
+        for k, ref in enumerate(refs):
+            rec = ref.records[it]
+            assert bool(outs[k]["accepted"]) == rec.accepted, (k, it)
+            assert abs(outs[k]["delta"] - rec.delta) <= 1e-12 * rec.delta, (k, it)
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    bo = dg.offsets["bus"]
+    for k, ref in enumerate(refs):
+        assert rel_err(xf["w"][bo[k]:bo[k + 1]], ref.x.w) <= TOL

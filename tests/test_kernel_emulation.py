@@ -84,7 +84,7 @@ class HostGrid:
         vals.append(self.arr(g.gbus, np.int32))
         for n in _abi.GRID_GEN_FIELDS:
             vals.append(self.arr(getattr(g, n)))
-        self.c = _abi.Grid(g.n_bus, g.n_line, g.n_gen, g.ref, *vals)
+        self.c = _abi.Grid(g.n_bus, g.n_line, g.n_gen, g.ref, 1, 0, *vals)
 
     def arr(self, a, dt=np.float64):
         a = np.ascontiguousarray(a, dtype=dt)
