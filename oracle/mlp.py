@@ -1,21 +1,28 @@
 """Learned warm start for the ADMM solve (not in the paper): a small
-per-component MLP that predicts initial multipliers of a component's
-couplings from local data, trained on multipliers the method itself
-produces.  Plain FP64 NumPy restatement of the network the HIP path trains
-in FP32.
+per-component MLP that predicts, from local data, the correction to the
+plain start of a component's coupling multipliers (at the first QP of an
+SQP run, where the plain start is zero) and a factor on each coupling's
+penalty, trained on traces the method itself produces.  Plain FP64 NumPy
+restatement of what the HIP path computes (the network in FP32).
 
 Network: x -> relu(W1 x + b1) -> relu(W2 h1 + b2) -> W3 h2 + b3, loss the
 mean squared error over samples and outputs, optimiser Adam (Kingma and Ba,
-2015) with bias correction.
+2015) with bias correction.  Training runs on standardised inputs and
+outputs (per-column mean and standard deviation of the training set,
+outputs clipped to +-5 deviations); the affine maps are then folded into
+the first and last layers, so the trained network takes raw features and
+returns raw outputs.
 
-Features (per component, from the grid, the loads and the SQP iterate):
-  line (16): p_d, q_d at both ends; g_ij, b_ij, g_ii, b_ii, g_jj, b_jj
+Features (per component, from the grid, the loads, the SQP iterate and the
+multipliers of the previous solve):
+  line (25): p_d, q_d at both ends; g_ij, b_ij, g_ii, b_ii, g_jj, b_jj
              scaled by 1/100; w_i, w_j, wR, wI; sin of the angle
-             difference; s_max_ij;
-  gen (8):   p_d, q_d of its bus; cost2 / 1e4; cost1 / 1e3; p_g, q_g;
-             p_max, q_max.
-Targets: the component's coupling multipliers (8 per line, 2 per generator)
-divided by 1e3.
+             difference; s_max_ij; the 8 previous multipliers / 1e3; 1 at
+             the first QP of a run, else 0;
+  gen (11):  p_d, q_d of its bus; cost2 / 1e4; cost1 / 1e3; p_g, q_g;
+             p_max, q_max; the 2 previous multipliers / 1e3; the flag.
+Targets: (final multiplier - starting multiplier) / 1e3 of each coupling
+(8 per line, 2 per generator), then the log penalty factors.
 
 Test infrastructure only (see the package docstring).
 """
@@ -25,22 +32,28 @@ from dataclasses import dataclass
 import numpy as np
 
 LAM_SCALE = 1e3
-N_LINE_FEAT = 16
-N_GEN_FEAT = 8
+N_LINE_FEAT = 25
+N_GEN_FEAT = 11
+STD_FLOOR = 1e-4
+OUT_CLIP = 5.0
 
 
-def line_features(grid, x) -> np.ndarray:
+def line_features(grid, x, lam_prev_l, first) -> np.ndarray:
+    """lam_prev_l: (L, 8) multipliers the plain start would use; first: bool."""
     f, t = grid.f, grid.t
     ph = x.th[f] - x.th[t]
     cols = [grid.pd[f], grid.qd[f], grid.pd[t], grid.qd[t],
             grid.gij / 100, grid.bij / 100, grid.gii / 100, grid.bii / 100, grid.gjj / 100, grid.bjj / 100,
             x.w[f], x.w[t], x.wR, x.wI, np.sin(ph), grid.smax_ij]
+    cols += [lam_prev_l[:, c] / LAM_SCALE for c in range(8)]
+    cols += [np.full(grid.n_line, 1.0 if first else 0.0)]
     return np.stack(cols, 1)
 
 
-def gen_features(grid, x) -> np.ndarray:
+def gen_features(grid, x, lam_prev_g, first) -> np.ndarray:
     b = grid.gbus
-    cols = [grid.pd[b], grid.qd[b], grid.cost2 / 1e4, grid.cost1 / 1e3, x.pg, x.qg, grid.pmax, grid.qmax]
+    cols = [grid.pd[b], grid.qd[b], grid.cost2 / 1e4, grid.cost1 / 1e3, x.pg, x.qg, grid.pmax, grid.qmax,
+            lam_prev_g[:, 0] / LAM_SCALE, lam_prev_g[:, 1] / LAM_SCALE, np.full(grid.n_gen, 1.0 if first else 0.0)]
     return np.stack(cols, 1)
 
 
@@ -110,6 +123,31 @@ def adam_step(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def column_stats(X):
+    """Per-column mean and standard deviation (population) of samples X
+    (n, F); deviations below STD_FLOOR are raised to it."""
+    X = np.asarray(X, dtype=np.float64)
+    mean = X.mean(0)
+    std = np.sqrt(np.mean((X - mean) ** 2, 0))
+    return mean, np.maximum(std, STD_FLOOR)
+
+
+def standardize(X, mean, std, clip=0.0):
+    """(X - mean) / std per column, clipped to +-clip if clip > 0."""
+    Z = (np.asarray(X, dtype=np.float64) - mean) / std
+    return np.clip(Z, -clip, clip) if clip > 0 else Z
+
+
+def fold(p: Params, in_mean, in_std, out_mean, out_std) -> Params:
+    """The network x -> out_std * net((x - in_mean) / in_std) + out_mean as
+    one network: the input map folded into W1, b1, the output map into W3, b3."""
+    W1 = p.W1 / in_std[None, :]
+    b1 = p.b1 - W1 @ in_mean
+    W3 = p.W3 * out_std[:, None]
+    b3 = p.b3 * out_std + out_mean
+    return Params(W1, b1, p.W2.copy(), p.b2.copy(), W3, b3)
+
+
 # ---------------------------------------------------------------------------
 # Training targets and the decoding of network outputs into an ADMM start.
 #
@@ -161,22 +199,24 @@ def log_rho_factor(rho, sum_r, sum_s):
     return np.log(np.clip(np.sqrt(ratio), 1.0 / RHO_CLIP, RHO_CLIP))
 
 
-def targets(rho, lam_g, lam_l, sums):
-    """Training targets of one traced solve: (line rows (L, 16), gen rows (G, 4))."""
+def targets(rho, lam_g, lam_l, lam0_g, lam0_l, sums):
+    """Training targets of one traced solve that started from (lam0_g,
+    lam0_l) and ended at (lam_g, lam_l): (line rows (L, 16), gen rows (G, 4))."""
     rg, sg, rl, sl = sums
-    tl = np.concatenate([lam_l / LAM_SCALE, log_rho_factor(rho.l, rl, sl)], 1)
-    tg = np.concatenate([lam_g / LAM_SCALE, log_rho_factor(rho.g, rg, sg)], 1)
+    tl = np.concatenate([(lam_l - lam0_l) / LAM_SCALE, log_rho_factor(rho.l, rl, sl)], 1)
+    tg = np.concatenate([(lam_g - lam0_g) / LAM_SCALE, log_rho_factor(rho.g, rg, sg)], 1)
     return tl, tg
 
 
-def decode(out_l, out_g, rho_l0, rho_g0, lam_l_plain, lam_g_plain, use_rho):
-    """ADMM start from network outputs: multipliers out * LAM_SCALE, penalties
-    rho0 exp(out) with out clipped to +-log(RHO_CLIP).  A non-finite output
-    falls back to the plain start of that coupling (the previous solve's
-    multiplier, the base penalty).  Returns (lam_l, lam_g, rho_l, rho_g)."""
-    def lam(out, plain):
-        v = np.asarray(out, dtype=np.float64) * LAM_SCALE
-        return np.where(np.isfinite(v), v, plain)
+def decode(out_l, out_g, rho_l0, rho_g0, lam_l_prev, lam_g_prev, use_lam, use_rho):
+    """ADMM start from network outputs: multipliers lam_prev + out *
+    LAM_SCALE if use_lam (else lam_prev, the plain start), penalties rho0
+    exp(out) with out clipped to +-log(RHO_CLIP) if use_rho (else rho0).  A
+    non-finite output falls back to the plain start of that coupling.
+    Returns (lam_l, lam_g, rho_l, rho_g)."""
+    def lam(out, prev):
+        v = prev + np.asarray(out, dtype=np.float64) * LAM_SCALE
+        return np.where(np.isfinite(v) & bool(use_lam), v, prev)
 
     def rho(out, r0):
         o = np.asarray(out, dtype=np.float64)
@@ -184,5 +224,5 @@ def decode(out_l, out_g, rho_l0, rho_g0, lam_l_plain, lam_g_plain, use_rho):
         v = r0 * np.exp(c)
         return np.where(np.isfinite(o) & bool(use_rho), v, r0)
 
-    return (lam(out_l[:, :8], lam_l_plain), lam(out_g[:, :2], lam_g_plain),
+    return (lam(out_l[:, :8], lam_l_prev), lam(out_g[:, :2], lam_g_prev),
             rho(out_l[:, 8:], rho_l0), rho(out_g[:, 2:], rho_g0))

@@ -121,25 +121,65 @@ def test_decode_applies_scales_clip_and_guard():
     out_l[0, 8:] = [0.0, 1.0, -1.0, 5.0, -5.0, np.log(2.0), np.nan, 0.0]
     out_l[1, 3] = np.inf
     out_g = np.array([[1.0, np.nan, 0.5, np.nan]])
-    plain_l = np.full((2, 8), -7.0)
-    plain_g = np.full((1, 2), 9.0)
-    lam_l, lam_g, rho_l, rho_g = mlp.decode(out_l, out_g, 100.0, 50.0, plain_l, plain_g, True)
-    assert np.allclose(lam_l[0], np.arange(8) * 500.0)
-    assert lam_l[1, 3] == -7.0 and np.all(lam_l[1, [0, 1, 2, 4, 5, 6, 7]] == 0.0)
+    prev_l = np.full((2, 8), -7.0)
+    prev_g = np.full((1, 2), 9.0)
+    lam_l, lam_g, rho_l, rho_g = mlp.decode(out_l, out_g, 100.0, 50.0, prev_l, prev_g, True, True)
+    # multipliers: the plain start plus the scaled correction
+    assert np.allclose(lam_l[0], -7.0 + np.arange(8) * 500.0)
+    assert lam_l[1, 3] == -7.0 and np.all(lam_l[1, [0, 1, 2, 4, 5, 6, 7]] == -7.0)
     assert np.allclose(rho_l[0], 100.0 * np.array([1.0, np.e, 1 / np.e, 10.0, 0.1, 2.0, 1.0, 1.0]))
-    assert lam_g[0, 0] == 1000.0 and lam_g[0, 1] == 9.0
+    assert lam_g[0, 0] == 1009.0 and lam_g[0, 1] == 9.0
     assert rho_g[0, 0] == pytest.approx(50.0 * np.exp(0.5)) and rho_g[0, 1] == 50.0
-    _, _, rho_l2, rho_g2 = mlp.decode(out_l, out_g, 100.0, 50.0, plain_l, plain_g, False)
+    lam_l2, lam_g2, rho_l2, rho_g2 = mlp.decode(out_l, out_g, 100.0, 50.0, prev_l, prev_g, False, False)
+    assert np.all(lam_l2 == -7.0) and np.all(lam_g2 == 9.0)
     assert np.all(rho_l2 == 100.0) and np.all(rho_g2 == 50.0)
+
+
+def test_targets_are_the_scaled_change_of_the_multipliers():
+    rho = admm.Rho(np.full((1, 2), 4.0), np.full((1, 8), 4.0))
+    lam0_l, lam_l = np.arange(8.0)[None] * 100, np.arange(8.0)[None] * 300
+    lam0_g, lam_g = np.array([[5.0, -5.0]]), np.array([[2005.0, 995.0]])
+    sums = (np.ones((1, 2)), np.full((1, 2), 4.0), np.ones((1, 8)), np.full((1, 8), 16.0))
+    tl, tg = mlp.targets(rho, lam_g, lam_l, lam0_g, lam0_l, sums)
+    assert np.allclose(tl[0, :8], np.arange(8) * 0.2) and np.allclose(tg[0, :2], [2.0, 1.0])
+    # log factors: sqrt(4 * 1 / 4) = 1, sqrt(4 * 1 / 16) = 1/2
+    assert np.allclose(tg[0, 2:], 0.0, atol=1e-6) and np.allclose(tl[0, 8:], np.log(0.5), atol=1e-6)
+
+
+def test_column_stats_and_standardize_hand_cases():
+    X = np.array([[1.0, 7.0], [2.0, 7.0], [3.0, 7.0], [4.0, 7.0]])
+    mean, std = mlp.column_stats(X)
+    assert np.allclose(mean, [2.5, 7.0]) and np.allclose(std, [np.sqrt(1.25), mlp.STD_FLOOR])
+    Z = mlp.standardize(np.array([[2.5 + 10 * np.sqrt(1.25), 7.0]]), mean, std, clip=5.0)
+    assert np.allclose(Z, [[5.0, 0.0]])
+    assert np.allclose(mlp.standardize(X, mean, std)[:, 0], (X[:, 0] - 2.5) / np.sqrt(1.25))
+
+
+def test_fold_equals_the_standardised_network():
+    """Folding the input and output maps into the first and last layers
+    gives the same function as applying them around the network."""
+    rng = np.random.default_rng(11)
+    p = _random_net(rng, 25, 64, 16)
+    X = rng.standard_normal((50, 25)) * rng.uniform(0.01, 3, 25) + rng.uniform(-2, 2, 25)
+    mi, si = X.mean(0), X.std(0)
+    mo, so = rng.uniform(-1, 1, 16), rng.uniform(0.1, 2, 16)
+    y_ref, _ = mlp.forward(p, (X - mi) / si)
+    y_ref = y_ref * so + mo
+    y, _ = mlp.forward(mlp.fold(p, mi, si, mo, so), X)
+    assert np.allclose(y, y_ref, rtol=1e-12, atol=1e-12)
 
 
 def test_features_have_the_documented_columns():
     g = tiny_grid(5)
     x, _ = start_point(g)
-    fl, fg = mlp.line_features(g, x), mlp.gen_features(g, x)
+    rng = np.random.default_rng(2)
+    pl, pg = rng.normal(0, 1e3, (g.n_line, 8)), rng.normal(0, 1e3, (g.n_gen, 2))
+    fl, fg = mlp.line_features(g, x, pl, True), mlp.gen_features(g, x, pg, False)
     assert fl.shape == (g.n_line, mlp.N_LINE_FEAT) and fg.shape == (g.n_gen, mlp.N_GEN_FEAT)
     l = g.n_line - 1
     assert fl[l, 0] == g.pd[g.f[l]] and fl[l, 3] == g.qd[g.t[l]] and fl[l, 12] == x.wR[l]
     assert fl[l, 14] == np.sin(x.th[g.f[l]] - x.th[g.t[l]]) and fl[l, 15] == g.smax_ij[l]
+    assert np.allclose(fl[:, 16:24], pl / 1e3) and np.all(fl[:, 24] == 1.0)
     k = g.n_gen - 1
     assert fg[k, 0] == g.pd[g.gbus[k]] and fg[k, 4] == x.pg[k] and fg[k, 7] == g.qmax[k]
+    assert np.allclose(fg[:, 8:10], pg / 1e3) and np.all(fg[:, 10] == 0.0)
