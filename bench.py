@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=20, help="oracle sweeps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--train-scen", type=int, default=512, help="warmstart: training scenarios")
     ap.add_argument("--test-scen", type=int, default=128, help="warmstart: held-out scenarios")
+    ap.add_argument("--val-scen", type=int, default=64, help="warmstart: validation scenarios (policy choice)")
     ap.add_argument("--sqp-iters", type=int, default=15, help="warmstart: SQP iterations per scenario")
     ap.add_argument("--train-steps", type=int, default=3000, help="warmstart: full-batch Adam steps")
     args = ap.parse_args()
@@ -237,10 +238,12 @@ def ring14_scenarios(seeds):
 
 def bench_warmstart(args):
     """Learned warm start: trace the plain batched SQP on the training
-    scenarios, train the line and generator networks on the device, then
-    solve the held-out scenarios with the plain and the learned start.  The
-    value is held-out scenarios solved to primal <= 1e-4 per second with the
-    learned start; the roofline is the network's training kernel."""
+    scenarios, train the line and generator networks on the device, choose
+    the start policy (which of multipliers / penalties come from the
+    network) on validation scenarios, then solve the held-out scenarios
+    with the plain and every learned start.  The value is held-out scenarios
+    solved to primal <= 1e-4 per second with the chosen policy; the roofline
+    is the network's training kernel."""
     import torch
     from paper_2310_13143_amd.solver import DeviceGrid
     from paper_2310_13143_amd import warmstart as W
@@ -260,23 +263,35 @@ def bench_warmstart(args):
     t_collect = time.perf_counter() - t0
     net = W.WarmStart("cuda:0", seed=7)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    log = max(1, args.train_steps // 10)
     ev[0].record()
-    hl = net.line.fit(Xl, Tl, args.train_steps, lr=3e-3, lr_end=3e-5, log_every=max(1, args.train_steps // 10))
+    hl = net.line.fit_standardized(Xl, Tl, args.train_steps, lr=3e-3, lr_end=3e-5, log_every=log)
     ev[1].record()
-    hg = net.gen.fit(Xg, Tg, args.train_steps, lr=3e-3, lr_end=3e-5, log_every=max(1, args.train_steps // 10))
+    hg = net.gen.fit_standardized(Xg, Tg, args.train_steps, lr=3e-3, lr_end=3e-5, log_every=log)
     ev[2].record()
     torch.cuda.synchronize()
     ms_line = ev[0].elapsed_time(ev[1])
     ms_gen = ev[1].elapsed_time(ev[2])
 
-    test = 60000 + np.arange(args.test_scen)
-    runs = {}
-    for name, kw in (("plain", dict(net=None)), ("learned_lam", dict(net=net, use_rho=False)),
-                     ("learned_lam_rho", dict(net=net, use_rho=True))):
-        for rep in range(2):  # the first pass warms up the launches
-            dg, x = device_batch(test)
-            r = W.run_sqp(dg, x, args.sqp_iters, **sq, **kw)
-        runs[name] = r
+    variants = (("plain", dict(net=None)),
+                ("learned_lam_first_rho", dict(net=net, lam_policy="first", use_rho=True)),
+                ("learned_lam_first", dict(net=net, lam_policy="first", use_rho=False)),
+                ("learned_rho", dict(net=net, lam_policy="none", use_rho=True)),
+                ("learned_lam_all_rho", dict(net=net, lam_policy="all", use_rho=True)))
+
+    def evaluate(seeds):
+        runs = {}
+        for name, kw in variants:
+            for rep in range(2):  # the first pass warms up the launches
+                dg, x = device_batch(seeds)
+                r = W.run_sqp(dg, x, args.sqp_iters, **sq, **kw)
+            runs[name] = r
+        return runs
+
+    # the policy is chosen on validation scenarios, then measured on held-out ones
+    val = evaluate(55000 + np.arange(args.val_scen))
+    choice = min((k for k, _ in variants if k != "plain"), key=lambda k: float(val[k]["sweeps"].sum(0).mean()))
+    runs = evaluate(60000 + np.arange(args.test_scen))
 
     def summary(r):
         hit = r["it_hit"] >= 0
@@ -287,11 +302,10 @@ def bench_warmstart(args):
                 "wall_s": r["wall"]}
 
     res = {k: summary(v) for k, v in runs.items()}
-    best = runs["learned_lam_rho"] if res["learned_lam_rho"]["sweeps_total_mean"] <= \
-        res["learned_lam"]["sweeps_total_mean"] else runs["learned_lam"]
+    best = runs[choice]
     t_all = float(np.nanmax(best["t_hit"])) if (best["it_hit"] >= 0).all() else best["wall"]
     n_line_samples, n_gen_samples = Xl.shape[1], Xg.shape[1]
-    flop_line = 3 * 2 * (16 * 64 + 64 * 64 + 64 * 16) * n_line_samples * args.train_steps
+    flop_line = 3 * 2 * (25 * 64 + 64 * 64 + 64 * 16) * n_line_samples * args.train_steps
     tflops = flop_line / (ms_line / 1e3) / 1e12
     out = {
         "metric": "held-out ACOPF scenarios solved to primal <= 1e-4 per second, learned ADMM warm start, 1 GPU",
@@ -301,9 +315,12 @@ def bench_warmstart(args):
         "config": {"workload": f"warmstart: ring14 with per-bus load factors N(1,0.1); {args.train_scen} training "
                                f"and {args.test_scen} held-out scenarios, each a batch in one workspace; "
                                f"{args.sqp_iters} SQP iterations, <= {args.sweeps} sweeps per QP, eps={args.eps:g}, "
-                               f"delta0={args.delta:g}, rho={args.rho:g}; networks 16-64-64-16 (lines) and "
-                               f"8-64-64-4 (generators), {args.train_steps} full-batch Adam steps"},
-        "warmstart": {"collect_s": t_collect, "line_samples": n_line_samples, "gen_samples": n_gen_samples,
+                               f"delta0={args.delta:g}, rho={args.rho:g}; networks 25-64-64-16 (lines) and "
+                               f"11-64-64-4 (generators), {args.train_steps} full-batch Adam steps on "
+                               "standardised data; start policy chosen on "
+                               f"{args.val_scen} validation scenarios"},
+        "warmstart": {"policy": choice, "validation": {k: summary(v) for k, v in val.items()},
+                      "collect_s": t_collect, "line_samples": n_line_samples, "gen_samples": n_gen_samples,
                       "train_ms_line": ms_line, "train_ms_gen": ms_gen, "loss_line": hl, "loss_gen": hg,
                       "results": res},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,

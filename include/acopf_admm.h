@@ -283,53 +283,60 @@ acopf_status acopf_residuals_batch(const acopf_grid* grid, const acopf_iterate* 
                                    acopf_residuals_report* out);
 
 /*
- * Learned warm start (an extension: the paper starts ADMM from a fixed or
- * the previous point).  A per-component network (acopf_mlp.h) maps local
- * features of each line and generator at the SQP iterate to the starting
- * multipliers of its couplings and a factor on each coupling's penalty.
+ * Learned warm start (an extension: the paper starts ADMM from zero or the
+ * previous point).  A per-component network (acopf_mlp.h) maps local
+ * features of each line and generator to a correction of the plain start of
+ * its couplings' multipliers (the multipliers held in the workspace: the
+ * previous solve's; zero at the first QP of an SQP run, `first`) and to a
+ * factor on each coupling's penalty.
  *
  * Line features (ACOPF_LINE_FEATURES, in order): p_d, q_d of the from bus,
  * p_d, q_d of the to bus; g_ij, b_ij, g_ii, b_ii, g_jj, b_jj divided by 100;
- * w_i, w_j, wR, wI; sin(th_i - th_j); smax_ij.  Generator features
- * (ACOPF_GEN_FEATURES): p_d, q_d of its bus; cost2 / 1e4; cost1 / 1e3; pg,
- * qg; pmax, qmax.  Outputs (ACOPF_LINE_OUTPUTS per line: 8 multipliers in
- * coupling order divided by ACOPF_WARM_LAM_SCALE, then 8 log penalty
- * factors; ACOPF_GEN_OUTPUTS per generator: the same for its 2 couplings).
- * The target penalty factor of a coupling is the residual balance of a
- * traced solve, clip(sqrt((rho sum|r_c| + ACOPF_WARM_RHO_REG) / (sum|s_c| +
+ * w_i, w_j, wR, wI; sin(th_i - th_j); smax_ij; the 8 plain-start
+ * multipliers divided by ACOPF_WARM_LAM_SCALE; 1 if `first`, else 0.  Generator features (ACOPF_GEN_FEATURES): p_d, q_d of its
+ * bus; cost2 / 1e4; cost1 / 1e3; pg, qg; pmax, qmax; its 2 plain-start
+ * multipliers / ACOPF_WARM_LAM_SCALE; the flag.  Outputs and training
+ * targets (ACOPF_LINE_OUTPUTS per line: the change of the 8 multipliers over
+ * a solve divided by ACOPF_WARM_LAM_SCALE, then 8 log penalty factors;
+ * ACOPF_GEN_OUTPUTS per generator: the same for its 2 couplings).  The
+ * target penalty factor of a coupling is the residual balance of a traced
+ * solve, clip(sqrt((rho sum|r_c| + ACOPF_WARM_RHO_REG) / (sum|s_c| +
  * ACOPF_WARM_RHO_REG)), 1/ACOPF_WARM_RHO_CLIP, ACOPF_WARM_RHO_CLIP): the
  * regulariser gives factor 1 to couplings that never move (the reference
- * angle), whatever rounding noise their sums hold.  All feature, target and output arrays are FP32,
- * feature-major: feature f of component c at a[f * ld + c].
+ * angle), whatever rounding noise their sums hold.  All feature, target and
+ * output arrays are FP32, feature-major: feature f of component c at
+ * a[f * ld + c].
  */
-#define ACOPF_LINE_FEATURES 16
-#define ACOPF_GEN_FEATURES 8
+#define ACOPF_LINE_FEATURES 25
+#define ACOPF_GEN_FEATURES 11
 #define ACOPF_LINE_OUTPUTS 16
 #define ACOPF_GEN_OUTPUTS 4
 #define ACOPF_WARM_LAM_SCALE 1e3
 #define ACOPF_WARM_RHO_CLIP 10.0
 #define ACOPF_WARM_RHO_REG 1e-6
 
-/* Features of every line and generator at iterate x. */
-acopf_status acopf_features(const acopf_grid* grid, const acopf_iterate* x, float* line_x, int64_t ld_line,
-                            float* gen_x, int64_t ld_gen, void* stream);
+/* Features of every line and generator at iterate x (the workspace's
+ * multipliers as the plain start, or zero if first = 1). */
+acopf_status acopf_features(const acopf_grid* grid, const acopf_iterate* x, void* workspace, int32_t first,
+                            float* line_x, int64_t ld_line, float* gen_x, int64_t ld_gen, void* stream);
 
-/* Training targets from the last solve in the workspace: its final
- * multipliers and, from its trace sums (a solve with trace = 1), the
- * target log penalty factors. */
+/* Training targets from the last solve in the workspace: the change of its
+ * multipliers from their start to their end and, from its trace sums (a
+ * solve with trace = 1), the target log penalty factors. */
 acopf_status acopf_warm_targets(const acopf_grid* grid, void* workspace, float* line_t, int64_t ld_line,
                                 float* gen_t, int64_t ld_gen, void* stream);
 
-/* Starting point from network outputs: multipliers lam = y *
- * ACOPF_WARM_LAM_SCALE; penalties rho0 exp(y) with y clipped to
+/* Starting point from network outputs y: multipliers lam + y *
+ * ACOPF_WARM_LAM_SCALE if use_lam, else lam (lam = the plain start: the
+ * workspace's multipliers, or zero if first = 1); penalties rho0 exp(y) with y clipped to
  * +-log(ACOPF_WARM_RHO_CLIP) if use_rho, else rho0 (rho_l0 for lines, rho_g0
  * for generators, > 0).  A non-finite output keeps the plain start of its
- * coupling: the multiplier held in the workspace (the previous solve's) or
- * the base penalty.  Outputs (device, layout of acopf_admm_state) feed
+ * coupling.  Outputs (device, layout of acopf_admm_state) feed
  * acopf_admm_init or acopf_sqp_step with ACOPF_START_GIVEN. */
 acopf_status acopf_warm_decode(const acopf_grid* grid, void* workspace, const float* line_y, int64_t ld_line,
-                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t use_rho,
-                               double* lam_l, double* lam_g, double* rho_l, double* rho_g, void* stream);
+                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t first,
+                               int32_t use_lam, int32_t use_rho, double* lam_l, double* lam_g, double* rho_l,
+                               double* rho_g, void* stream);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,29 @@ acopf_status acopf_mlp_gradient(const float* theta, int32_t n_in, int32_t n_out,
 acopf_status acopf_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t count, int32_t t,
                             float lr, float beta1, float beta2, float eps, void* stream);
 
+/* Standardisation used for training (an affine map per input and per
+ * output, afterwards folded into the network so that it takes raw inputs
+ * and returns raw outputs). */
+#define ACOPF_MLP_STD_FLOOR 1e-4
+
+/* Mean and standard deviation (population; deviations below
+ * ACOPF_MLP_STD_FLOOR raised to it) of each of `rows` rows of X over its
+ * first n columns; mean and stdev: rows doubles each (device).  FP64 sums
+ * in a fixed order. */
+acopf_status acopf_mlp_feature_stats(const float* X, int32_t rows, int64_t ldx, int64_t n, double* mean,
+                                    double* stdev, void* stream);
+
+/* In place: X[r][i] <- (X[r][i] - mean[r]) / stdev[r], clipped to +-clip if
+ * clip > 0 (0 = no clip). */
+acopf_status acopf_mlp_standardize(float* X, int32_t rows, int64_t ldx, int64_t n, const double* mean,
+                                   const double* stdev, double clip, void* stream);
+
+/* Fold the input map x -> (x - in_mean) / in_std (n_in entries) into W1, b1
+ * and the output map y -> out_std y + out_mean (n_out entries) into W3, b3
+ * of theta, in place (FP64 arithmetic, FP32 result). */
+acopf_status acopf_mlp_fold(float* theta, int32_t n_in, int32_t n_out, const double* in_mean, const double* in_std,
+                            const double* out_mean, const double* out_std, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ HESSIAN_PSD, HESSIAN_RAW = 0, 1
 SWEEP_PERSISTENT, SWEEP_LAUNCHES = 0, 1
 ADMM_CONVERGED, ADMM_MAX_SWEEPS, ADMM_FAILED = 0, 1, 2
 START_ZERO, START_PREVIOUS, START_GIVEN = 0, 1, 2
-LINE_FEATURES, GEN_FEATURES, LINE_OUTPUTS, GEN_OUTPUTS = 16, 8, 16, 4
+LINE_FEATURES, GEN_FEATURES, LINE_OUTPUTS, GEN_OUTPUTS = 25, 11, 16, 4
 WARM_LAM_SCALE, WARM_RHO_CLIP = 1e3, 10.0
 MLP_HIDDEN = 64
 
@@ -77,7 +77,8 @@ EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_se
            "acopf_admm_result_get", "acopf_admm_state_get", "acopf_step", "acopf_sqp_step",
            "acopf_sqp_step_batch", "acopf_residuals", "acopf_residuals_batch", "acopf_features",
            "acopf_warm_targets", "acopf_warm_decode", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes",
-           "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_adam")
+           "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_adam", "acopf_mlp_feature_stats",
+           "acopf_mlp_standardize", "acopf_mlp_fold")
 SIZE_RETURNING = ("acopf_workspace_bytes", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes")
 
 
@@ -120,10 +121,11 @@ def load(path: str = LIB_PATH):
     lib.acopf_sqp_step.argtypes = [P(Grid), P(Iterate), P(Iterate), c_void_p, c_void_p, P(SqpParams), c_void_p,
                                    c_void_p, P(SqpState)]
     lib.acopf_residuals.argtypes = [P(Grid), P(Iterate), c_void_p, c_void_p, P(ResidualsReport)]
-    lib.acopf_features.argtypes = [P(Grid), P(Iterate), c_void_p, c_int64, c_void_p, c_int64, c_void_p]
+    lib.acopf_features.argtypes = [P(Grid), P(Iterate), c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                                   c_void_p]
     lib.acopf_warm_targets.argtypes = [P(Grid), c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     lib.acopf_warm_decode.argtypes = [P(Grid), c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_double, c_double,
-                                      c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+                                      c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.acopf_mlp_param_count.restype = c_size_t
     lib.acopf_mlp_param_count.argtypes = [c_int32, c_int32]
     lib.acopf_mlp_scratch_bytes.restype = c_size_t
@@ -134,6 +136,10 @@ def load(path: str = LIB_PATH):
                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.acopf_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_float, c_float,
                                    c_float, c_float, c_void_p]
+    lib.acopf_mlp_feature_stats.argtypes = [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.acopf_mlp_standardize.argtypes = [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_double,
+                                          c_void_p]
+    lib.acopf_mlp_fold.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     for name in EXPORTS[1:]:
         if name not in SIZE_RETURNING:
             getattr(lib, name).restype = c_int32

@@ -562,22 +562,33 @@ int blocks_for(long long n, int bs) {
 }
 
 // ---------------------------------------------------------------- learned warm start
+static_assert(ACOPF_LINE_FEATURES == 16 + 8 + 1, "line feature layout");
+static_assert(ACOPF_GEN_FEATURES == 8 + 2 + 1, "generator feature layout");
+
 // Features of every line and generator (FP32, feature-major with leading
-// dimensions ldl, ldg).
-__global__ void k_features(acopf_grid g, acopf_iterate x, float* fl, long long ldl, float* fg, long long ldg) {
-  for (int l = gtid(); l < g.n_line; l += gstride()) {
+// dimensions ldl, ldg); the previous multipliers are the workspace's, zero
+// at the first QP of a run.
+__global__ void k_features(acopf_grid g, acopf_iterate x, Workspace w, int first, float* fl, long long ldl,
+                           float* fg, long long ldg) {
+  const int L = g.n_line, G = g.n_gen;
+  const double flag = first ? 1.0 : 0.0;
+  for (int l = gtid(); l < L; l += gstride()) {
     const int i = g.line_from[l], j = g.line_to[l];
-    const double v[ACOPF_LINE_FEATURES] = {g.pd[i], g.qd[i], g.pd[j], g.qd[j],
-                                           g.gij[l] / 100.0, g.bij[l] / 100.0, g.gii[l] / 100.0, g.bii[l] / 100.0,
-                                           g.gjj[l] / 100.0, g.bjj[l] / 100.0, x.w[i], x.w[j], x.wR[l], x.wI[l],
-                                           sin(x.th[i] - x.th[j]), g.smax_ij[l]};
+    const double v[16] = {g.pd[i], g.qd[i], g.pd[j], g.qd[j],
+                          g.gij[l] / 100.0, g.bij[l] / 100.0, g.gii[l] / 100.0, g.bii[l] / 100.0,
+                          g.gjj[l] / 100.0, g.bjj[l] / 100.0, x.w[i], x.w[j], x.wR[l], x.wI[l],
+                          sin(x.th[i] - x.th[j]), g.smax_ij[l]};
 #pragma unroll
-    for (int f = 0; f < ACOPF_LINE_FEATURES; ++f) fl[f * ldl + l] = (float)v[f];
+    for (int f = 0; f < 16; ++f) fl[f * ldl + l] = (float)v[f];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) fl[(16 + c) * ldl + l] = first ? 0.0f : (float)(w.lam_l[c * L + l] / kLamScale);
+    fl[24 * ldl + l] = (float)flag;
   }
-  for (int k = gtid(); k < g.n_gen; k += gstride()) {
+  for (int k = gtid(); k < G; k += gstride()) {
     const int b = g.gen_bus[k];
-    const double v[ACOPF_GEN_FEATURES] = {g.pd[b], g.qd[b], g.cost2[k] / 1e4, g.cost1[k] / 1e3,
-                                          x.pg[k], x.qg[k], g.pmax[k], g.qmax[k]};
+    const double v[ACOPF_GEN_FEATURES] = {g.pd[b], g.qd[b], g.cost2[k] / 1e4, g.cost1[k] / 1e3, x.pg[k], x.qg[k],
+                                          g.pmax[k], g.qmax[k], first ? 0.0 : w.lam_g[k] / kLamScale,
+                                          first ? 0.0 : w.lam_g[G + k] / kLamScale, flag};
 #pragma unroll
     for (int f = 0; f < ACOPF_GEN_FEATURES; ++f) fg[f * ldg + k] = (float)v[f];
   }
@@ -595,7 +606,7 @@ __global__ void k_targets(Workspace w, float* tl, long long ldl, float* tg, long
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int q = c * L + l;
-      tl[c * ldl + l] = (float)(w.lam_l[q] / kLamScale);
+      tl[c * ldl + l] = (float)((w.lam_l[q] - w.lam0_l[q]) / kLamScale);
       tl[(8 + c) * ldl + l] = (float)log_rho_factor(w.rho_l[q], w.tr_r_l[q], w.tr_s_l[q]);
     }
   }
@@ -603,24 +614,27 @@ __global__ void k_targets(Workspace w, float* tl, long long ldl, float* tg, long
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int q = c * G + k;
-      tg[c * ldg + k] = (float)(w.lam_g[q] / kLamScale);
+      tg[c * ldg + k] = (float)((w.lam_g[q] - w.lam0_g[q]) / kLamScale);
       tg[(2 + c) * ldg + k] = (float)log_rho_factor(w.rho_g[q], w.tr_r_g[q], w.tr_s_g[q]);
     }
   }
 }
 
-// ADMM start from network outputs; a non-finite output keeps the plain
-// start of its coupling (the workspace's multiplier, the base penalty).
+// ADMM start from network outputs: the plain start (the workspace's
+// multipliers, the base penalty) corrected by the outputs; a non-finite
+// output keeps the plain start of its coupling.
 __global__ void k_decode(Workspace w, const float* yl, long long ldl, const float* yg, long long ldg, double rho_l0,
-                         double rho_g0, int use_rho, double* lam_l, double* lam_g, double* rho_l, double* rho_g) {
+                         double rho_g0, int first, int use_lam, int use_rho, double* lam_l, double* lam_g,
+                         double* rho_l, double* rho_g) {
   const int L = w.n_line, G = w.n_gen;
   const double lmax = log(kRhoClip);
   for (int l = gtid(); l < L; l += gstride()) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int q = c * L + l;
-      const double a = (double)yl[c * ldl + l] * kLamScale;
-      lam_l[q] = isfinite(a) ? a : w.lam_l[q];
+      const double base = first ? 0.0 : w.lam_l[q];
+      const double a = base + (double)yl[c * ldl + l] * kLamScale;
+      lam_l[q] = (use_lam && isfinite(a)) ? a : base;
       const double o = (double)yl[(8 + c) * ldl + l];
       rho_l[q] = (use_rho && isfinite(o)) ? rho_l0 * exp(fmin(fmax(o, -lmax), lmax)) : rho_l0;
     }
@@ -629,8 +643,9 @@ __global__ void k_decode(Workspace w, const float* yl, long long ldl, const floa
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int q = c * G + k;
-      const double a = (double)yg[c * ldg + k] * kLamScale;
-      lam_g[q] = isfinite(a) ? a : w.lam_g[q];
+      const double base = first ? 0.0 : w.lam_g[q];
+      const double a = base + (double)yg[c * ldg + k] * kLamScale;
+      lam_g[q] = (use_lam && isfinite(a)) ? a : base;
       const double o = (double)yg[(2 + c) * ldg + k];
       rho_g[q] = (use_rho && isfinite(o)) ? rho_g0 * exp(fmin(fmax(o, -lmax), lmax)) : rho_g0;
     }
@@ -776,6 +791,8 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
     fill(w.lam_g, G2, 0.0);
     fill(w.lam_l, L8, 0.0);
   }
+  copy(w.lam0_g, w.lam_g, G2);  // the start of this solve (training targets)
+  copy(w.lam0_l, w.lam_l, L8);
   fill(w.xg, G2, 0.0);
   fill(w.xbar_g, G2, 0.0);
   fill(w.xl, L8, 0.0);
@@ -1129,16 +1146,17 @@ acopf_status acopf_residuals(const acopf_grid* g, const acopf_iterate* x, void* 
   return acopf_residuals_batch(g, x, workspace, stream, out);
 }
 
-acopf_status acopf_features(const acopf_grid* g, const acopf_iterate* x, float* line_x, int64_t ld_line,
-                            float* gen_x, int64_t ld_gen, void* stream) {
-  if (!grid_ok(g) || !iterate_ok(x) || !line_x || (g->n_gen > 0 && !gen_x))
+acopf_status acopf_features(const acopf_grid* g, const acopf_iterate* x, void* workspace, int32_t first,
+                            float* line_x, int64_t ld_line, float* gen_x, int64_t ld_gen, void* stream) {
+  if (!grid_ok(g) || !iterate_ok(x) || !workspace || !line_x || (g->n_gen > 0 && !gen_x))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_features: null argument");
   if (ld_line < g->n_line || (g->n_gen > 0 && ld_gen < g->n_gen))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_features: leading dimension below the component count");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = std::max(g->n_line, g->n_gen);
-  hipLaunchKernelGGL(k_features, dim3(blocks_for(n, 256)), dim3(256), 0, s, *g, *x, line_x, (long long)ld_line,
-                     gen_x, (long long)ld_gen);
+  Workspace w = ws_of(g, workspace);
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(n, 256)), dim3(256), 0, s, *g, *x, w, (int)(first != 0), line_x,
+                     (long long)ld_line, gen_x, (long long)ld_gen);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -1159,8 +1177,9 @@ acopf_status acopf_warm_targets(const acopf_grid* g, void* workspace, float* lin
 }
 
 acopf_status acopf_warm_decode(const acopf_grid* g, void* workspace, const float* line_y, int64_t ld_line,
-                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t use_rho,
-                               double* lam_l, double* lam_g, double* rho_l, double* rho_g, void* stream) {
+                               const float* gen_y, int64_t ld_gen, double rho_l0, double rho_g0, int32_t first,
+                               int32_t use_lam, int32_t use_rho, double* lam_l, double* lam_g, double* rho_l,
+                               double* rho_g, void* stream) {
   if (!grid_ok(g) || !workspace || !line_y || !lam_l || !rho_l ||
       (g->n_gen > 0 && (!gen_y || !lam_g || !rho_g)))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_warm_decode: null argument");
@@ -1172,7 +1191,8 @@ acopf_status acopf_warm_decode(const acopf_grid* g, void* workspace, const float
   Workspace w = ws_of(g, workspace);
   const int n = std::max(g->n_line, g->n_gen);
   hipLaunchKernelGGL(k_decode, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, line_y, (long long)ld_line, gen_y,
-                     (long long)ld_gen, rho_l0, rho_g0, (int)(use_rho != 0), lam_l, lam_g, rho_l, rho_g);
+                     (long long)ld_gen, rho_l0, rho_g0, (int)(first != 0), (int)(use_lam != 0), (int)(use_rho != 0),
+                     lam_l, lam_g, rho_l, rho_g);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }

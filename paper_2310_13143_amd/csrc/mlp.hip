@@ -328,6 +328,78 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __r
   }
 }
 
+// Mean and standard deviation (population, floored) of each row of a
+// feature-major array: one block per row, two passes in FP64, fixed-order
+// block sums.
+__device__ double block_sum_d(double v, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+  __syncthreads();
+  return t;
+}
+
+__global__ void k_feature_stats(const float* __restrict__ X, long long ldx, long long n, double floor_std,
+                               double* __restrict__ mean, double* __restrict__ stdev) {
+  __shared__ double lds[kThreads / 64];
+  const float* row = X + blockIdx.x * ldx;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) s += (double)row[i];
+  const double m = block_sum_d(s, lds) / (double)n;
+  double q = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = (double)row[i] - m;
+    q += d * d;
+  }
+  const double var = block_sum_d(q, lds) / (double)n;
+  if (threadIdx.x == 0) {
+    mean[blockIdx.x] = m;
+    stdev[blockIdx.x] = fmax(sqrt(var), floor_std);
+  }
+}
+
+// X <- (X - mean) / std per row, clipped to +-clip if clip > 0.
+__global__ void k_standardize(float* __restrict__ X, int rows, long long ldx, long long n,
+                              const double* __restrict__ mean, const double* __restrict__ stdev, double clip) {
+  const long long total = (long long)rows * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n);
+    const long long i = e - (long long)r * n;
+    double z = ((double)X[r * ldx + i] - mean[r]) / stdev[r];
+    if (clip > 0.0) z = fmin(fmax(z, -clip), clip);
+    X[r * ldx + i] = (float)z;
+  }
+}
+
+// Fold x -> (x - in_mean) / in_std into W1, b1 and y -> out_std y + out_mean
+// into W3, b3 (one block).
+__global__ void k_fold(float* __restrict__ th, int n_in, int n_out, const double* __restrict__ in_mean,
+                       const double* __restrict__ in_std, const double* __restrict__ out_mean,
+                       const double* __restrict__ out_std) {
+  const Offsets P = offsets(n_in, n_out);
+  for (int h = threadIdx.x; h < H; h += blockDim.x) {
+    double shift = 0.0;
+    for (int f = 0; f < n_in; ++f) {
+      const double wv = (double)th[P.w1 + h * n_in + f] / in_std[f];
+      th[P.w1 + h * n_in + f] = (float)wv;
+      shift += wv * in_mean[f];
+    }
+    th[P.b1 + h] = (float)((double)th[P.b1 + h] - shift);
+  }
+  for (int e = threadIdx.x; e < n_out * H; e += blockDim.x) {
+    const int o = e / H;
+    th[P.w3 + e] = (float)((double)th[P.w3 + e] * out_std[o]);
+  }
+  for (int o = threadIdx.x; o < n_out; o += blockDim.x)
+    th[P.b3 + o] = (float)((double)th[P.b3 + o] * out_std[o] + out_mean[o]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -389,6 +461,43 @@ acopf_status acopf_mlp_adam(float* theta, float* m, float* v, const float* grad,
   const int nb = (int)std::min<long long>((count + 255) / 256, 4096);
   hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, s, theta, m, v, grad, (long long)count, lr, beta1, beta2,
                      eps, c1, c2);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_mlp_feature_stats(const float* X, int32_t rows, int64_t ldx, int64_t n, double* mean,
+                                    double* stdev, void* stream) {
+  if (!X || !mean || !stdev || rows < 1 || n < 1 || ldx < n)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_feature_stats: null array, empty input or leading dimension below n");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_feature_stats, dim3(rows), dim3(kThreads), 0, s, X, (long long)ldx, (long long)n,
+                     (double)ACOPF_MLP_STD_FLOOR, mean, stdev);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_mlp_standardize(float* X, int32_t rows, int64_t ldx, int64_t n, const double* mean,
+                                   const double* stdev, double clip, void* stream) {
+  if (!X || !mean || !stdev || rows < 1 || n < 0 || ldx < n || !(clip >= 0.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_standardize: bad argument");
+  if (n == 0) return ACOPF_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long total = (long long)rows * n;
+  const int nb = (int)std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_standardize, dim3(nb), dim3(256), 0, s, X, (int)rows, (long long)ldx, (long long)n, mean,
+                     stdev, clip);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+acopf_status acopf_mlp_fold(float* theta, int32_t n_in, int32_t n_out, const double* in_mean, const double* in_std,
+                            const double* out_mean, const double* out_std, void* stream) {
+  if (!sizes_ok(n_in, n_out)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_fold: n_in must be in [1, 64], n_out in [1, 16]");
+  if (!theta || !in_mean || !in_std || !out_mean || !out_std)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_fold: null array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kThreads), 0, s, theta, (int)n_in, (int)n_out, in_mean, in_std,
+                     out_mean, out_std);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }

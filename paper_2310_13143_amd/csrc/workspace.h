@@ -108,6 +108,7 @@ struct Workspace {
   double *dw, *dth, *nu;                 // [n_bus], [n_bus], [2][n_bus]
   double *mu;                            // [2][n_line]
   int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
+  double *lam0_g, *lam0_l;               // [2][n_gen], [8][n_line] multipliers the last solve started from
   // per-coupling sums of |r_c| and |s_c| over the sweeps of a traced solve
   double *tr_r_g, *tr_s_g;               // [2][n_gen]
   double *tr_r_l, *tr_s_l;               // [8][n_line]
@@ -176,6 +177,8 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.nu = (double*)take((size_t)2 * nb * D);
   t.mu = (double*)take((size_t)2 * nl * D);
   t.line_mask = (int32_t*)take((size_t)nl * I);
+  t.lam0_g = (double*)take((size_t)2 * ng * D);
+  t.lam0_l = (double*)take((size_t)8 * nl * D);
   t.tr_r_g = (double*)take((size_t)2 * ng * D);
   t.tr_s_g = (double*)take((size_t)2 * ng * D);
   t.tr_r_l = (double*)take((size_t)8 * nl * D);

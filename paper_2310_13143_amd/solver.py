@@ -240,18 +240,20 @@ class DeviceGrid:
         return [{k: getattr(st, k) for k, _ in SqpState._fields_} for st in sts]
 
     # ------------------------------------------------------------ learned warm start
-    def features(self, x: dict, out=None, cols=(0, 0)):
-        """Line and generator features at x (FP32, feature-major).  With out =
-        (line_x, gen_x) (2-D tensors, row stride = leading dimension) they are
-        written from columns cols = (line column, gen column); otherwise new
-        tensors are returned."""
+    def features(self, x: dict, first: bool, out=None, cols=(0, 0)):
+        """Line and generator features at x (FP32, feature-major; the
+        workspace's multipliers as the previous ones; first = first QP of a
+        run).  With out = (line_x, gen_x) (2-D tensors, row stride = leading
+        dimension) they are written from columns cols = (line column, gen
+        column); otherwise new tensors are returned."""
         if out is None:
             out = (torch.empty(_abi.LINE_FEATURES, self.n_line, dtype=torch.float32, device=self.device),
                    torch.empty(_abi.GEN_FEATURES, max(self.n_gen, 1), dtype=torch.float32, device=self.device))
         fl, fg = out
         cx = self.c_iterate(x)
-        check(self.lib.acopf_features(ctypes.byref(self.cgrid), ctypes.byref(cx), _col_ptr(fl, cols[0]),
-                                      fl.stride(0), _col_ptr(fg, cols[1]), fg.stride(0), self.stream))
+        check(self.lib.acopf_features(ctypes.byref(self.cgrid), ctypes.byref(cx), self.ws, int(bool(first)),
+                                      _col_ptr(fl, cols[0]), fl.stride(0), _col_ptr(fg, cols[1]), fg.stride(0),
+                                      self.stream))
         return fl, fg
 
     def warm_targets(self, out=None, cols=(0, 0)):
@@ -265,15 +267,18 @@ class DeviceGrid:
                                           _col_ptr(tg, cols[1]), tg.stride(0), self.stream))
         return tl, tg
 
-    def warm_decode(self, yl, yg, rho_l0: float, rho_g0: float, use_rho: bool = True):
+    def warm_decode(self, yl, yg, rho_l0: float, rho_g0: float, first: bool, use_lam: bool = True,
+                    use_rho: bool = True):
         """ADMM start (lam_g, lam_l, rho_g, rho_l; FP64, layout of the ADMM
-        state) from network outputs yl [16][n_line], yg [4][n_gen]."""
+        state) from network outputs yl [16][n_line], yg [4][n_gen]: the plain
+        start (the workspace's multipliers, zero if first) corrected by the
+        outputs (if use_lam), the base penalties scaled by them (if use_rho)."""
         G, L = self.n_gen, self.n_line
         z = lambda n: torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
         lam_g, lam_l, rho_g, rho_l = z(2 * G), z(8 * L), z(2 * G), z(8 * L)
         check(self.lib.acopf_warm_decode(ctypes.byref(self.cgrid), self.ws, yl.data_ptr(), yl.stride(0),
-                                         yg.data_ptr(), yg.stride(0), float(rho_l0), float(rho_g0),
-                                         int(bool(use_rho)), lam_l.data_ptr(), lam_g.data_ptr(),
+                                         yg.data_ptr(), yg.stride(0), float(rho_l0), float(rho_g0), int(bool(first)),
+                                         int(bool(use_lam)), int(bool(use_rho)), lam_l.data_ptr(), lam_g.data_ptr(),
                                          rho_l.data_ptr(), rho_g.data_ptr(), self.stream))
         return lam_g[:2 * G], lam_l, rho_g[:2 * G], rho_l
 

@@ -90,6 +90,32 @@ class MLP:
                                       grad.data_ptr(), self.count, self.t, float(lr), float(beta1), float(beta2),
                                       float(eps), self.stream))
 
+    def fit_standardized(self, X: torch.Tensor, T: torch.Tensor, steps: int, lr: float = 3e-3,
+                         lr_end: float | None = None, log_every: int = 0, out_clip: float = 5.0):
+        """Train on standardised copies of X and T (per-row mean and
+        deviation of the training set; targets clipped to +-out_clip
+        deviations), then fold the two maps into the network so that it takes
+        raw features and returns raw outputs.  Returns the loss log."""
+        stats = {}
+        for name, A, rows in (("in", X, self.n_in), ("out", T, self.n_out)):
+            mean = torch.empty(rows, dtype=torch.float64, device=self.device)
+            std = torch.empty(rows, dtype=torch.float64, device=self.device)
+            check(self.lib.acopf_mlp_feature_stats(A.data_ptr(), rows, A.stride(0), A.shape[1], mean.data_ptr(),
+                                                   std.data_ptr(), self.stream))
+            stats[name] = (mean, std)
+        Xs, Ts = X.clone(), T.clone()
+        check(self.lib.acopf_mlp_standardize(Xs.data_ptr(), self.n_in, Xs.stride(0), Xs.shape[1],
+                                             stats["in"][0].data_ptr(), stats["in"][1].data_ptr(), 0.0, self.stream))
+        check(self.lib.acopf_mlp_standardize(Ts.data_ptr(), self.n_out, Ts.stride(0), Ts.shape[1],
+                                             stats["out"][0].data_ptr(), stats["out"][1].data_ptr(), float(out_clip),
+                                             self.stream))
+        hist = self.fit(Xs, Ts, steps, lr, lr_end, log_every)
+        check(self.lib.acopf_mlp_fold(self.theta.data_ptr(), self.n_in, self.n_out, stats["in"][0].data_ptr(),
+                                      stats["in"][1].data_ptr(), stats["out"][0].data_ptr(),
+                                      stats["out"][1].data_ptr(), self.stream))
+        self.stats = stats
+        return hist
+
     def fit(self, X: torch.Tensor, T: torch.Tensor, steps: int, lr: float = 3e-3, lr_end: float | None = None,
             log_every: int = 0):
         """Full-batch Adam for `steps` steps (learning rate decayed
@@ -123,12 +149,20 @@ class WarmStart:
         self.line = MLP(_abi.LINE_FEATURES, _abi.LINE_OUTPUTS, device, seed)
         self.gen = MLP(_abi.GEN_FEATURES, _abi.GEN_OUTPUTS, device, seed + 1)
 
-    def start(self, dg, x: dict, rho0: float, use_rho: bool = True):
-        """(lam_g, lam_l, rho_g, rho_l) for the QP at iterate x of grid dg."""
-        fl, fg = dg.features(x)
+    def fit(self, data, steps: int, lr: float = 3e-3, lr_end: float = 3e-5, log_every: int = 0):
+        """Train both networks on collected samples (see collect)."""
+        Xl, Tl, Xg, Tg = data
+        hl = self.line.fit_standardized(Xl, Tl, steps, lr, lr_end, log_every)
+        hg = self.gen.fit_standardized(Xg, Tg, steps, lr, lr_end, log_every)
+        return hl, hg
+
+    def start(self, dg, x: dict, first: bool, rho0: float, use_lam: bool = True, use_rho: bool = True):
+        """(lam_g, lam_l, rho_g, rho_l) for the QP at iterate x of grid dg
+        (the workspace holds the plain start's multipliers)."""
+        fl, fg = dg.features(x, first)
         yl = self.line.forward(fl, dg.n_line)
         yg = self.gen.forward(fg, dg.n_gen) if dg.n_gen > 0 else fg[:_abi.GEN_OUTPUTS]
-        return dg.warm_decode(yl, yg, rho0, rho0, use_rho)
+        return dg.warm_decode(yl, yg, rho0, rho0, first, use_lam, use_rho)
 
 
 def collect(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int, eps: float, block_size: int = 64,
@@ -144,7 +178,7 @@ def collect(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int,
     rho_g, rho_l = dg.rho_scalar(rho)
     dg.set_delta(delta0)
     for it in range(iters):
-        dg.features(x, (Xl, Xg), (it * L, it * G))
+        dg.features(x, it == 0, (Xl, Xg), (it * L, it * G))
         start = _abi.START_ZERO if it == 0 else _abi.START_PREVIOUS
         dg.sqp_step_batch(x, rho_g, rho_l, warm_start=start, max_sweeps=max_sweeps, eps=eps,
                           block_size=block_size, sync=False, trace=True, **sqp_kw)
@@ -153,12 +187,15 @@ def collect(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int,
 
 
 def run_sqp(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int, eps: float,
-            net: WarmStart | None = None, use_rho: bool = True, block_size: int = 64, tol: float = 1e-4,
-            **sqp_kw):
-    """Batched SQP from x for up to `iters` iterations, plain start (net=None:
-    zero, then the previous multipliers) or learned start.  Returns per-scenario records: ADMM sweeps
-    per iteration, primal infeasibility after each iteration, the iteration
-    and wall time at which it first reached tol, and the total wall time."""
+            net: WarmStart | None = None, lam_policy: str = "first", use_rho: bool = True, block_size: int = 64,
+            tol: float = 1e-4, **sqp_kw):
+    """Batched SQP from x for up to `iters` iterations, with the plain start
+    (net=None: zero, then the previous multipliers) or the learned start:
+    penalties from the network if use_rho, multipliers corrected by the
+    network at the first QP (lam_policy "first"), at every QP ("all") or
+    never ("none").  Returns per-scenario records: ADMM sweeps per
+    iteration, primal infeasibility after each iteration, the iteration and
+    wall time at which it first reached tol, and the total wall time."""
     S = dg.n_scen
     rho_g, rho_l = dg.rho_scalar(rho)
     dg.set_delta(delta0)
@@ -174,7 +211,8 @@ def run_sqp(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int,
             outs = dg.sqp_step_batch(x, rho_g, rho_l, warm_start=start, max_sweeps=max_sweeps,
                                      eps=eps, block_size=block_size, **sqp_kw)
         else:
-            lam_g, lam_l, rg, rl = net.start(dg, x, rho, use_rho)
+            use_lam = lam_policy == "all" or (lam_policy == "first" and it == 0)
+            lam_g, lam_l, rg, rl = net.start(dg, x, it == 0, rho, use_lam, use_rho)
             outs = dg.sqp_step_batch(x, rg, rl, warm_start=_abi.START_GIVEN, lam=(lam_g, lam_l),
                                      max_sweeps=max_sweeps, eps=eps, block_size=block_size, **sqp_kw)
         rep = dg.residuals_batch(x)

@@ -141,12 +141,14 @@ def test_features_trace_targets_and_decode_match_oracle():
     from paper_2310_13143_amd import _abi
     from paper_2310_13143_amd.solver import DeviceGrid
     g = tiny_grid(7)
+    G, L = g.n_gen, g.n_line
     x, pi = start_point(g, pi_scale=30.0)
     dg = DeviceGrid(g, "cuda:0")
     xi = dg.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pi)
-    fl, fg = dg.features(xi)
-    assert rel_err(fl.cpu().numpy().T, mlp.line_features(g, x)) <= 1e-7
-    assert rel_err(fg.cpu().numpy()[:, :g.n_gen].T, mlp.gen_features(g, x)) <= 1e-7
+    fl, fg = dg.features(xi, True)
+    zl, zg = np.zeros((L, 8)), np.zeros((G, 2))
+    assert rel_err(fl.cpu().numpy().T, mlp.line_features(g, x, zl, True)) <= 1e-7
+    assert rel_err(fg.cpu().numpy()[:, :G].T, mlp.gen_features(g, x, zg, True)) <= 1e-7
 
     rng = np.random.default_rng(9)
     rho = admm.Rho(rng.uniform(5e3, 5e4, (g.n_gen, 2)), rng.uniform(5e3, 5e4, (g.n_line, 8)))
@@ -159,28 +161,69 @@ def test_features_trace_targets_and_decode_match_oracle():
     ref = admm.solve(g, Q, rho, sweeps, 0.0, 0.0, state=lam0, record_states=True)
     sums = mlp.trace_sums(g, rho, lam0, ref.history)
     st = dg.admm_state()
-    G, L = g.n_gen, g.n_line
     got = [st["sum_r_g"].cpu().numpy().reshape(2, G).T, st["sum_s_g"].cpu().numpy().reshape(2, G).T,
            st["sum_r_l"].cpu().numpy().reshape(8, L).T, st["sum_s_l"].cpu().numpy().reshape(8, L).T]
     for a, b in zip(got, sums):
         assert rel_err(a, b) <= 1e-8
     tl, tg = dg.warm_targets()
-    rl, rg = mlp.targets(rho, ref.state.lam_g, ref.state.lam_l, sums)
+    rl, rg = mlp.targets(rho, ref.state.lam_g, ref.state.lam_l, lam0.lam_g, lam0.lam_l, sums)
     assert rel_err(tl.cpu().numpy().T, rl) <= 1e-6
     assert rel_err(tg.cpu().numpy()[:, :G].T, rg) <= 1e-6
 
-    # decode: network-like outputs with non-finite entries
+    # features of a later QP carry the workspace's multipliers
+    plain_l, plain_g = st["lam_l"].cpu().numpy().reshape(8, L).T, st["lam_g"].cpu().numpy().reshape(2, G).T
+    fl, fg = dg.features(xi, False)
+    assert rel_err(fl.cpu().numpy().T, mlp.line_features(g, x, plain_l, False)) <= 1e-7
+    assert rel_err(fg.cpu().numpy()[:, :G].T, mlp.gen_features(g, x, plain_g, False)) <= 1e-7
+
+    # decode: network-like outputs with non-finite entries, later and first QP
     yl = rng.normal(0, 1, (16, L)).astype(np.float32)
     yg = rng.normal(0, 1, (4, G)).astype(np.float32)
     yl[3, 1] = np.nan
     yl[10, 2] = np.inf
     yl[9, 0] = 7.0
     yg[1, 0] = np.nan
-    lam_g, lam_l, rho_g, rho_l = dg.warm_decode(torch.as_tensor(yl).cuda(), torch.as_tensor(yg).cuda(), 2e4, 3e4)
-    plain_l, plain_g = st["lam_l"].cpu().numpy().reshape(8, L).T, st["lam_g"].cpu().numpy().reshape(2, G).T
-    el, eg, erl, erg = mlp.decode(yl.T.astype(np.float64), yg.T.astype(np.float64), 2e4, 3e4, plain_l, plain_g,
-                                  True)
-    assert rel_err(lam_l.cpu().numpy().reshape(8, L).T, el) <= 1e-15
-    assert rel_err(lam_g.cpu().numpy().reshape(2, G).T, eg) <= 1e-15
-    assert rel_err(rho_l.cpu().numpy().reshape(8, L).T, erl) <= 1e-14
-    assert rel_err(rho_g.cpu().numpy().reshape(2, G).T, erg) <= 1e-14
+    for first, use_lam, use_rho in ((False, True, True), (True, True, False), (False, False, True)):
+        got = dg.warm_decode(torch.as_tensor(yl).cuda(), torch.as_tensor(yg).cuda(), 2e4, 3e4, first, use_lam,
+                             use_rho)
+        base_l, base_g = (zl, zg) if first else (plain_l, plain_g)
+        el, eg, erl, erg = mlp.decode(yl.T.astype(np.float64), yg.T.astype(np.float64), 2e4, 3e4, base_l, base_g,
+                                      use_lam, use_rho)
+        lam_g, lam_l, rho_g, rho_l = (t.cpu().numpy() for t in got)
+        assert rel_err(lam_l.reshape(8, L).T, el) <= 1e-15
+        assert rel_err(lam_g.reshape(2, G).T, eg) <= 1e-15
+        assert rel_err(rho_l.reshape(8, L).T, erl) <= 1e-14
+        assert rel_err(rho_g.reshape(2, G).T, erg) <= 1e-14
+
+
+def test_standardize_and_fold_match_oracle():
+    """Per-feature statistics, in-place standardisation with clipping, and
+    the fold of both maps into the network, against the oracle."""
+    print("[gpu] mlp stats / standardize / fold", flush=True)
+    torch = _torch()
+    from paper_2310_13143_amd import _abi
+    lib = _abi.load()
+    rng = np.random.default_rng(4)
+    n, ld = 5003, 5011
+    X = np.zeros((25, ld), np.float32)
+    X[:, :n] = rng.standard_normal((25, n)) * rng.uniform(1e-3, 5, (25, 1)) + rng.uniform(-3, 3, (25, 1))
+    X[7, :n] = 1.5  # constant feature: deviation floored
+    Xd = torch.as_tensor(X).cuda()
+    mean = torch.empty(25, dtype=torch.float64, device="cuda")
+    std = torch.empty(25, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    _abi.check(lib.acopf_mlp_feature_stats(Xd.data_ptr(), 25, ld, n, mean.data_ptr(), std.data_ptr(), stream))
+    m_ref, s_ref = mlp.column_stats(X[:, :n].T.astype(np.float64))
+    assert rel_err(mean.cpu().numpy(), m_ref) <= 1e-12 and rel_err(std.cpu().numpy(), s_ref) <= 1e-10
+    _abi.check(lib.acopf_mlp_standardize(Xd.data_ptr(), 25, ld, n, mean.data_ptr(), std.data_ptr(), 2.0, stream))
+    Z = Xd.cpu().numpy()
+    assert rel_err(Z[:, :n].T, mlp.standardize(X[:, :n].T.astype(np.float64), m_ref, s_ref, 2.0)) <= 1e-6
+    assert np.array_equal(Z[:, n:], X[:, n:])  # columns past n untouched
+
+    net, p = _net(25, 16, 5)
+    mo, so = rng.uniform(-1, 1, 16), rng.uniform(0.1, 3, 16)
+    mod, sod = torch.as_tensor(mo).cuda(), torch.as_tensor(so).cuda()
+    _abi.check(lib.acopf_mlp_fold(net.theta.data_ptr(), 25, 16, mean.data_ptr(), std.data_ptr(), mod.data_ptr(),
+                                  sod.data_ptr(), stream))
+    ref = mlp.fold(p, m_ref, s_ref, mo, so).flat()
+    assert rel_err(net.theta.cpu().numpy(), ref) <= 1e-6
