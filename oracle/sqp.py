@@ -19,7 +19,12 @@ Readings where the paper is silent (also listed in the design notes):
 * the model q(d) uses the Hessian the QP used (reduced M, possibly PSD
   projected);
 * pi and the ADMM multipliers are carried to the next iteration (warm
-  start); pi is replaced only on acceptance.
+  start); pi is replaced only on acceptance;
+* optional safeguard (``pi_if_converged``, off by default): pi is replaced
+  only if the solve also met its stop test (eps > 0).  On a QP without a
+  feasible point the ADMM multipliers grow with every sweep; their
+  estimates scale the next line Hessians without bound, until the line
+  matrices cannot be factored in FP64.
 
 Test infrastructure only (see the package docstring).
 """
@@ -47,6 +52,10 @@ class SqpParams:
     tol_step: float = 1e-6
     max_iter: int = 30
     hessian_mode: str = "psd"
+    # False: an accepted step always takes the new multiplier estimates
+    # (Algorithm 1).  True: only when the ADMM solve met its stop test (a
+    # safeguard for QPs without a feasible point; see the module docstring).
+    pi_if_converged: bool = False
 
 
 @dataclass
@@ -164,7 +173,9 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
         accepted = ared > 0 and pred > 0
         if accepted:
             x = xt
-            pi = pi_new
+            stop_set = params.eps_pri > 0 or params.eps_dual > 0
+            if not params.pi_if_converged or (stop_set and res.converged):
+                pi = pi_new
             if dn >= 0.99 * delta and ared >= 0.75 * pred:
                 delta = min(2 * delta, params.delta_max)
         else:
