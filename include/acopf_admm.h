@@ -208,6 +208,13 @@ acopf_status acopf_admm_state_get(const acopf_grid* grid, void* workspace,
 acopf_status acopf_step(const acopf_grid* grid, const acopf_iterate* x, void* workspace,
                         const acopf_iterate* d, void* stream);
 
+/* When an accepted step also replaces x.pi by the new estimates.  The
+ * paper's Algorithm 1 always does (ACOPF_PI_ALWAYS).  ACOPF_PI_IF_CONVERGED
+ * keeps the previous pi unless the solve met its stop test: on a QP without
+ * a feasible point ADMM's multipliers grow with every sweep, and their
+ * estimates would scale the next line Hessians without bound. */
+typedef enum { ACOPF_PI_ALWAYS = 0, ACOPF_PI_IF_CONVERGED = 1 } acopf_pi_update;
+
 /* Multipliers an SQP iteration's ADMM solve starts from (the primal
  * values always start at zero). */
 typedef enum {
@@ -236,6 +243,8 @@ typedef struct {
   acopf_admm_params admm;
   const double* lam_g0;  /* ACOPF_START_GIVEN: starting multipliers,      */
   const double* lam_l0;  /* layout of acopf_admm_state (device)           */
+  int32_t pi_update;     /* acopf_pi_update                               */
+  int32_t reserved;
 } acopf_sqp_params;
 
 typedef struct {

@@ -16,6 +16,7 @@ HESSIAN_PSD, HESSIAN_RAW = 0, 1
 SWEEP_PERSISTENT, SWEEP_LAUNCHES = 0, 1
 ADMM_CONVERGED, ADMM_MAX_SWEEPS, ADMM_FAILED = 0, 1, 2
 START_ZERO, START_PREVIOUS, START_GIVEN = 0, 1, 2
+PI_ALWAYS, PI_IF_CONVERGED = 0, 1
 LINE_FEATURES, GEN_FEATURES, LINE_OUTPUTS, GEN_OUTPUTS = 25, 11, 16, 4
 WARM_LAM_SCALE, WARM_RHO_CLIP = 1e3, 10.0
 MLP_HIDDEN = 64
@@ -58,7 +59,7 @@ class AdmmState(ctypes.Structure):
 class SqpParams(ctypes.Structure):
     _fields_ = [("mu", c_double), ("delta_max", c_double), ("grow_ratio", c_double),
                 ("hessian_mode", c_int32), ("warm_start", c_int32), ("admm", AdmmParams),
-                ("lam_g0", c_void_p), ("lam_l0", c_void_p)]
+                ("lam_g0", c_void_p), ("lam_l0", c_void_p), ("pi_update", c_int32), ("reserved", c_int32)]
 
 
 class SqpState(ctypes.Structure):

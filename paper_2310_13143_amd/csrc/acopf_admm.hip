@@ -401,7 +401,7 @@ __global__ void k_merit_parts(acopf_grid g, acopf_iterate x, Workspace w, acopf_
 
 // Acceptance test and trust-radius update of Algorithm 1, one block per
 // scenario (fixed-order sums over the scenario's components).
-__global__ void k_decide(Workspace w, double mu, double delta_max, double grow) {
+__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule) {
   __shared__ double lds[16];
   const int s = blockIdx.x, L = w.n_line, G = w.n_gen;
   const int l0 = w.scen_line_off[s], l1 = w.scen_line_off[s + 1];
@@ -452,6 +452,7 @@ __global__ void k_decide(Workspace w, double mu, double delta_max, double grow) 
     }
     dc->delta_out = dn;
     dc->accepted = ok ? 1 : 0;
+    dc->update_pi = (ok && (pi_rule == ACOPF_PI_ALWAYS || w.scen[s].converged)) ? 1 : 0;
     w.scen[s].delta = dn;
   }
 }
@@ -470,9 +471,11 @@ __global__ void k_apply(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspac
     x.th[i] += d.th[i];
   }
   for (int l = gtid(); l < L; l += gstride()) {
-    if (!w.decision[w.bus_scen[g.line_from[l]]].accepted) continue;
+    const SqpDecision& dc = w.decision[w.bus_scen[g.line_from[l]]];
+    if (!dc.accepted) continue;
     x.wR[l] += d.wR[l];
     x.wI[l] += d.wI[l];
+    if (!dc.update_pi) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) x.pi[k * L + l] = d.pi[k * L + l];
   }
@@ -1050,6 +1053,8 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   Workspace w = ws_of(g, workspace);
   acopf_status rc = acopf_qp_build(g, x, 0.0, p->hessian_mode, workspace, stream);
   if (rc != ACOPF_OK) return rc;
+  if (p->pi_update != ACOPF_PI_ALWAYS && p->pi_update != ACOPF_PI_IF_CONVERGED)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown multiplier update rule");
   if (p->warm_start < ACOPF_START_ZERO || p->warm_start > ACOPF_START_GIVEN)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown warm-start mode");
   if (p->warm_start == ACOPF_START_GIVEN && (!p->lam_l0 || (g->n_gen > 0 && !p->lam_g0)))
@@ -1071,7 +1076,8 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   const int bs = 256;
   const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
   hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
-  hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio);
+  hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
+                     (int)p->pi_update);
   hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w);
   HIP_TRY(hipGetLastError());
   if (!states) return ACOPF_OK;

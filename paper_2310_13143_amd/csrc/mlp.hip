@@ -29,7 +29,7 @@ namespace {
 constexpr int H = ACOPF_MLP_HIDDEN;  // hidden width (4 row tiles of 16)
 constexpr int TS = 64;               // samples per tile
 constexpr int kThreads = 256;        // 4 waves
-constexpr int kMaxBlocks = 1024;
+constexpr int kMaxBlocks = 512;  // two resident blocks per CU (54 KB of LDS each)
 constexpr int kMaxIn = 64, kMaxOut = 16;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -301,13 +301,31 @@ __global__ void __launch_bounds__(kThreads) k_mlp(const float* __restrict__ th, 
   if (tid == 0) out[P.count] = sRed[0] + sRed[1] + sRed[2] + sRed[3];
 }
 
-// grad[p] = sum over blocks of the partials in block order; loss = sum / (n n_out).
-__global__ void k_mlp_reduce(const float* __restrict__ part, int nblk, int count, float inv_count,
-                             float* __restrict__ grad, float* __restrict__ loss) {
+// grad[p] = sum over blocks of the partials; loss = sum / (n n_out), in two
+// levels with a fixed segmentation (results independent of timing):
+// k_mlp_reduce_seg sums kSegs contiguous ranges of blocks per entry (block
+// order inside a range), k_mlp_reduce_fin adds the kSegs range sums in
+// order.  A block of the first kernel serves 64 entries x 4 ranges.
+constexpr int kSegs = 32;
+
+__global__ void __launch_bounds__(256) k_mlp_reduce_seg(const float* __restrict__ part, int nblk, int count,
+                                                        float* __restrict__ seg_out) {
+  const int j = threadIdx.x & 63;
+  const int seg = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int p = blockIdx.x * 64 + j;
+  if (p > count) return;
+  const int b0 = seg * nblk / kSegs, b1 = (seg + 1) * nblk / kSegs;
+  float t = 0.0f;
+  for (int b = b0; b < b1; ++b) t += part[(size_t)b * (count + 1) + p];
+  seg_out[(size_t)seg * (count + 1) + p] = t;
+}
+
+__global__ void k_mlp_reduce_fin(const float* __restrict__ seg_in, int count, float inv_count,
+                                 float* __restrict__ grad, float* __restrict__ loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > count) return;
   float t = 0.0f;
-  for (int b = 0; b < nblk; ++b) t += part[(size_t)b * (count + 1) + p];
+  for (int k = 0; k < kSegs; ++k) t += seg_in[(size_t)k * (count + 1) + p];
   if (p < count)
     grad[p] = t;
   else
@@ -411,7 +429,7 @@ size_t acopf_mlp_param_count(int32_t n_in, int32_t n_out) {
 
 size_t acopf_mlp_scratch_bytes(int32_t n_in, int32_t n_out, int64_t n) {
   if (!sizes_ok(n_in, n_out) || n < 1) return 0;
-  return (size_t)blocks_for_samples(n) * (offsets(n_in, n_out).count + 1) * sizeof(float);
+  return (size_t)(blocks_for_samples(n) + kSegs) * (offsets(n_in, n_out).count + 1) * sizeof(float);
 }
 
 acopf_status acopf_mlp_forward(const float* theta, int32_t n_in, int32_t n_out, const float* X, int64_t ldx,
@@ -442,7 +460,10 @@ acopf_status acopf_mlp_gradient(const float* theta, int32_t n_in, int32_t n_out,
   const double denom = (double)n * (double)n_out;
   hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(kThreads), 0, s, theta, (int)n_in, (int)n_out, X,
                      (long long)ldx, T, (long long)ldt, (long long)n, nullptr, 0LL, part, (float)(2.0 / denom));
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((count + 1 + 255) / 256), dim3(256), 0, s, part, nblk, count,
+  float* seg = part + (size_t)nblk * (count + 1);  // kSegs range sums after the block partials
+  hipLaunchKernelGGL(k_mlp_reduce_seg, dim3((count + 1 + 63) / 64, kSegs / 4), dim3(256), 0, s, part, nblk, count,
+                     seg);
+  hipLaunchKernelGGL(k_mlp_reduce_fin, dim3((count + 1 + 255) / 256), dim3(256), 0, s, seg, count,
                      (float)(1.0 / denom), grad, loss);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;

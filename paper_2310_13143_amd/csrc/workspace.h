@@ -68,7 +68,7 @@ struct SqpDecision {
   double ared, pred, step_inf;
   double delta_in, delta_out;
   int accepted;
-  int pad;
+  int update_pi;           // accepted and the multiplier rule allows the new estimates
 };
 
 // Residual report (maxima; order independent).

@@ -180,9 +180,10 @@ class DeviceGrid:
                                   self.stream))
         return d
 
-    def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam):
+    def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam, pi_update):
         start = int(warm_start) if not isinstance(warm_start, bool) else int(warm_start)
         p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), start, admm)
+        p.pi_update = int(pi_update)
         if start == _abi.START_GIVEN:
             if lam is None:
                 raise ValueError("warm_start=START_GIVEN needs lam=(lam_g, lam_l)")
@@ -195,7 +196,7 @@ class DeviceGrid:
                  grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                  max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
                  block_size: int = 0, max_blocks: int = 0, d: dict | None = None, lam=None,
-                 trace: bool = False) -> dict:
+                 trace: bool = False, pi_update: int = _abi.PI_ALWAYS) -> dict:
         """One trust-region SQP iteration on the device; x is updated in place
         when the step is accepted.  warm_start: False/True (zero / previous
         multipliers) or one of _abi.START_*; lam = (lam_g, lam_l) for
@@ -207,7 +208,7 @@ class DeviceGrid:
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
                              AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size),
-                                        int(max_blocks), int(bool(trace))), lam)
+                                        int(max_blocks), int(bool(trace))), lam, pi_update)
         st = SqpState()
         st.delta = float(delta)
         cx, cd = self.c_iterate(x), self.c_iterate(d)
@@ -219,7 +220,7 @@ class DeviceGrid:
     def sqp_step_batch(self, x: dict, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
                        grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                        max_sweeps: int = 20000, eps: float = 1e-4, block_size: int = 0, d: dict | None = None,
-                       sync: bool = True, lam=None, trace: bool = False):
+                       sync: bool = True, lam=None, trace: bool = False, pi_update: int = _abi.PI_ALWAYS):
         """One SQP iteration for every scenario of the batch (radii held on
         the device, see set_delta); per-scenario decisions if sync."""
         if d is None:
@@ -229,7 +230,7 @@ class DeviceGrid:
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
                              AdmmParams(int(max_sweeps), float(eps), float(eps), _abi.SWEEP_LAUNCHES,
-                                        int(block_size), 0, int(bool(trace))), lam)
+                                        int(block_size), 0, int(bool(trace))), lam, pi_update)
         sts = (SqpState * self.n_scen)() if sync else None
         cx, cd = self.c_iterate(x), self.c_iterate(d)
         check(self.lib.acopf_sqp_step_batch(ctypes.byref(self.cgrid), ctypes.byref(cx), ctypes.byref(cd),

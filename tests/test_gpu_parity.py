@@ -239,16 +239,18 @@ def test_error_paths():
     assert e.value.code == -1
 
 
-def test_sqp_iterations_match_oracle():
+@pytest.mark.parametrize("pi_rule", [0, 1])
+def test_sqp_iterations_match_oracle(pi_rule):
     """Trust-region SQP (Algorithm 1) on the device against the oracle's SQP,
     iteration by iteration, with a fixed sweep budget per QP (no early stop,
     so both sides run the same ADMM iterations): acceptance decisions, trust
-    radii, iterates, multipliers and the residual report."""
-    print("[gpu] sqp ring14", flush=True)
+    radii, iterates, multipliers and the residual report.  pi_rule 1 (keep
+    pi unless the solve met a stop test) keeps pi at zero here."""
+    print(f"[gpu] sqp ring14 pi_rule={pi_rule}", flush=True)
     g = grid_14()
     x0, _ = start_point(g)
     params = sqp.SqpParams(max_iter=6, max_sweeps=300, eps_pri=0.0, eps_dual=0.0, delta0=0.05, tol_step=0.0,
-                           tol_primal=0.0, tol_dual=0.0)
+                           tol_primal=0.0, tol_dual=0.0, pi_if_converged=bool(pi_rule))
     ref = sqp.solve(g, params, x0=x0)
     dg = _dev()(g)
     x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, None)
@@ -256,7 +258,7 @@ def test_sqp_iterations_match_oracle():
     delta = params.delta0
     for k, rec in enumerate(ref.records):
         out = dg.sqp_step(x, delta, rho_g, rho_l, mu=params.mu_merit, delta_max=params.delta_max,
-                          warm_start=k > 0, max_sweeps=params.max_sweeps, eps=0.0)
+                          warm_start=k > 0, max_sweeps=params.max_sweeps, eps=0.0, pi_update=pi_rule)
         assert out["admm_sweeps"] == params.max_sweeps
         assert bool(out["accepted"]) == rec.accepted, k
         scale = 1.0 + abs(rec.pred)
@@ -270,7 +272,10 @@ def test_sqp_iterations_match_oracle():
     xf = {k: v.cpu().numpy() for k, v in x.items()}
     for name in ("pg", "qg", "w", "th", "wR", "wI"):
         assert rel_err(xf[name], getattr(ref.x, name)) <= TOL, name
-    assert rel_err(xf["pi"].reshape(4, -1).T, ref.pi) <= 1e-7
+    if pi_rule:
+        assert np.all(ref.pi == 0.0) and np.all(xf["pi"] == 0.0)
+    else:
+        assert rel_err(xf["pi"].reshape(4, -1).T, ref.pi) <= 1e-7
 
 
 def _batch_cases():
