@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--rho", type=float, default=2e4)
     ap.add_argument("--delta", type=float, default=0.05)
-    ap.add_argument("--mode", default="launches", choices=["persistent", "launches"])
+    ap.add_argument("--mode", default="graph", choices=["persistent", "launches", "graph"])
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--max-blocks", type=int, default=0, help="persistent grid size cap (0 = fill the device)")
     ap.add_argument("--cpu-sweeps", type=int, default=20, help="oracle sweeps timed for the CPU baseline (0 = skip)")
@@ -97,7 +97,7 @@ def main():
     import torch
     from synth.grids import WORKLOADS, power_flow_start
     from paper_2310_13143_amd.solver import DeviceGrid
-    from paper_2310_13143_amd import SWEEP_LAUNCHES, SWEEP_PERSISTENT
+    from paper_2310_13143_amd import SWEEP_GRAPH, SWEEP_LAUNCHES, SWEEP_PERSISTENT
 
     if args.workload == "batch64":
         return bench_batch(args)
@@ -111,7 +111,7 @@ def main():
     pi = np.zeros((g.n_line, 4))
     x = dg.iterate(s["pg"], s["qg"], s["w"], s["th"], s["wR"], s["wI"], pi)
     rho_g, rho_l = dg.rho_scalar(args.rho)
-    mode = SWEEP_PERSISTENT if args.mode == "persistent" else SWEEP_LAUNCHES
+    mode = {"persistent": SWEEP_PERSISTENT, "launches": SWEEP_LAUNCHES, "graph": SWEEP_GRAPH}[args.mode]
     stream = torch.cuda.current_stream(dev)
 
     state = {"delta": args.delta, "k": 0}
@@ -211,7 +211,7 @@ def bench_batch(args):
     import torch
     from synth.grids import power_flow_start
     from paper_2310_13143_amd.solver import DeviceGrid, autotune_block
-    from paper_2310_13143_amd._abi import PI_IF_CONVERGED
+    from paper_2310_13143_amd._abi import PI_IF_CONVERGED, SWEEP_GRAPH, SWEEP_LAUNCHES
     grids = batch_grids()
     starts = [power_flow_start(g) for g in grids]
     dg = DeviceGrid(grids, "cuda:0")
@@ -228,7 +228,8 @@ def bench_batch(args):
         outs = []
         for it in range(steps):
             outs.append(dg.sqp_step_batch(x, rho_g, rho_l, warm_start=it > 0, max_sweeps=args.sweeps,
-                                          eps=args.eps, block_size=bs, pi_update=PI_IF_CONVERGED))
+                                          eps=args.eps, block_size=bs, pi_update=PI_IF_CONVERGED,
+                                          sweep_mode=SWEEP_GRAPH if args.mode == "graph" else SWEEP_LAUNCHES))
         return outs
 
     run(args.warmup)

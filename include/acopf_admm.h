@@ -44,7 +44,13 @@ typedef enum {
 } acopf_admm_outcome;
 
 typedef enum { ACOPF_HESSIAN_PSD = 0, ACOPF_HESSIAN_RAW = 1 } acopf_hessian_mode;
-typedef enum { ACOPF_SWEEP_PERSISTENT = 0, ACOPF_SWEEP_LAUNCHES = 1 } acopf_sweep_mode;
+/* How the sweeps of a solve are issued: one cooperative kernel for all
+ * sweeps (single scenario); kernel launches per phase; or the same launches
+ * replayed from an instantiated HIP graph of one chunk of sweeps (64; the
+ * stop flag is read between chunks), built on first use and cached for the
+ * process per workspace, grid arrays and launch parameters (at most 256
+ * graphs; past that, and on a stream being captured, plain launches). */
+typedef enum { ACOPF_SWEEP_PERSISTENT = 0, ACOPF_SWEEP_LAUNCHES = 1, ACOPF_SWEEP_GRAPH = 2 } acopf_sweep_mode;
 
 /*
  * Network data of the ACOPF model (Section III-A, eqs. acopf and acopf_pf),
@@ -269,7 +275,10 @@ acopf_status acopf_sqp_step(const acopf_grid* grid, const acopf_iterate* x, cons
 /* The same step for every scenario of a batch, each with its own radius
  * (held in the workspace; set it with acopf_set_delta) and its own
  * decision.  states (host, n_scen entries) may be NULL: then nothing is
- * copied back and the call does not synchronise the stream. */
+ * copied back and the call does not synchronise the stream.  With states =
+ * NULL and eps_pri = eps_dual = 0 the call enqueues device work only, so a
+ * caller may record it under stream capture and replay the graph as SQP
+ * iterations (the iterate, radii and multipliers stay on the device). */
 acopf_status acopf_sqp_step_batch(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
                                   const double* rho_g, const double* rho_l, const acopf_sqp_params* params,
                                   void* workspace, void* stream, acopf_sqp_state* states);

@@ -13,7 +13,7 @@ ACOPF_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "NONCONVEX_LINE", -4: "NUMERIC",
                 -5: "UNSUPPORTED", -6: "BARRIER"}
 HESSIAN_PSD, HESSIAN_RAW = 0, 1
-SWEEP_PERSISTENT, SWEEP_LAUNCHES = 0, 1
+SWEEP_PERSISTENT, SWEEP_LAUNCHES, SWEEP_GRAPH = 0, 1, 2
 ADMM_CONVERGED, ADMM_MAX_SWEEPS, ADMM_FAILED = 0, 1, 2
 START_ZERO, START_PREVIOUS, START_GIVEN = 0, 1, 2
 PI_ALWAYS, PI_IF_CONVERGED = 0, 1

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -811,6 +813,101 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
   return ACOPF_OK;
 }
 
+// ---------------------------------------------------------------- sweep launches
+// Arguments of the launch-per-phase sweeps of one solve.
+struct SweepLaunch {
+  acopf_grid g;
+  Workspace w;
+  int nbl, nbb, bs, fold, ns, trace, max_sweeps;
+  double eps_pri, eps_dual;
+};
+
+void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w);
+    if (a.trace)
+      hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.fold, a.max_sweeps,
+                         a.eps_pri, a.eps_dual);
+    else
+      hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.fold,
+                         a.max_sweeps, a.eps_pri, a.eps_dual);
+    if (!a.fold)
+      hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(256), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
+  }
+}
+
+// Instantiated graphs of n launch-per-phase sweeps, cached per process and
+// keyed by everything their kernels receive (device, workspace, grid
+// arrays, sizes, launch shape, stop parameters), so that a hit replays
+// exactly the launches the plain mode would enqueue.  Entries live until
+// the process ends; past kMaxGraphs distinct keys the solve launches
+// without a graph.
+constexpr size_t kMaxGraphs = 256;
+
+struct GraphCache {
+  std::mutex mu;
+  std::map<std::string, hipGraphExec_t> execs;
+  std::map<int, hipStream_t> capture_streams;
+};
+
+GraphCache& graph_cache() {
+  static GraphCache* c = new GraphCache();  // never destroyed: graphs may be in flight at exit
+  return *c;
+}
+
+std::string graph_key(const SweepLaunch& a, int n, int dev) {
+  std::string k;
+  auto put = [&](const void* p, size_t b) { k.append(static_cast<const char*>(p), b); };
+  put(&dev, sizeof dev);
+  put(&n, sizeof n);
+  const acopf_grid& g = a.g;
+  const int32_t ints[6] = {g.n_bus, g.n_line, g.n_gen, g.ref_bus, g.n_scen, g.reserved};
+  put(ints, sizeof ints);
+  const void* ptrs[] = {g.vmin, g.vmax, g.pd, g.qd, g.gsh, g.bsh, g.line_from, g.line_to, g.gii, g.bii, g.gij,
+                        g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
+                        g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
+  put(ptrs, sizeof ptrs);
+  const int shape[7] = {a.nbl, a.nbb, a.bs, a.fold, a.ns, a.trace, a.max_sweeps};
+  put(shape, sizeof shape);
+  put(&a.eps_pri, sizeof a.eps_pri);
+  put(&a.eps_dual, sizeof a.eps_dual);
+  return k;
+}
+
+// Graph of n sweeps for a (built on first use); *exec = nullptr when the
+// cache is full.
+acopf_status sweep_graph(const SweepLaunch& a, int n, hipGraphExec_t* exec) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const std::string key = graph_key(a, n, dev);
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  auto it = c.execs.find(key);
+  if (it != c.execs.end()) {
+    *exec = it->second;
+    return ACOPF_OK;
+  }
+  *exec = nullptr;
+  if (c.execs.size() >= kMaxGraphs) return ACOPF_OK;
+  auto cs = c.capture_streams.find(dev);
+  if (cs == c.capture_streams.end()) {
+    hipStream_t st;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    cs = c.capture_streams.emplace(dev, st).first;
+  }
+  HIP_TRY(hipStreamBeginCapture(cs->second, hipStreamCaptureModeThreadLocal));
+  enqueue_sweeps(a, n, cs->second);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamEndCapture(cs->second, &graph));
+  hipGraphExec_t ge = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+  HIP_TRY(hipGraphDestroy(graph));
+  HIP_TRY(e);
+  c.execs.emplace(key, ge);
+  *exec = ge;
+  return ACOPF_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -893,8 +990,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     return ACOPF_OK;
   }
   if (p->trace != 0 && p->trace != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: trace must be 0 or 1");
-  if (p->trace && p->sweep_mode != ACOPF_SWEEP_LAUNCHES)
-    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: traced solves run in the launch-per-phase mode");
+  if (p->trace && p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
+    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: traced solves run in the launch-per-phase modes");
   if (p->trace) {
     const int bz = kDefaultBlock;
     const long long G2 = 2LL * g->n_gen, L8 = 8LL * g->n_line;
@@ -905,26 +1002,41 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(L8, bz)), dim3(bz), 0, s, w.tr_r_l, L8, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(L8, bz)), dim3(bz), 0, s, w.tr_s_l, L8, 0.0);
   }
-  if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES) {
+  if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES || p->sweep_mode == ACOPF_SWEEP_GRAPH) {
     // upper bounds of the per-scenario block counts (excess blocks exit)
     const long long nbl = (g->n_line + bs - 1) / bs + ns, nbb = (g->n_bus + bs - 1) / bs + ns;
     if (nbb > w.max_partials || nbl > 65535 || nbb > 65535)
       return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: grid too large for the block size");
-    const int fold = (ns == 1 && nbb - 1 <= kFoldMaxBlocks) ? 1 : 0;
+    SweepLaunch a;
+    a.g = *g;
+    a.w = w;
+    a.nbl = (int)nbl;
+    a.nbb = (int)nbb;
+    a.bs = bs;
+    a.fold = (ns == 1 && nbb - 1 <= kFoldMaxBlocks) ? 1 : 0;
+    a.ns = ns;
+    a.trace = p->trace;
+    a.max_sweeps = p->max_sweeps;
+    a.eps_pri = p->eps_pri;
+    a.eps_dual = p->eps_dual;
+    bool use_graph = p->sweep_mode == ACOPF_SWEEP_GRAPH;
+    if (use_graph) {  // a stream under capture records plain launches instead
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      HIP_TRY(hipStreamIsCapturing(s, &cap));
+      use_graph = cap == hipStreamCaptureStatusNone;
+    }
     hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs);
     for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
       const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
-      for (int k = k0; k < k1; ++k) {
-        hipLaunchKernelGGL(k_line_phase, dim3((unsigned)nbl), dim3(bs), 0, s, *g, w);
-        if (p->trace)
-          hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)nbb), dim3(bs), 0, s, *g, w, fold, p->max_sweeps,
-                             p->eps_pri, p->eps_dual);
-        else
-          hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)nbb), dim3(bs), 0, s, *g, w, fold, p->max_sweeps,
-                             p->eps_pri, p->eps_dual);
-        if (!fold)
-          hipLaunchKernelGGL(k_finish_phase, dim3(ns), dim3(256), 0, s, w, p->max_sweeps, p->eps_pri, p->eps_dual);
+      hipGraphExec_t ge = nullptr;
+      if (use_graph) {
+        acopf_status rc = sweep_graph(a, k1 - k0, &ge);
+        if (rc != ACOPF_OK) return rc;
       }
+      if (ge)
+        HIP_TRY(hipGraphLaunch(ge, s));
+      else
+        enqueue_sweeps(a, k1 - k0, s);
       HIP_TRY(hipGetLastError());
       if (k1 < p->max_sweeps && (p->eps_pri > 0.0 || p->eps_dual > 0.0)) {
         // look at the stop flag before enqueueing more sweeps
@@ -1051,6 +1163,15 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: penalty and radius cap must be > 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (capturing && states)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step_batch: host results need a synchronisation; pass states = NULL "
+                                       "while the stream is being captured");
+  if (capturing && (p->admm.eps_pri > 0.0 || p->admm.eps_dual > 0.0) && p->admm.sweep_mode != ACOPF_SWEEP_PERSISTENT)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step_batch: under capture the sweeps cannot poll the stop flag; "
+                                       "use eps = 0 (a fixed sweep count)");
   acopf_status rc = acopf_qp_build(g, x, 0.0, p->hessian_mode, workspace, stream);
   if (rc != ACOPF_OK) return rc;
   if (p->pi_update != ACOPF_PI_ALWAYS && p->pi_update != ACOPF_PI_IF_CONVERGED)
@@ -1065,12 +1186,16 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
     rc = admm_init_impl(g, rho_g, rho_l, nullptr, nullptr, p->warm_start == ACOPF_START_PREVIOUS, workspace,
                         stream);
   if (rc != ACOPF_OK) return rc;
+  // under stream capture (a caller recording the SQP loop in a graph) the
+  // iteration is recorded without timing events and without results
   EventPair ev;
-  HIP_TRY(ev.create());
-  HIP_TRY(hipEventRecord(ev.a, s));
+  if (!capturing) {
+    HIP_TRY(ev.create());
+    HIP_TRY(hipEventRecord(ev.a, s));
+  }
   rc = acopf_admm_solve(g, &p->admm, workspace, stream, nullptr);
   if (rc != ACOPF_OK) return rc;
-  HIP_TRY(hipEventRecord(ev.b, s));
+  if (!capturing) HIP_TRY(hipEventRecord(ev.b, s));
   rc = acopf_step(g, x, workspace, d, stream);
   if (rc != ACOPF_OK) return rc;
   const int bs = 256;

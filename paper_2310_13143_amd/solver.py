@@ -220,7 +220,8 @@ class DeviceGrid:
     def sqp_step_batch(self, x: dict, rho_g, rho_l, mu: float = 1e5, delta_max: float = 10.0,
                        grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                        max_sweeps: int = 20000, eps: float = 1e-4, block_size: int = 0, d: dict | None = None,
-                       sync: bool = True, lam=None, trace: bool = False, pi_update: int = _abi.PI_ALWAYS):
+                       sync: bool = True, lam=None, trace: bool = False, pi_update: int = _abi.PI_ALWAYS,
+                       sweep_mode: int = _abi.SWEEP_LAUNCHES):
         """One SQP iteration for every scenario of the batch (radii held on
         the device, see set_delta); per-scenario decisions if sync."""
         if d is None:
@@ -229,7 +230,7 @@ class DeviceGrid:
         f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
-                             AdmmParams(int(max_sweeps), float(eps), float(eps), _abi.SWEEP_LAUNCHES,
+                             AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode),
                                         int(block_size), 0, int(bool(trace))), lam, pi_update)
         sts = (SqpState * self.n_scen)() if sync else None
         cx, cd = self.c_iterate(x), self.c_iterate(d)

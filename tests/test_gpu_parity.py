@@ -417,3 +417,76 @@ def test_batch_sqp_matches_oracle_per_scenario():
     bo = dg.offsets["bus"]
     for k, ref in enumerate(refs):
         assert rel_err(xf["w"][bo[k]:bo[k + 1]], ref.x.w) <= TOL
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_graph_sweeps_match_launches(eps):
+    """Sweeps replayed from cached HIP graphs give bit for bit the state,
+    sweep count and residuals of plain launches (single grid and batch, two
+    solves each so that the second replays a cached graph)."""
+    print(f"[gpu] graph sweep mode eps={eps}", flush=True)
+    from paper_2310_13143_amd import _abi
+    DeviceGrid = _dev()
+    for grids in ([grid_14()], _batch_cases()):
+        pts = [start_point(g, pi_scale=20.0, seed=k) for k, g in enumerate(grids)]
+        cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+        pi = np.concatenate([p[1] for p in pts])
+        out = {}
+        for mode in (_abi.SWEEP_LAUNCHES, _abi.SWEEP_GRAPH):
+            dg = DeviceGrid(grids if len(grids) > 1 else grids[0])
+            xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), pi)
+            dg.qp_build(xb, 0.05)
+            runs = []
+            for rep in range(2):
+                dg.admm_init(*dg.rho_scalar(2e4))
+                dg.admm_solve(150, eps, eps, sweep_mode=mode, block_size=64, sync=False)
+                res = dg.admm_results()
+                st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+                runs.append((res, st))
+            out[mode] = runs
+        for (ra, sa), (rb, sb) in zip(out[_abi.SWEEP_LAUNCHES], out[_abi.SWEEP_GRAPH]):
+            for k in range(len(grids)):
+                assert ra[k]["sweeps"] == rb[k]["sweeps"] and ra[k]["r"] == rb[k]["r"] and ra[k]["s"] == rb[k]["s"]
+            for name in sa:
+                assert np.array_equal(sa[name], sb[name]), name
+
+
+def test_captured_sqp_iteration_replays_like_eager():
+    """One batched SQP iteration (fixed sweep count, no host results)
+    recorded under stream capture and replayed three times, with eager work
+    between the replays, gives bit for bit the iterates of three eager
+    iterations after every replay."""
+    print("[gpu] captured batched SQP iteration", flush=True)
+    import torch
+    from paper_2310_13143_amd import _abi
+    DeviceGrid = _dev()
+    grids = _batch_cases()
+    pts = [start_point(g) for g in grids]
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    kw = dict(mu=1e5, warm_start=_abi.START_PREVIOUS, max_sweeps=120, eps=0.0, block_size=64, sync=False)
+
+    def fresh():
+        dg = DeviceGrid(grids)
+        x = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
+        dg.set_delta(0.05)
+        rho_g, rho_l = (t.cuda() for t in dg.rho_scalar(2e4))
+        return dg, x, rho_g, rho_l, dg.empty_iterate()
+
+    dg_e, x_e, rg_e, rl_e, d_e = fresh()
+    eager = []
+    for it in range(3):
+        dg_e.sqp_step_batch(x_e, rg_e, rl_e, d=d_e, **kw)
+        eager.append({k: v.cpu().numpy() for k, v in x_e.items()})
+    dg_c, x_c, rg_c, rl_c, d_c = fresh()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dg_c.sqp_step_batch(x_c, rg_c, rl_c, d=d_c, **kw)
+    # capture records without executing: the iterate is still the start point
+    assert np.array_equal(x_c["w"].cpu().numpy(), cat("w"))
+    for it in range(3):
+        graph.replay()
+        dg_c.residuals_batch(x_c)  # eager work and a synchronisation between replays
+        got = {k: v.cpu().numpy() for k, v in x_c.items()}
+        for name in got:
+            assert np.array_equal(got[name], eager[it][name]), (it, name)
