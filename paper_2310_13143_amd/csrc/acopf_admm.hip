@@ -145,6 +145,24 @@ __global__ void k_copy(double* dst, const double* src, long long n) {
   for (long long i = gtid(); i < n; i += gstride()) dst[i] = src[i];
 }
 
+// Line-by-line state [n][F] from / to the field-by-field layout [F][n] of
+// the C ABI.
+__global__ void k_fields_to_lines(double* dst, const double* src, int n, int F) {
+  const long long total = (long long)n * F;
+  for (long long e = gtid(); e < total; e += gstride()) {
+    const long long i = e / F, f = e - i * F;
+    dst[e] = src[f * n + i];
+  }
+}
+
+__global__ void k_lines_to_fields(double* dst, const double* src, int n, int F) {
+  const long long total = (long long)n * F;
+  for (long long e = gtid(); e < total; e += gstride()) {
+    const long long f = e / n, i = e - f * n;
+    dst[e] = src[i * F + f];
+  }
+}
+
 __global__ void k_prep_lines(Workspace w) {
   for (int l = gtid(); l < w.n_line; l += gstride())
     if (!prep_line(w, l)) fail_line(w, l, ACOPF_ERR_NONCONVEX_LINE, &w.sync->nonconvex);
@@ -586,7 +604,7 @@ __global__ void k_features(acopf_grid g, acopf_iterate x, Workspace w, int first
 #pragma unroll
     for (int f = 0; f < 16; ++f) fl[f * ldl + l] = (float)v[f];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) fl[(16 + c) * ldl + l] = first ? 0.0f : (float)(w.lam_l[c * L + l] / kLamScale);
+    for (int c = 0; c < 8; ++c) fl[(16 + c) * ldl + l] = first ? 0.0f : (float)(w.lam_l[lc8(l, c)] / kLamScale);
     fl[24 * ldl + l] = (float)flag;
   }
   for (int k = gtid(); k < G; k += gstride()) {
@@ -610,9 +628,10 @@ __global__ void k_targets(Workspace w, float* tl, long long ldl, float* tg, long
   for (int l = gtid(); l < L; l += gstride()) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const int q = c * L + l;
+      const size_t q = lc8(l, c);  // line-by-line state
+      const int t = c * L + l;     // trace sums, field by field
       tl[c * ldl + l] = (float)((w.lam_l[q] - w.lam0_l[q]) / kLamScale);
-      tl[(8 + c) * ldl + l] = (float)log_rho_factor(w.rho_l[q], w.tr_r_l[q], w.tr_s_l[q]);
+      tl[(8 + c) * ldl + l] = (float)log_rho_factor(w.rho_l[q], w.tr_r_l[t], w.tr_s_l[t]);
     }
   }
   for (int k = gtid(); k < G; k += gstride()) {
@@ -636,8 +655,8 @@ __global__ void k_decode(Workspace w, const float* yl, long long ldl, const floa
   for (int l = gtid(); l < L; l += gstride()) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const int q = c * L + l;
-      const double base = first ? 0.0 : w.lam_l[q];
+      const int q = c * L + l;  // caller layout
+      const double base = first ? 0.0 : w.lam_l[lc8(l, c)];
       const double a = base + (double)yl[c * ldl + l] * kLamScale;
       lam_l[q] = (use_lam && isfinite(a)) ? a : base;
       const double o = (double)yl[(8 + c) * ldl + l];
@@ -785,13 +804,16 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
   auto copy = [&](double* d, const double* src, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, bs)), dim3(bs), 0, s, d, src, n);
   };
+  auto to_lines = [&](double* d, const double* src, int n, int F) {
+    hipLaunchKernelGGL(k_fields_to_lines, dim3(blocks_for((long long)n * F, bs)), dim3(bs), 0, s, d, src, n, F);
+  };
   copy(w.rho_g, rho_g, G2);
-  copy(w.rho_l, rho_l, L8);
+  to_lines(w.rho_l, rho_l, g->n_line, 8);
   if (keep_lam) {
     // multipliers of the previous solve stay in place (previous-iterate warm start)
   } else if (lam_l) {
     copy(w.lam_g, lam_g, G2);
-    copy(w.lam_l, lam_l, L8);
+    to_lines(w.lam_l, lam_l, g->n_line, 8);
   } else {
     fill(w.lam_g, G2, 0.0);
     fill(w.lam_l, L8, 0.0);
@@ -1122,14 +1144,22 @@ acopf_status acopf_admm_state_get(const acopf_grid* g, void* workspace, const ac
     if (!dst || n == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, n * D, hipMemcpyDeviceToDevice, s);
   };
+  auto fields = [&](double* dst, const double* src, int F) -> hipError_t {  // line-by-line -> caller layout
+    if (!dst) return hipSuccess;
+    const long long n = (long long)g->n_line * F;
+    hipLaunchKernelGGL(k_lines_to_fields, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, src, g->n_line, F);
+    return hipGetLastError();
+  };
+  (void)L8;
+  (void)L4;
   HIP_TRY(cp(o->xg, w.xg, G2));
   HIP_TRY(cp(o->xbar_g, w.xbar_g, G2));
   HIP_TRY(cp(o->lam_g, w.lam_g, G2));
   HIP_TRY(cp(o->rho_g, w.rho_g, G2));
-  HIP_TRY(cp(o->xl, w.xl, L8));
-  HIP_TRY(cp(o->xbar_f, w.xbar_f, L4));
-  HIP_TRY(cp(o->lam_l, w.lam_l, L8));
-  HIP_TRY(cp(o->rho_l, w.rho_l, L8));
+  HIP_TRY(fields(o->xl, w.xl, 8));
+  HIP_TRY(fields(o->xbar_f, w.xbar_f, 4));
+  HIP_TRY(fields(o->lam_l, w.lam_l, 8));
+  HIP_TRY(fields(o->rho_l, w.rho_l, 8));
   HIP_TRY(cp(o->dw, w.dw, g->n_bus));
   HIP_TRY(cp(o->dth, w.dth, g->n_bus));
   HIP_TRY(cp(o->nu, w.nu, 2 * (size_t)g->n_bus));

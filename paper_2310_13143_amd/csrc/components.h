@@ -11,6 +11,12 @@
 
 namespace acopf {
 
+// The coupling state of the lines (x, lambda, rho and the starting
+// multipliers: 8 couplings per line; the bus-side flow copies: 4) is stored
+// line by line, so the values one line end needs share a cache line.
+ACOPF_HD size_t lc8(int l, int k) { return 8 * (size_t)l + k; }
+ACOPF_HD size_t lc4(int l, int k) { return 4 * (size_t)l + k; }
+
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // QP data of line l at the iterate (Sections III-B, III-C and IV-B2).
@@ -254,7 +260,7 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
   for (int i = 0; i < 4; ++i) cc[i] = d[(LF_Q + i) * L + l];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const double rho = w.rho_l[r * L + l];
+    const double rho = w.rho_l[lc8(l, r)];
     const double f0 = d[(LF_F0 + r) * L + l];
     double Fr[4];
 #pragma unroll
@@ -267,7 +273,7 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Q[i][i] += w.rho_l[(4 + i) * L + l];
+  for (int i = 0; i < 4; ++i) Q[i][i] += w.rho_l[lc8(l, 4 + i)];
   double Lc[4][4], Pinv[4][4];
   const bool ok = chol4(Q, Lc);
   chol4_inverse(Lc, Pinv);
@@ -300,10 +306,10 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   double c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-    c[i] = w.line_cc[i * L + l] + w.lam_l[(4 + i) * L + l] - w.rho_l[(4 + i) * L + l] * xbv[i];
+    c[i] = w.line_cc[i * L + l] + w.lam_l[lc8(l, 4 + i)] - w.rho_l[lc8(l, 4 + i)] * xbv[i];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const double a = w.lam_l[r * L + l] - w.rho_l[r * L + l] * w.xbar_f[r * L + l];
+    const double a = w.lam_l[lc8(l, r)] - w.rho_l[lc8(l, r)] * w.xbar_f[lc4(l, r)];
 #pragma unroll
     for (int i = 0; i < 4; ++i) c[i] += F[r][i] * a;
   }
@@ -323,8 +329,8 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   for (int r = 0; r < 4; ++r) {
     const double fl = F[r][0] * res.z[0] + F[r][1] * res.z[1] + F[r][2] * res.z[2] +
                       F[r][3] * res.z[3] + d[(LF_F0 + r) * L + l];
-    w.xl[r * L + l] = fl;
-    w.xl[(4 + r) * L + l] = res.z[r];
+    w.xl[lc8(l, r)] = fl;
+    w.xl[lc8(l, 4 + r)] = res.z[r];
   }
   w.mu[l] = res.mu[0];
   w.mu[L + l] = res.mu[1];
@@ -392,18 +398,18 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
 #pragma unroll
       for (int m = 0; m < 12; ++m) v[j][m] = 0.0;
       if (on[j]) {
-        v[j][0] = w.rho_l[kp * L + l[j]];
-        v[j][1] = w.rho_l[(kp + 1) * L + l[j]];
-        v[j][2] = w.rho_l[kw * L + l[j]];
-        v[j][3] = w.rho_l[(kw + 1) * L + l[j]];
-        v[j][4] = w.xl[kp * L + l[j]];
-        v[j][5] = w.xl[(kp + 1) * L + l[j]];
-        v[j][6] = w.xl[kw * L + l[j]];
-        v[j][7] = w.xl[(kw + 1) * L + l[j]];
-        v[j][8] = w.lam_l[kp * L + l[j]];
-        v[j][9] = w.lam_l[(kp + 1) * L + l[j]];
-        v[j][10] = w.lam_l[kw * L + l[j]];
-        v[j][11] = w.lam_l[(kw + 1) * L + l[j]];
+        v[j][0] = w.rho_l[lc8(l[j], kp)];
+        v[j][1] = w.rho_l[lc8(l[j], kp + 1)];
+        v[j][2] = w.rho_l[lc8(l[j], kw)];
+        v[j][3] = w.rho_l[lc8(l[j], kw + 1)];
+        v[j][4] = w.xl[lc8(l[j], kp)];
+        v[j][5] = w.xl[lc8(l[j], kp + 1)];
+        v[j][6] = w.xl[lc8(l[j], kw)];
+        v[j][7] = w.xl[lc8(l[j], kw + 1)];
+        v[j][8] = w.lam_l[lc8(l[j], kp)];
+        v[j][9] = w.lam_l[lc8(l[j], kp + 1)];
+        v[j][10] = w.lam_l[lc8(l[j], kw)];
+        v[j][11] = w.lam_l[lc8(l[j], kw + 1)];
       }
     }
 #pragma unroll
@@ -470,20 +476,20 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
 #pragma unroll
       for (int m = 0; m < 14; ++m) v[j][m] = 1.0;
       if (on[j]) {
-        v[j][0] = w.rho_l[kp * L + l[j]];
-        v[j][1] = w.rho_l[(kp + 1) * L + l[j]];
-        v[j][2] = w.rho_l[kw * L + l[j]];
-        v[j][3] = w.rho_l[(kw + 1) * L + l[j]];
-        v[j][4] = w.xl[kp * L + l[j]];
-        v[j][5] = w.xl[(kp + 1) * L + l[j]];
-        v[j][6] = w.xl[kw * L + l[j]];
-        v[j][7] = w.xl[(kw + 1) * L + l[j]];
-        v[j][8] = w.lam_l[kp * L + l[j]];
-        v[j][9] = w.lam_l[(kp + 1) * L + l[j]];
-        v[j][10] = w.lam_l[kw * L + l[j]];
-        v[j][11] = w.lam_l[(kw + 1) * L + l[j]];
-        v[j][12] = w.xbar_f[kp * L + l[j]];
-        v[j][13] = w.xbar_f[(kp + 1) * L + l[j]];
+        v[j][0] = w.rho_l[lc8(l[j], kp)];
+        v[j][1] = w.rho_l[lc8(l[j], kp + 1)];
+        v[j][2] = w.rho_l[lc8(l[j], kw)];
+        v[j][3] = w.rho_l[lc8(l[j], kw + 1)];
+        v[j][4] = w.xl[lc8(l[j], kp)];
+        v[j][5] = w.xl[lc8(l[j], kp + 1)];
+        v[j][6] = w.xl[lc8(l[j], kw)];
+        v[j][7] = w.xl[lc8(l[j], kw + 1)];
+        v[j][8] = w.lam_l[lc8(l[j], kp)];
+        v[j][9] = w.lam_l[lc8(l[j], kp + 1)];
+        v[j][10] = w.lam_l[lc8(l[j], kw)];
+        v[j][11] = w.lam_l[lc8(l[j], kw + 1)];
+        v[j][12] = w.xbar_f[lc4(l[j], kp)];
+        v[j][13] = w.xbar_f[lc4(l[j], kp + 1)];
       }
     }
 #pragma unroll
@@ -497,8 +503,8 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
         const double lam_new = -((m == 0) ? nup : nuq);
         const double xb = xv + (lam - lam_new) / rho;
         const double ds = rho * (xb - v[j][12 + m]);
-        w.lam_l[(kp + m) * L + l[j]] = lam_new;
-        w.xbar_f[(kp + m) * L + l[j]] = xb;
+        w.lam_l[lc8(l[j], kp + m)] = lam_new;
+        w.xbar_f[lc4(l[j], kp + m)] = xb;
         rr += (xv - xb) * (xv - xb);
         ss += ds * ds;
         if (kTrace) {
@@ -512,7 +518,7 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
         const double rho = v[j][2 + m], xv = v[j][6 + m], lam = v[j][10 + m];
         const double xb = (m == 0) ? dw_new : dth_new;
         const double ds = rho * (xb - ((m == 0) ? dw_old : dth_old));
-        w.lam_l[(kw + m) * L + l[j]] = lam + rho * (xv - xb);
+        w.lam_l[lc8(l[j], kw + m)] = lam + rho * (xv - xb);
         rr += (xv - xb) * (xv - xb);
         ss += ds * ds;
         if (kTrace) {
@@ -550,7 +556,7 @@ ACOPF_HD void step_line(const acopf_grid& g, const acopf_iterate& x, const Works
   // multipliers from the line subproblem's KKT conditions at its own solution
   double z[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) z[k] = w.xl[(4 + k) * L + l];
+  for (int k = 0; k < 4; ++k) z[k] = w.xl[lc8(l, 4 + k)];
   const double u[6] = {z[0], z[1], aR[0] * z[0] + aR[1] * z[1] + aR[2] * z[2] + aR[3] * z[3] + bR,
                        aI[0] * z[0] + aI[1] * z[1] + aI[2] * z[2] + aI[3] * z[3] + bI, z[2], z[3]};
   double huR = 0.0, huI = 0.0;
@@ -562,7 +568,7 @@ ACOPF_HD void step_line(const acopf_grid& g, const acopf_iterate& x, const Works
   const double gij = g.gij[l], bij = g.bij[l], gji = g.gji[l], bji = g.bji[l];
   const double pij = q[(LF_PK + 0) * L + l], qij = q[(LF_PK + 1) * L + l];
   const double pji = q[(LF_PK + 2) * L + l], qji = q[(LF_PK + 3) * L + l];
-  const double lam[4] = {w.lam_l[l], w.lam_l[L + l], w.lam_l[2 * L + l], w.lam_l[3 * L + l]};
+  const double lam[4] = {w.lam_l[lc8(l, 0)], w.lam_l[lc8(l, 1)], w.lam_l[lc8(l, 2)], w.lam_l[lc8(l, 3)]};
   const double mu0 = w.mu[l], mu1 = w.mu[L + l];
   const double gR = huR + lam[0] * gij - lam[1] * bij + lam[2] * gji - lam[3] * bji +
                     mu0 * (2.0 * pij * gij - 2.0 * qij * bij) + mu1 * (2.0 * pji * gji - 2.0 * qji * bji);

@@ -2,10 +2,12 @@
 // topology tables, QP data, ADMM state and reduction scratch, carved out of
 // one caller-allocated buffer.  The scenarios of a batch are packed one after
 // another (buses, lines and generators of scenario s occupy contiguous index
-// ranges) and never reference each other's components.  All arrays are
-// structure-of-arrays with one entry per component so that consecutive
-// threads touch consecutive addresses; field k of an array with n entries per
-// field lives at [k * n + index].
+// ranges) and never reference each other's components.  Arrays are
+// structure-of-arrays with one entry per component, so that consecutive
+// threads touch consecutive addresses (field k of an array with n entries per
+// field at [k * n + index]), except the lines' coupling state, which the bus
+// update gathers per line end and which is therefore stored line by line
+// ([index * fields + k]).
 #pragma once
 
 #include <stddef.h>
@@ -103,12 +105,12 @@ struct Workspace {
   double* line_cc;         // [4][n_line]   q + sum_f rho_f f0_f F_f
   // ADMM state
   double *xg, *xbar_g, *lam_g, *rho_g;   // [2][n_gen]
-  double *xl, *lam_l, *rho_l;            // [8][n_line]
-  double *xbar_f;                        // [4][n_line]
+  double *xl, *lam_l, *rho_l;            // [n_line][8] line by line
+  double *xbar_f;                        // [n_line][4] line by line
   double *dw, *dth, *nu;                 // [n_bus], [n_bus], [2][n_bus]
   double *mu;                            // [2][n_line]
   int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
-  double *lam0_g, *lam0_l;               // [2][n_gen], [8][n_line] multipliers the last solve started from
+  double *lam0_g, *lam0_l;               // [2][n_gen], [n_line][8] multipliers the last solve started from
   // per-coupling sums of |r_c| and |s_c| over the sweeps of a traced solve
   double *tr_r_g, *tr_s_g;               // [2][n_gen]
   double *tr_r_l, *tr_s_l;               // [8][n_line]

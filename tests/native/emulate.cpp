@@ -71,10 +71,13 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   for (int k = 0; k < ng; ++k) build_gen(*g, *x, delta, w, k);
   for (int i = 0; i < nb; ++i) build_bus(*g, *x, w, i);
   std::memcpy(w.rho_g, rho_g, sizeof(double) * 2 * ng);
-  std::memcpy(w.rho_l, rho_l, sizeof(double) * 8 * nl);
+  // caller layout [field][line] -> the workspace's line-by-line state
+  for (int l = 0; l < nl; ++l)
+    for (int k = 0; k < 8; ++k) w.rho_l[8 * l + k] = rho_l[k * nl + l];
   if (lam_l) {
     std::memcpy(w.lam_g, lam_g, sizeof(double) * 2 * ng);
-    std::memcpy(w.lam_l, lam_l, sizeof(double) * 8 * nl);
+    for (int l = 0; l < nl; ++l)
+      for (int k = 0; k < 8; ++k) w.lam_l[8 * l + k] = lam_l[k * nl + l];
   } else {
     std::memset(w.lam_g, 0, sizeof(double) * 2 * ng);
     std::memset(w.lam_l, 0, sizeof(double) * 8 * nl);
