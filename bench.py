@@ -34,7 +34,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("08ec6ce15efc5441", 4018238), "rgg70000": ("08ec6ce15efc5441", 113847397)}
+MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("59a4b131816d3417", 4306094), "rgg70000": ("59a4b131816d3417", 124545914)}
 
 
 def sweep_sources_sha() -> str:

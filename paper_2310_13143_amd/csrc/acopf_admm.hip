@@ -244,13 +244,25 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
   return __hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-__global__ void __launch_bounds__(256) k_line_phase(acopf_grid g, Workspace w) {
-  if (batch_done(w)) return;
-  const int s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
-  if (s < 0 || w.scen[s].done) return;
-  const int l = w.scen_line_off[s] + (blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x;
-  if (l < w.scen_line_off[s + 1] && update_line(g, w, l) != 0)
-    atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
+// `single`: one scenario, launched with exactly ceil(n / block) blocks, so a
+// block needs no table lookup (one flag read before the line work).  At
+// most 256 registers per lane: two waves per SIMD (measured faster than one
+// wave with 270 registers, despite a few spilled values).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_line_phase(acopf_grid g, Workspace w, int single) {
+  int s = 0, l;
+  if (single) {
+    if (w.scen[0].done) return;
+    l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= w.n_line) return;
+  } else {
+    if (batch_done(w)) return;
+    s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
+    if (s < 0 || w.scen[s].done) return;
+    l = w.scen_line_off[s] + (blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x;
+    if (l >= w.scen_line_off[s + 1]) return;
+  }
+  if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
 // Bus phase of the launch-per-phase mode.  With `fold` (a single scenario
@@ -258,16 +270,24 @@ __global__ void __launch_bounds__(256) k_line_phase(acopf_grid g, Workspace w) {
 // sweep; each block then pays a device-scope fence, which only pays off for
 // small grids.  Otherwise k_finish_phase ends the sweep as a third launch.
 template <bool kTrace>
-__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w, int fold, int max_sweeps,
+__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w, int single, int fold, int max_sweeps,
                                                    double eps_pri, double eps_dual) {
   __shared__ double lds[16];
   __shared__ int s_last;
-  if (batch_done(w)) return;
-  const int s = scen_of_block(w.bus_blk_off, w.n_scen, blockIdx.x);
-  if (s < 0 || w.scen[s].done) return;
-  const int i = w.scen_bus_off[s] + (blockIdx.x - w.bus_blk_off[s]) * blockDim.x + threadIdx.x;
+  int s = 0, i, end;
+  if (single) {  // exactly ceil(n_bus / block) blocks
+    if (w.scen[0].done) return;
+    i = blockIdx.x * blockDim.x + threadIdx.x;
+    end = w.n_bus;
+  } else {
+    if (batch_done(w)) return;
+    s = scen_of_block(w.bus_blk_off, w.n_scen, blockIdx.x);
+    if (s < 0 || w.scen[s].done) return;
+    i = w.scen_bus_off[s] + (blockIdx.x - w.bus_blk_off[s]) * blockDim.x + threadIdx.x;
+    end = w.scen_bus_off[s + 1];
+  }
   double r2 = 0.0, s2 = 0.0;
-  if (i < w.scen_bus_off[s + 1]) update_bus<kTrace>(g, w, i, r2, s2);
+  if (i < end) update_bus<kTrace>(g, w, i, r2, s2);
   r2 = block_sum(r2, lds);
   s2 = block_sum(s2, lds);
   if (threadIdx.x == 0) {
@@ -279,7 +299,7 @@ __global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w, in
   if (threadIdx.x == 0) {
     __threadfence();
     const unsigned int ticket = atomicAdd(&w.sync->count, 1u);
-    s_last = (ticket == (unsigned int)w.bus_blk_off[w.n_scen] - 1u) ? 1 : 0;
+    s_last = (ticket == gridDim.x - 1u) ? 1 : 0;  // fold runs with one scenario and exact blocks
     if (s_last) __threadfence();
   }
   __syncthreads();
@@ -824,6 +844,7 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
   fill(w.xbar_g, G2, 0.0);
   fill(w.xl, L8, 0.0);
   fill(w.xbar_f, 4LL * g->n_line, 0.0);
+  fill(w.xbar_v, 4LL * g->n_line, 0.0);
   fill(w.dw, g->n_bus, 0.0);
   fill(w.dth, g->n_bus, 0.0);
   fill(w.nu, 2LL * g->n_bus, 0.0);
@@ -840,18 +861,18 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
 struct SweepLaunch {
   acopf_grid g;
   Workspace w;
-  int nbl, nbb, bs, fold, ns, trace, max_sweeps;
+  int nbl, nbb, bs, single, fold, ns, trace, max_sweeps;
   double eps_pri, eps_dual;
 };
 
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w);
+    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single);
     if (a.trace)
-      hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.fold, a.max_sweeps,
-                         a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.single, a.fold,
+                         a.max_sweeps, a.eps_pri, a.eps_dual);
     else
-      hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.fold,
+      hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.single, a.fold,
                          a.max_sweeps, a.eps_pri, a.eps_dual);
     if (!a.fold)
       hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(256), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
@@ -889,7 +910,7 @@ std::string graph_key(const SweepLaunch& a, int n, int dev) {
                         g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
                         g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
   put(ptrs, sizeof ptrs);
-  const int shape[7] = {a.nbl, a.nbb, a.bs, a.fold, a.ns, a.trace, a.max_sweeps};
+  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.fold, a.ns, a.trace, a.max_sweeps};
   put(shape, sizeof shape);
   put(&a.eps_pri, sizeof a.eps_pri);
   put(&a.eps_dual, sizeof a.eps_dual);
@@ -1025,8 +1046,11 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(L8, bz)), dim3(bz), 0, s, w.tr_s_l, L8, 0.0);
   }
   if (p->sweep_mode == ACOPF_SWEEP_LAUNCHES || p->sweep_mode == ACOPF_SWEEP_GRAPH) {
-    // upper bounds of the per-scenario block counts (excess blocks exit)
-    const long long nbl = (g->n_line + bs - 1) / bs + ns, nbb = (g->n_bus + bs - 1) / bs + ns;
+    // one scenario: exact block counts; a batch: upper bounds of the
+    // per-scenario block counts (excess blocks exit)
+    const int single = ns == 1 ? 1 : 0;
+    const long long nbl = (g->n_line + bs - 1) / bs + (single ? 0 : ns);
+    const long long nbb = (g->n_bus + bs - 1) / bs + (single ? 0 : ns);
     if (nbb > w.max_partials || nbl > 65535 || nbb > 65535)
       return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: grid too large for the block size");
     SweepLaunch a;
@@ -1035,7 +1059,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.nbl = (int)nbl;
     a.nbb = (int)nbb;
     a.bs = bs;
-    a.fold = (ns == 1 && nbb - 1 <= kFoldMaxBlocks) ? 1 : 0;
+    a.single = single;
+    a.fold = (single && nbb <= kFoldMaxBlocks) ? 1 : 0;
     a.ns = ns;
     a.trace = p->trace;
     a.max_sweeps = p->max_sweeps;

@@ -293,7 +293,7 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
 ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   const int L = w.n_line;
   const double* d = w.line;
-  const int f = g.line_from[l], t = g.line_to[l];
+  (void)g;
   double Pp[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) Pp[k] = w.line_P[k * L + l];
@@ -302,7 +302,9 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int k = 0; k < 4; ++k) F[r][k] = d[(LF_F + 4 * r + k) * L + l];
-  const double xbv[4] = {w.dw[f], w.dth[f], w.dw[t], w.dth[t]};
+  // bus-side values of the voltage copies, stored in the line's record by
+  // the last bus update (the end buses' d_w, d_th)
+  const double xbv[4] = {w.xbar_v[lc4(l, 0)], w.xbar_v[lc4(l, 1)], w.xbar_v[lc4(l, 2)], w.xbar_v[lc4(l, 3)]};
   double c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -519,6 +521,7 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
         const double xb = (m == 0) ? dw_new : dth_new;
         const double ds = rho * (xb - ((m == 0) ? dw_old : dth_old));
         w.lam_l[lc8(l[j], kw + m)] = lam + rho * (xv - xb);
+        w.xbar_v[lc4(l[j], 2 * sd[j] + m)] = xb;
         rr += (xv - xb) * (xv - xb);
         ss += ds * ds;
         if (kTrace) {

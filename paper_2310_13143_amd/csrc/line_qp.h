@@ -152,6 +152,117 @@ ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], c
   return p;
 }
 
+// KKT check of a working set (warm start), in the variables' own
+// coordinates: an active bound fixes its variable (t_v = +1 lower, -1
+// upper, 0 free), an active row enters through v_r = P G_r^T.  The
+// multipliers y solve the 6x6 Schur system (N P N^T) y = b - N zu with the
+// inactive entries replaced by identity rows, so no branch or register
+// placement depends on which constraints are active; LDL^T without
+// pivoting (the system is positive definite).  Returns true, with the
+// minimiser z and the rows' multipliers, if the working set is optimal.
+ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double lo[4], const double hi[4],
+                         const double G[2][4], const double h[2], const double gn[2], int warm_mask, double cs,
+                         double z[4], double mu[2]) {
+  double t[4], a[4], beta[4], ar[2];
+  bool ok = (warm_mask & (warm_mask >> 4) & 0xF) == 0;  // a lower and an upper bound of one variable
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool lower = (warm_mask >> v) & 1, upper = (warm_mask >> (v + 4)) & 1;
+    a[v] = (lower || upper) ? 1.0 : 0.0;
+    t[v] = lower ? 1.0 : (upper ? -1.0 : 0.0);
+    beta[v] = lower ? lo[v] : hi[v];
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) ar[r] = ((warm_mask >> (8 + r)) & 1) ? 1.0 : 0.0;
+  double vr[2][4];
+  matvec4(P, G[0], vr[0]);
+  matvec4(P, G[1], vr[1]);
+  // lower triangle of the Schur system and its right-hand side
+  double S[6][6], rhs[6];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j <= i) S[i][j] = t[i] * t[j] * P[i][j] + ((i == j) ? 1.0 - a[i] : 0.0);
+    rhs[i] = t[i] * (beta[i] - zu[i]);
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S[4 + r][j] = -ar[r] * t[j] * vr[r][j];
+#pragma unroll
+    for (int r2 = 0; r2 < 2; ++r2)
+      if (r2 <= r) S[4 + r][4 + r2] = ar[r] * ar[r2] * dot4(G[r], vr[r2]) + ((r == r2) ? 1.0 - ar[r] : 0.0);
+    rhs[4 + r] = ar[r] * (dot4(G[r], zu) - h[r]);
+  }
+  // LDL^T: S = L D L^T with unit lower triangular L
+  double L[6][6], D[6], dinv[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double d = S[j][j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k < j) d -= L[j][k] * L[j][k] * D[k];
+    D[j] = d;
+    ok = ok && d > 0.0;
+    dinv[j] = 1.0 / d;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i > j) {
+        double s = S[i][j];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (k < j) s -= L[i][k] * L[j][k] * D[k];
+        L[i][j] = s * dinv[j];
+      }
+    }
+  }
+  double y[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = rhs[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k < i) s -= L[i][k] * y[k];
+    y[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) y[i] *= dinv[i];
+#pragma unroll
+  for (int ii = 0; ii < 6; ++ii) {
+    const int i = 5 - ii;
+    double s = y[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k > i) s -= L[k][i] * y[k];
+    y[i] = s;
+  }
+  // minimiser of the working set: z = zu + P N^T y
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double zi = zu[i] - ar[0] * y[4] * vr[0][i] - ar[1] * y[5] * vr[1][i];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) zi += t[v] * y[v] * P[i][v];
+    z[i] = zi;
+  }
+  // KKT: non-negative multipliers (free sign for a bound of a fixed
+  // variable), active constraints met, every other constraint satisfied
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool fixed_var = lo[v] >= hi[v];
+    ok = ok && (a[v] == 0.0 || fixed_var || y[v] >= -1e-10 * cs);
+    ok = ok && (a[v] == 0.0 || fabs(z[v] - beta[v]) <= 1e-9 * (1.0 + fabs(beta[v])));
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    ok = ok && (ar[r] == 0.0 || y[4 + r] >= -1e-10 * cs);
+    ok = ok && (ar[r] == 0.0 || fabs(dot4(G[r], z) - h[r]) <= 1e-9 * (1.0 + fabs(h[r])));
+    mu[r] = ar[r] * y[4 + r];
+  }
+  ok = ok && gi_most_violated(z, warm_mask, lo, hi, G, h, gn) < 0;
+  return ok;
+}
+
 ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], const double lo[4],
                                     const double hi[4], const double G[2][4], const double h[2],
                                     int warm_mask) {
@@ -180,64 +291,15 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
 
   // 1. warm start from the previous working set
   if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
-    double b[4] = {0.0, 0.0, 0.0, 0.0};
-    int qq = 0;
+    double zw[4], muw[2];
+    if (warm_check(P, zu, lo, hi, G, h, gn, warm_mask, cs, zw, muw)) {
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
-      if ((warm_mask >> k) & 1) {
-        double n[4], bk;
-        gi_constraint(k, G, lo, hi, h, n, bk);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool here = (j == qq);
-          act[j] = here ? k : act[j];
-          b[j] = here ? bk : b[j];
-#pragma unroll
-          for (int d = 0; d < 4; ++d) N[j][d] = here ? n[d] : N[j][d];
-        }
-        qq += 1;
-      }
-    }
-    q = qq;
-    double W[4][4], S[4][4], rhs[4], y[4];
-    gi_products(P, N, q, W, S);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) rhs[j] = b[j] - dot4(N[j], zu);
-    spd_solve_padded(S, q, rhs, y);
-    double zw[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) zw[i] = zu[i] + W[i][0] * y[0] + W[i][1] * y[1] + W[i][2] * y[2] + W[i][3] * y[3];
-    // KKT check: multipliers non-negative (free sign for a bound of a fixed
-    // variable), every other constraint satisfied, working set reproduced
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = act[j];
-      const bool fixed_var = (k >= 0 && k < 8) && (lo[k & 3] >= hi[k & 3]);
-      ok = ok && (j >= q || fixed_var || y[j] >= -1e-10 * cs);
-      double n[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) n[d] = N[j][d];
-      ok = ok && (j >= q || fabs(dot4(n, zw) - b[j]) <= 1e-9 * (1.0 + fabs(b[j])));
-    }
-    ok = ok && gi_most_violated(zw, warm_mask, lo, hi, G, h, gn) < 0;
-    if (ok) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) z[i] = zw[i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = (j < q) ? y[j] : 0.0;
-      mask = warm_mask;
-      done = true;
-    } else {
-      // restart from the unconstrained minimiser with an empty working set
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        act[j] = -1;
-        u[j] = 0.0;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) N[j][d] = 0.0;
-      }
-      q = 0;
+      for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(zw[i], lo[i]), hi[i]);
+      res.mu[0] = muw[0];
+      res.mu[1] = muw[1];
+      res.status = 0;
+      res.mask = warm_mask;
+      return res;
     }
   }
 

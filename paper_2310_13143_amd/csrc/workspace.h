@@ -106,7 +106,8 @@ struct Workspace {
   // ADMM state
   double *xg, *xbar_g, *lam_g, *rho_g;   // [2][n_gen]
   double *xl, *lam_l, *rho_l;            // [n_line][8] line by line
-  double *xbar_f;                        // [n_line][4] line by line
+  double *xbar_f;                        // [n_line][4] line by line: bus-side flow copies
+  double *xbar_v;                        // [n_line][4] line by line: the end buses' d_w, d_th (w_i, th_i, w_j, th_j)
   double *dw, *dth, *nu;                 // [n_bus], [n_bus], [2][n_bus]
   double *mu;                            // [2][n_line]
   int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
@@ -174,6 +175,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.lam_l = (double*)take((size_t)8 * nl * D);
   t.rho_l = (double*)take((size_t)8 * nl * D);
   t.xbar_f = (double*)take((size_t)4 * nl * D);
+  t.xbar_v = (double*)take((size_t)4 * nl * D);
   t.dw = (double*)take((size_t)nb * D);
   t.dth = (double*)take((size_t)nb * D);
   t.nu = (double*)take((size_t)2 * nb * D);

@@ -12,16 +12,21 @@ using namespace acopf;
 
 extern "C" {
 
+// warm: per-instance starting working sets (NULL = none); mask_out
+// (optional): the returned working sets.
 void emu_line_qp(int n, const double* P, const double* c, const double* lo, const double* hi,
-                 const double* G, const double* h, double* z, double* mu, int* status) {
+                 const double* G, const double* h, double* z, double* mu, int* status, const int* warm,
+                 int* mask_out) {
   for (int k = 0; k < n; ++k) {
     double Gk[2][4] = {{G[8 * k + 0], G[8 * k + 1], G[8 * k + 2], G[8 * k + 3]},
                        {G[8 * k + 4], G[8 * k + 5], G[8 * k + 6], G[8 * k + 7]}};
-    LineQPResult r = solve_line_qp(P + 10 * k, c + 4 * k, lo + 4 * k, hi + 4 * k, Gk, h + 2 * k, 0);
+    LineQPResult r = solve_line_qp(P + 10 * k, c + 4 * k, lo + 4 * k, hi + 4 * k, Gk, h + 2 * k,
+                                   warm ? warm[k] : 0);
     for (int i = 0; i < 4; ++i) z[4 * k + i] = r.z[i];
     mu[2 * k] = r.mu[0];
     mu[2 * k + 1] = r.mu[1];
     status[k] = r.status;
+    if (mask_out) mask_out[k] = r.mask;
   }
 }
 
@@ -86,6 +91,7 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   std::memset(w.xbar_g, 0, sizeof(double) * 2 * ng);
   std::memset(w.xl, 0, sizeof(double) * 8 * nl);
   std::memset(w.xbar_f, 0, sizeof(double) * 4 * nl);
+  std::memset(w.xbar_v, 0, sizeof(double) * 4 * nl);
   std::memset(w.dw, 0, sizeof(double) * nb);
   std::memset(w.dth, 0, sizeof(double) * nb);
   std::memset(w.nu, 0, sizeof(double) * 2 * nb);

@@ -51,14 +51,29 @@ def test_line_qp_solver_matches_enumeration(emu):
     iu = np.triu_indices(4)
     Pp = np.ascontiguousarray(P[:, iu[0], iu[1]])
     z = np.zeros((n, 4)); mu = np.zeros((n, 2)); st = np.zeros(n, dtype=np.int32)
-    emu.emu_line_qp(n, ptr(Pp), ptr(np.ascontiguousarray(c)), ptr(lo), ptr(hi), ptr(np.ascontiguousarray(G)),
-                    ptr(h), ptr(z), ptr(mu), ptr(st))
+    args = (ptr(Pp), ptr(np.ascontiguousarray(c)), ptr(lo), ptr(hi), ptr(np.ascontiguousarray(G)), ptr(h))
+    masks = np.zeros(n, dtype=np.int32)
+    emu.emu_line_qp(n, *args, ptr(z), ptr(mu), ptr(st), None, ptr(masks))
     zr, mur, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h)
     assert feas.all() and (st == 0).all()
     scale = 1.0 + np.abs(zr).max(1)
     assert (np.abs(z - zr).max(1) / scale).max() < 1e-8
     mscale = 1.0 + np.abs(mur).max(1)
     assert (np.abs(mu - mur).max(1) / mscale).max() < 1e-6
+    assert (masks != 0).sum() > n // 2  # most instances have active constraints
+    # warm starts: the optimal working set (accepted by the KKT check), a
+    # wrong one (one bit flipped: rejected, then solved from scratch), none
+    rng2 = np.random.default_rng(5)
+    flip = (1 << rng2.integers(0, 10, n)).astype(np.int32)
+    for warm in (masks, masks ^ flip, np.zeros(n, dtype=np.int32)):
+        z2 = np.zeros((n, 4)); mu2 = np.zeros((n, 2)); st2 = np.zeros(n, dtype=np.int32)
+        m2 = np.zeros(n, dtype=np.int32)
+        emu.emu_line_qp(n, *args, ptr(z2), ptr(mu2), ptr(st2), ptr(np.ascontiguousarray(warm, dtype=np.int32)),
+                        ptr(m2))
+        assert (st2 == 0).all()
+        assert (np.abs(z2 - zr).max(1) / scale).max() < 1e-8
+        assert (np.abs(mu2 - mur).max(1) / mscale).max() < 1e-6
+        assert np.array_equal(m2, masks)
 
 
 def test_psd_projection_matches_oracle(emu):
