@@ -144,7 +144,7 @@ def main():
         kern_ms.append(out["admm_ms"])
         pr = dg.residuals(x)["primal"]
         recs.append({"accepted": out["accepted"], "delta": out["delta"], "sweeps": out["admm_sweeps"],
-                     "primal": pr, "objective": out["objective"]})
+                     "admm_ms": out["admm_ms"], "primal": pr, "objective": out["objective"]})
         if t_first_1e4 is None and pr <= 1e-4:
             t_first_1e4 = time.perf_counter() - t0
     torch.cuda.synchronize()
@@ -185,7 +185,8 @@ def main():
                    "last_r": res["r"], "last_s": res["s"], "blocks": res["blocks"]},
         "sqp": {"time_to_1e-4_s": t_first_1e4, "primal_final": pr_final,
                 "accepted": int(sum(r["accepted"] for r in recs)),
-                "primal": [r["primal"] for r in recs], "sweeps": [r["sweeps"] for r in recs]},
+                "primal": [r["primal"] for r in recs], "sweeps": [r["sweeps"] for r in recs],
+                "admm_ms": [r["admm_ms"] for r in recs], "delta": [r["delta"] for r in recs]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload),
                      "kernel": "k_sweep_persistent" if mode == SWEEP_PERSISTENT else "k_line_phase+k_bus_phase",

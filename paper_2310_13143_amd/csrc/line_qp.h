@@ -12,10 +12,12 @@
 //     non-negative (the KKT conditions, which certify the minimiser of a
 //     strictly convex QP).  Between sweeps the working set rarely changes.
 //  2. otherwise the dual active-set method of Goldfarb and Idnani (Math.
-//     Programming 27, 1983) runs from the unconstrained minimiser: add the
-//     most violated constraint, take the primal/dual step that keeps the
-//     active multipliers non-negative (dropping a constraint whose
-//     multiplier reaches zero), until no constraint is violated.
+//     Programming 27, 1983) runs: add the most violated constraint, take the
+//     primal/dual step that keeps the active multipliers non-negative
+//     (dropping a constraint whose multiplier reaches zero), until no
+//     constraint is violated.  It starts from the previous working set when
+//     that set's multipliers are non-negative (a valid state of the method),
+//     else from the unconstrained minimiser with an empty working set.
 //
 // Constraints are numbered 0-3 (lower bounds of z_0..z_3), 4-7 (upper
 // bounds) and 8-9 (the two rows), written as n_k . z >= b_k.  The working
@@ -160,9 +162,14 @@ ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], c
 // placement depends on which constraints are active; LDL^T without
 // pivoting (the system is positive definite).  Returns true, with the
 // minimiser z and the rows' multipliers, if the working set is optimal.
+//
+// dual_ok reports whether the working set is at least dual feasible (its
+// minimiser exists, its multipliers y, by variable then row, are all
+// non-negative and its constraints hold): the dual active-set method may
+// then continue from it instead of starting over.
 ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double lo[4], const double hi[4],
                          const double G[2][4], const double h[2], const double gn[2], int warm_mask, double cs,
-                         double z[4], double mu[2]) {
+                         double z[4], double mu[2], double y[6], bool& dual_ok) {
   double t[4], a[4], beta[4], ar[2];
   bool ok = (warm_mask & (warm_mask >> 4) & 0xF) == 0;  // a lower and an upper bound of one variable
 #pragma unroll
@@ -217,7 +224,6 @@ ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double 
       }
     }
   }
-  double y[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double s = rhs[i];
@@ -247,18 +253,22 @@ ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double 
   }
   // KKT: non-negative multipliers (free sign for a bound of a fixed
   // variable), active constraints met, every other constraint satisfied
+  bool strict = ok;  // every multiplier non-negative, no exception
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const bool fixed_var = lo[v] >= hi[v];
-    ok = ok && (a[v] == 0.0 || fixed_var || y[v] >= -1e-10 * cs);
-    ok = ok && (a[v] == 0.0 || fabs(z[v] - beta[v]) <= 1e-9 * (1.0 + fabs(beta[v])));
+    const bool met = a[v] == 0.0 || fabs(z[v] - beta[v]) <= 1e-9 * (1.0 + fabs(beta[v]));
+    ok = ok && (a[v] == 0.0 || fixed_var || y[v] >= -1e-10 * cs) && met;
+    strict = strict && (a[v] == 0.0 || y[v] >= 0.0) && met;
   }
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    ok = ok && (ar[r] == 0.0 || y[4 + r] >= -1e-10 * cs);
-    ok = ok && (ar[r] == 0.0 || fabs(dot4(G[r], z) - h[r]) <= 1e-9 * (1.0 + fabs(h[r])));
+    const bool met = ar[r] == 0.0 || fabs(dot4(G[r], z) - h[r]) <= 1e-9 * (1.0 + fabs(h[r]));
+    ok = ok && (ar[r] == 0.0 || y[4 + r] >= -1e-10 * cs) && met;
+    strict = strict && (ar[r] == 0.0 || y[4 + r] >= 0.0) && met;
     mu[r] = ar[r] * y[4 + r];
   }
+  dual_ok = strict;
   ok = ok && gi_most_violated(z, warm_mask, lo, hi, G, h, gn) < 0;
   return ok;
 }
@@ -291,8 +301,9 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
 
   // 1. warm start from the previous working set
   if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
-    double zw[4], muw[2];
-    if (warm_check(P, zu, lo, hi, G, h, gn, warm_mask, cs, zw, muw)) {
+    double zw[4], muw[2], yw[6];
+    bool dual_ok = false;
+    if (warm_check(P, zu, lo, hi, G, h, gn, warm_mask, cs, zw, muw, yw, dual_ok)) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(zw[i], lo[i]), hi[i]);
       res.mu[0] = muw[0];
@@ -300,6 +311,33 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
       res.status = 0;
       res.mask = warm_mask;
       return res;
+    }
+    if (dual_ok) {
+      // The working set's minimiser with non-negative multipliers is a valid
+      // state of the dual active-set method: continue from it (it then only
+      // adds the constraints it violates) instead of starting over.
+      int qq = 0;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        if ((warm_mask >> k) & 1) {
+          double n[4], bk;
+          gi_constraint(k, G, lo, hi, h, n, bk);
+          const double uk = (k < 8) ? yw[k & 3] : yw[4 + (k - 8)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool here = (j == qq);
+            act[j] = here ? k : act[j];
+            u[j] = here ? uk : u[j];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) N[j][d] = here ? n[d] : N[j][d];
+          }
+          qq += 1;
+        }
+      }
+      q = qq;
+      mask = warm_mask;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[i] = zw[i];
     }
   }
 

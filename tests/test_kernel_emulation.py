@@ -65,7 +65,11 @@ def test_line_qp_solver_matches_enumeration(emu):
     # wrong one (one bit flipped: rejected, then solved from scratch), none
     rng2 = np.random.default_rng(5)
     flip = (1 << rng2.integers(0, 10, n)).astype(np.int32)
-    for warm in (masks, masks ^ flip, np.zeros(n, dtype=np.int32)):
+    # one active constraint removed: a dual feasible working set whose
+    # minimiser violates the removed constraint (the method continues from it)
+    drop = np.array([m & ~(1 << int(rng2.choice(np.nonzero([(m >> b) & 1 for b in range(10)])[0])))
+                     if m else 0 for m in masks], dtype=np.int32)
+    for warm in (masks, masks ^ flip, drop, np.zeros(n, dtype=np.int32)):
         z2 = np.zeros((n, 4)); mu2 = np.zeros((n, 2)); st2 = np.zeros(n, dtype=np.int32)
         m2 = np.zeros(n, dtype=np.int32)
         emu.emu_line_qp(n, *args, ptr(z2), ptr(mu2), ptr(st2), ptr(np.ascontiguousarray(warm, dtype=np.int32)),
