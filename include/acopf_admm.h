@@ -106,6 +106,8 @@ typedef struct {
   int32_t blocks;            /* grid size the sweeps ran with                        */
   int32_t status;            /* 0, or ACOPF_ERR_NUMERIC / ACOPF_ERR_NONCONVEX_LINE when the
                                 scenario's QP could not be built or factored (not solved) */
+  int32_t relaxed_lines;     /* lines whose limit rows the QP build relaxed because the
+                                line's box and linearised limits had no common point */
 } acopf_admm_result;
 
 /* Layout of an ADMM state held by the caller (export / warm start), line-

@@ -20,6 +20,11 @@ is answered directly (that point is then the minimiser).
 Returns z, the multipliers mu >= 0 of the two limit rows and the face
 multipliers of the bounds; lines without a feasible point are flagged.
 
+``limit_relaxation`` gives the shift of the limit rows that the QP build
+applies to a line whose box and rows have no common point (the paper's
+ADMM keeps progressing on such QPs, Section V, because its augmented
+Lagrangian line solver relaxes the limits instead of failing).
+
 Test infrastructure only (see the package docstring).
 """
 from __future__ import annotations
@@ -58,6 +63,53 @@ def _feasible(z, lo, hi, G, h, tol):
     g = np.einsum("...rj,...j->...r", G, z)
     rs = np.abs(h) + np.einsum("...rj,...j->...r", np.abs(G), np.abs(z)) + 1.0
     return ok & np.all(g <= h + tol * rs, axis=-1)
+
+
+RELAX_REL = 0.1    # margin of the relaxation, relative to the violation
+RELAX_ABS = 1e-9   # and absolute, per unit of 1 + |h_0| + |h_1|
+
+
+def min_max_violation(lo, hi, G, h):
+    """t* = min over lo <= z <= hi of max_r (G_r z - h_r), per line.
+
+    An LP in (z, t): minimise t subject to G_r z - h_r <= t and the box.
+    Its feasible set has no line, so an optimal vertex exists, with five
+    independent active constraints: either four bounds (z a vertex of the
+    box) and a row, or three bounds and both rows (z on an edge of the box,
+    where the two rows are equal).  Both kinds are enumerated (16 vertices,
+    32 edges) and the smallest objective kept."""
+    n = lo.shape[0]
+    best = np.full(n, np.inf)
+    corners = np.array(list(itertools.product((0, 1), repeat=4)), dtype=bool)   # (16, 4)
+    for cb in corners:
+        z = np.where(cb[None], hi, lo)
+        best = np.minimum(best, np.max(np.einsum("nrj,nj->nr", G, z) - h, axis=1))
+    dG = G[:, 0] - G[:, 1]
+    dh = h[:, 0] - h[:, 1]
+    for d in range(4):
+        others = [e for e in range(4) if e != d]
+        for cb in itertools.product((0, 1), repeat=3):
+            z = lo.copy()
+            for e, b in zip(others, cb):
+                z[:, e] = hi[:, e] if b else lo[:, e]
+            # rows equal: dG . z = dh, solved for z_d
+            rest = sum(dG[:, e] * z[:, e] for e in others)
+            ok = dG[:, d] != 0.0
+            zd = np.where(ok, (dh - rest) / np.where(ok, dG[:, d], 1.0), 0.0)
+            ok &= (zd >= lo[:, d]) & (zd <= hi[:, d])
+            z[:, d] = zd
+            t = np.max(np.einsum("nrj,nj->nr", G, z) - h, axis=1)
+            best = np.where(ok, np.minimum(best, t), best)
+    return best
+
+
+def limit_relaxation(lo, hi, G, h):
+    """Shift added to both limit rows of each line: 0 when the box and the
+    rows G z <= h have a common point (t* <= 0), else t* enlarged by a
+    margin, (1 + RELAX_REL) t* + RELAX_ABS (1 + |h_0| + |h_1|), so that the
+    relaxed set has an interior."""
+    t = min_max_violation(lo, hi, G, h)
+    return np.where(t > 0.0, (1.0 + RELAX_REL) * t + RELAX_ABS * (1.0 + np.abs(h).sum(1)), 0.0)
 
 
 def solve_line_qps(Q, c, lo, hi, G, h, tol: float = FEAS_TOL):

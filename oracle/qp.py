@@ -23,6 +23,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .acopf import Iterate, flows, line_hessian
+from .lineqp import limit_relaxation
 
 TWO_PI = 2.0 * np.pi
 
@@ -44,6 +45,7 @@ class LineQP:
     h: np.ndarray    # (L, 2)
     pk: np.ndarray   # (L, 4) flows at the iterate
     c0: np.ndarray   # (L,) 0.5 b^T H b
+    relax: np.ndarray  # (L,) shift already added to both entries of h (lineqp.limit_relaxation)
 
 
 @dataclass
@@ -184,6 +186,10 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
     G[:, 1] = 2 * col(pji) * F[:, 2] + 2 * col(qji) * F[:, 3]
     h = np.stack([grid.smax_ij ** 2 - pij ** 2 - qij ** 2 - 2 * pij * f0[:, 0] - 2 * qij * f0[:, 1],
                   grid.smax_ji ** 2 - pji ** 2 - qji ** 2 - 2 * pji * f0[:, 2] - 2 * qji * f0[:, 3]], 1)
+    # a line whose box and limit rows do not intersect gets both rows relaxed
+    # by the smallest common amount (plus a margin) that makes them intersect
+    relax = limit_relaxation(lo, hi, G, h)
+    h = h + relax[:, None]
 
     # generators (eq. gen_kernel bounds)
     fp = 2 * grid.cost2 * x.pg + grid.cost1
@@ -202,7 +208,7 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
            + np.bincount(f, qij, nb) + np.bincount(t, qji, nb) - grid.bsh * x.w)
 
     return QP(
-        line=LineQP(aR, bR, aI, bI, H, M, q, F, f0, lo, hi, G, h, pk, c0),
+        line=LineQP(aR, bR, aI, bI, H, M, q, F, f0, lo, hi, G, h, pk, c0, relax),
         gen=GenQP(fp, fpp, np.stack([plo, qlo], 1), np.stack([phi, qhi], 1)),
         bus=BusQP(pdk, qdk, blo, bhi),
         delta=float(delta), ref=int(grid.ref),

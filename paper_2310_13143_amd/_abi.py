@@ -49,7 +49,8 @@ class AdmmParams(ctypes.Structure):
 
 class AdmmResult(ctypes.Structure):
     _fields_ = [("sweeps", c_int32), ("outcome", c_int32), ("r_norm", c_double), ("s_norm", c_double),
-                ("infeasible_lines", c_int32), ("blocks", c_int32), ("status", c_int32)]
+                ("infeasible_lines", c_int32), ("blocks", c_int32), ("status", c_int32),
+                ("relaxed_lines", c_int32)]
 
 
 class AdmmState(ctypes.Structure):

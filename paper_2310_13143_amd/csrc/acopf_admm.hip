@@ -118,8 +118,10 @@ __global__ void k_copy_delta(Workspace w, const double* delta) {
 
 __global__ void k_build_lines(acopf_grid g, acopf_iterate x, int mode, Workspace w) {
   for (int l = gtid(); l < g.n_line; l += gstride()) {
-    const double delta = w.scen[w.bus_scen[g.line_from[l]]].delta;
-    if (!build_line(g, x, delta, mode, w, l)) fail_line(w, l, ACOPF_ERR_NUMERIC, &w.sync->numeric_error);
+    ScenState* sc = &w.scen[w.bus_scen[g.line_from[l]]];
+    bool relaxed = false;
+    if (!build_line(g, x, sc->delta, mode, w, l, &relaxed)) fail_line(w, l, ACOPF_ERR_NUMERIC, &w.sync->numeric_error);
+    if (relaxed) atomicAdd(&sc->relaxed, 1);
   }
 }
 
@@ -173,7 +175,10 @@ __global__ void k_clear_flags(Workspace w) {
     w.sync->numeric_error = 0;
     w.sync->nonconvex = 0;
   }
-  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].status = 0;
+  for (int s = gtid(); s < w.n_scen; s += gstride()) {
+    w.scen[s].status = 0;
+    w.scen[s].relaxed = 0;
+  }
 }
 
 // Start of a solve: per-scenario stop state, barrier flags, block tables of
@@ -1140,6 +1145,7 @@ acopf_status acopf_admm_result_batch(const acopf_grid* g, void* workspace, void*
     out[k].infeasible_lines = sc[k].sweeps > 0 ? sc[k].infeasible[(sc[k].sweeps - 1) & 1] : 0;
     out[k].blocks = st.blocks;
     out[k].status = sc[k].status;
+    out[k].relaxed_lines = sc[k].relaxed;
   }
   if (st.barrier_error) return fail(ACOPF_ERR_BARRIER, "acopf_admm_solve: grid barrier timed out");
   if (w.n_scen > 1) return ACOPF_OK;  // failures of a batch are per-scenario outcomes

@@ -19,11 +19,44 @@ ACOPF_HD size_t lc4(int l, int k) { return 4 * (size_t)l + k; }
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
+// Relaxation of the limit rows of a line whose box lo <= z <= hi and rows
+// G z <= h have no common point.  t* = min over the box of max_r (G_r z -
+// h_r) is an LP; by LP duality it equals the maximum over a in [0, 1] of the
+// concave piecewise-linear phi(a) = sum_d min(g_d lo_d, g_d hi_d) - a h_0 -
+// (1 - a) h_1 with g = a G_0 + (1 - a) G_1, whose maximum lies at a = 0, a =
+// 1 or a breakpoint where some g_d vanishes.  Returns the shift added to
+// both rows: 0 if t* <= 0, else 1.1 t* + 1e-9 (1 + |h_0| + |h_1|), a
+// margin that leaves the relaxed set an interior.  (The paper's ADMM keeps
+// progressing on QPs without a feasible point, Section V; this is the
+// relaxation its augmented Lagrangian line solver is read to perform.)
+ACOPF_HD double limit_relaxation(const double lo[4], const double hi[4], const double G[2][4], const double h[2]) {
+  double alpha[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const double den = G[1][d] - G[0][d];
+    const double a = (den != 0.0) ? G[1][d] / den : 0.0;
+    alpha[2 + d] = fmin(fmax(a, 0.0), 1.0);
+  }
+  double t = -1e300;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double a = alpha[k];
+    double phi = -a * h[0] - (1.0 - a) * h[1];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const double gd = a * G[0][d] + (1.0 - a) * G[1][d];
+      phi += fmin(gd * lo[d], gd * hi[d]);
+    }
+    t = fmax(t, phi);
+  }
+  return (t > 0.0) ? 1.1 * t + 1e-9 * (1.0 + fabs(h[0]) + fabs(h[1])) : 0.0;
+}
+
 // QP data of line l at the iterate (Sections III-B, III-C and IV-B2).
 // Returns false if the elimination pivot wR cos + wI sin vanishes or the
-// data are not finite.
+// data are not finite.  *relaxed (optional): the limit rows were relaxed.
 ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double delta, int mode,
-                         const Workspace& w, int l) {
+                         const Workspace& w, int l, bool* relaxed = nullptr) {
   const int L = g.n_line;
   const int f = g.line_from[l], t = g.line_to[l];
   const double wi = x.w[f], wj = x.w[t], thi = x.th[f], thj = x.th[t];
@@ -163,8 +196,11 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
     Gr[1][k] = 2.0 * pji * F[2][k] + 2.0 * qji * F[3][k];
   }
   const double sij = g.smax_ij[l], sji = g.smax_ji[l];
-  const double hr0 = sij * sij - pij * pij - qij * qij - 2.0 * pij * f0[0] - 2.0 * qij * f0[1];
-  const double hr1 = sji * sji - pji * pji - qji * qji - 2.0 * pji * f0[2] - 2.0 * qji * f0[3];
+  double hr[2] = {sij * sij - pij * pij - qij * qij - 2.0 * pij * f0[0] - 2.0 * qij * f0[1],
+                  sji * sji - pji * pji - qji * qji - 2.0 * pji * f0[2] - 2.0 * qji * f0[3]};
+  const double shift = limit_relaxation(lo, hi, Gr, hr);
+  const double hr0 = hr[0] + shift, hr1 = hr[1] + shift;
+  if (relaxed) *relaxed = shift > 0.0;
   ok = ok && isfinite(hr0) && isfinite(hr1) && isfinite(c0);
 
   double* d = w.line;

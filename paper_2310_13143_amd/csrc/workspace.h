@@ -59,7 +59,8 @@ struct ScenState {
   int converged;           // the stop test held at the last sweep
   int infeasible[2];       // infeasible line subproblems, by sweep parity
   int status;              // 0, or the acopf_status of a failed QP build / factorisation
-  int pad[2];
+  int relaxed;             // lines whose limit rows the last QP build relaxed
+  int pad;
   double r_norm, s_norm;   // residual norms of the last sweep
   double delta;            // trust radius of the current SQP iteration
 };

@@ -158,6 +158,7 @@ class DeviceGrid:
     def _result_dict(res: AdmmResult) -> dict:
         return {"sweeps": res.sweeps, "outcome": res.outcome, "r": res.r_norm, "s": res.s_norm,
                 "infeasible_lines": res.infeasible_lines, "blocks": res.blocks, "status": res.status,
+                "relaxed_lines": res.relaxed_lines,
                 "converged": res.outcome == _abi.ADMM_CONVERGED}
 
     def admm_state(self) -> dict:

@@ -30,6 +30,16 @@ void emu_line_qp(int n, const double* P, const double* c, const double* lo, cons
   }
 }
 
+// Limit-row shift of the QP build for n lines (lo, hi (n,4), G (n,2,4), h (n,2)).
+void emu_limit_relaxation(int n, const double* lo, const double* hi, const double* G, const double* h,
+                          double* out) {
+  for (int k = 0; k < n; ++k) {
+    const double Gk[2][4] = {{G[8 * k + 0], G[8 * k + 1], G[8 * k + 2], G[8 * k + 3]},
+                             {G[8 * k + 4], G[8 * k + 5], G[8 * k + 6], G[8 * k + 7]}};
+    out[k] = limit_relaxation(lo + 4 * k, hi + 4 * k, Gk, h + 2 * k);
+  }
+}
+
 void emu_psd_project(int n, double* m) {
   for (int k = 0; k < n; ++k) {
     double a[4][4];

@@ -147,6 +147,25 @@ def test_rgg2000_sweeps_match_oracle():
         _compare_state(st, ref.state)
 
 
+def test_relaxed_lines_match_oracle():
+    """At a trust radius too small for some lines to reach their linearised
+    limits, the build relaxes those lines' rows like the oracle and every
+    line subproblem has a solution."""
+    print("[gpu] rgg2000 relaxed lines", flush=True)
+    g = grid_2000()
+    x, pi = start_point(g, pi_scale=20.0, seed=2)
+    rho = admm.Rho.scalar(g, 2e4)
+    delta = 0.00625
+    Q = qpm.build_qp(g, x, pi, delta, "psd")
+    n_relaxed = int((Q.line.relax > 0).sum())
+    assert n_relaxed > 10
+    ref = admm.solve(g, Q, rho, 6, 0.0, 0.0)
+    assert ref.infeasible_lines == 0
+    _, _, res, st = _run_gpu(g, x, pi, delta, rho, None, None, 6, mode=1)
+    assert res["relaxed_lines"] == n_relaxed and res["infeasible_lines"] == 0
+    _compare_state(st, ref.state)
+
+
 def test_rgg70000_sampled_line_and_bus_updates():
     """At 70,000 buses (88,000 lines, the bench workload) the oracle checks one
     sweep of sampled lines and all buses from the GPU's own previous state."""
@@ -188,7 +207,7 @@ def test_rgg70000_sampled_line_and_bus_updates():
 def _subset_lines(Q, idx):
     import copy
     L = copy.copy(Q.line)
-    for f in ("aR", "bR", "aI", "bI", "H", "M", "q", "F", "f0", "lo", "hi", "G", "h", "pk", "c0"):
+    for f in ("aR", "bR", "aI", "bI", "H", "M", "q", "F", "f0", "lo", "hi", "G", "h", "pk", "c0", "relax"):
         setattr(L, f, getattr(Q.line, f)[idx])
     out = copy.copy(Q)
     out.line = L

@@ -9,7 +9,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from synth.grids import grid_14, tiny_grid, power_flow_start
+from synth.grids import grid_14, grid_2000, tiny_grid, power_flow_start
 from oracle import acopf, admm, lineqp, qp as qpm, sqp
 from paper_2310_13143_amd import _abi
 
@@ -78,6 +78,35 @@ def test_line_qp_solver_matches_enumeration(emu):
         assert (np.abs(z2 - zr).max(1) / scale).max() < 1e-8
         assert (np.abs(mu2 - mur).max(1) / mscale).max() < 1e-6
         assert np.array_equal(m2, masks)
+
+
+def test_limit_relaxation_matches_oracle(emu):
+    """The build's limit-row shift (LP dual over breakpoints) against the
+    oracle's (enumeration of the primal LP's vertices), on random boxes and
+    rows (fixed variables, zero rows, equal row entries) and on the lines of
+    the 2,000-bus grid at a small trust radius."""
+    rng = np.random.default_rng(1)
+    n = 5000
+    lo = -rng.uniform(0, 0.1, (n, 4)); hi = rng.uniform(0, 0.1, (n, 4))
+    lo[::7, 1] = 0.0; hi[::7, 1] = 0.0
+    G = rng.standard_normal((n, 2, 4)); h = rng.uniform(-0.3, 0.1, (n, 2))
+    G[::11, 1] = 0.0
+    G[::13, 0, 2] = G[::13, 1, 2]
+    cases = [(lo, hi, G, h)]
+    g = grid_2000()
+    x, pi = _setup(g, 0.00625, 20.0, 2)
+    Q = qpm.build_qp(g, x, pi, 0.00625, "psd")
+    L = Q.line
+    assert (L.relax > 0).sum() > 10
+    cases.append((L.lo, L.hi, L.G, L.h - L.relax[:, None]))
+    for lo_, hi_, G_, h_ in cases:
+        lo_, hi_, G_, h_ = (np.ascontiguousarray(a) for a in (lo_, hi_, G_, h_))
+        out = np.zeros(lo_.shape[0])
+        emu.emu_limit_relaxation(lo_.shape[0], ptr(lo_), ptr(hi_), ptr(G_), ptr(h_), ptr(out))
+        ref = lineqp.limit_relaxation(lo_, hi_, G_, h_)
+        assert np.array_equal(out > 0, ref > 0)
+        scale = 1.0 + np.abs(h_).sum(1) + np.abs(G_).sum((1, 2)) * np.maximum(np.abs(lo_), np.abs(hi_)).max(1)
+        assert (np.abs(out - ref) / scale).max() < 1e-14
 
 
 def test_psd_projection_matches_oracle(emu):

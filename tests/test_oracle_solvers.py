@@ -65,6 +65,38 @@ def test_line_qp_unconstrained_and_infeasible():
     assert not feas.any()
 
 
+def test_limit_relaxation_against_linprog_and_hand_case():
+    """t* = min over the box of the larger row violation: the oracle's vertex
+    and edge enumeration against SciPy's LP solver; the shift is zero for
+    lines with a feasible point and makes the others feasible."""
+    from scipy.optimize import linprog
+    rng = np.random.default_rng(0)
+    n = 200
+    lo = -rng.uniform(0, 0.1, (n, 4)); hi = rng.uniform(0, 0.1, (n, 4))
+    lo[::7, 1] = 0.0; hi[::7, 1] = 0.0
+    G = rng.standard_normal((n, 2, 4)); h = rng.uniform(-0.3, 0.1, (n, 2))
+    G[::11, 1] = 0.0
+    t = lineqp.min_max_violation(lo, hi, G, h)
+    for k in range(n):
+        r = linprog(np.r_[np.zeros(4), 1.0], A_ub=np.hstack([G[k], -np.ones((2, 1))]), b_ub=h[k],
+                    bounds=[(lo[k, i], hi[k, i]) for i in range(4)] + [(None, None)], method="highs")
+        assert r.status == 0 and abs(t[k] - r.fun) < 1e-12
+    assert 0.2 < (t > 0).mean() < 0.9
+    shift = lineqp.limit_relaxation(lo, hi, G, h)
+    assert np.all(shift[t <= 0] == 0.0)
+    assert np.all(shift[t > 0] > t[t > 0])
+    Q = np.broadcast_to(np.eye(4), (n, 4, 4)).copy()
+    c = rng.standard_normal((n, 4))
+    _, _, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h + shift[:, None])
+    assert feas.all()
+    # box [0, 1]^4, rows sum(z) <= -1 and 0 <= 1: t* = 1 at z = 0
+    lo1, hi1 = np.zeros((1, 4)), np.ones((1, 4))
+    G1 = np.zeros((1, 2, 4)); G1[0, 0] = 1.0
+    h1 = np.array([[-1.0, 1.0]])
+    assert lineqp.min_max_violation(lo1, hi1, G1, h1)[0] == 1.0
+    assert lineqp.limit_relaxation(lo1, hi1, G1, h1)[0] == pytest.approx(1.1 + 3e-9, rel=1e-15)
+
+
 def test_gen_update_matches_scalar_minimisation():
     g = tiny_grid(seed=2, n_bus=8, n_line=10, n_gen=5)
     rng = np.random.default_rng(3)
