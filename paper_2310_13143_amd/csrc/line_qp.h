@@ -57,31 +57,27 @@ ACOPF_HD void gi_constraint(int k, const double G[2][4], const double lo[4], con
   b = row ? -(r == 0 ? h[0] : h[1]) : ((k < 4) ? lo[v] : -hi[v]);
 }
 
-// Solve S y = rhs for the q x q leading block of S (SPD), padded to 4x4.
+// Solve S y = rhs for the q x q leading block of S (symmetric positive
+// definite, lower triangle read), padded to 4x4 with the identity: LDL^T
+// without square roots (E = L D is kept beside L).
 ACOPF_HD void spd_solve_padded(const double S[4][4], int q, const double rhs[4], double y[4]) {
-  double A[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) A[a][b] = (a < q && b < q) ? S[a][b] : ((a == b) ? 1.0 : 0.0);
-  double L[4][4], inv_d[4];
+  double L[4][4], E[4][4], dinv[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    double d = A[j][j];
+    double d = (j < q) ? S[j][j] : 1.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (k < j) d -= L[j][k] * L[j][k];
-    const double ljj = sqrt(fmax(d, 1e-300));
-    inv_d[j] = 1.0 / ljj;
-    L[j][j] = ljj;
+      if (k < j) d -= L[j][k] * E[j][k];
+    dinv[j] = 1.0 / fmax(d, 1e-300);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (i > j) {
-        double s = A[i][j];
+        double e = (i < q && j < q) ? S[i][j] : 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (k < j) s -= L[i][k] * L[j][k];
-        L[i][j] = s * inv_d[j];
+          if (k < j) e -= L[i][k] * E[j][k];
+        E[i][j] = e;
+        L[i][j] = e * dinv[j];
       }
     }
   }
@@ -92,22 +88,23 @@ ACOPF_HD void spd_solve_padded(const double S[4][4], int q, const double rhs[4],
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (k < i) s -= L[i][k] * t[k];
-    t[i] = s * inv_d[i];
+    t[i] = s;
   }
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
     const int i = 3 - ii;
-    double s = t[i];
+    double s = t[i] * dinv[i];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (k > i) s -= L[k][i] * y[k];
-    y[i] = s * inv_d[i];
+    y[i] = s;
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) y[a] = (a < q) ? y[a] : 0.0;
 }
 
-// Working-set products: W[:, j] = P N_j and S = N^T P N (padded).
+// Working-set products: W[:, j] = P N_j and the lower triangle of
+// S = N^T P N (padded).
 ACOPF_HD void gi_products(const double P[4][4], const double N[4][4], int q, double W[4][4], double S[4][4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -120,13 +117,14 @@ ACOPF_HD void gi_products(const double P[4][4], const double N[4][4], int q, dou
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      S[a][b] = N[a][0] * W[0][b] + N[a][1] * W[1][b] + N[a][2] * W[2][b] + N[a][3] * W[3][b];
+      if (b <= a) S[a][b] = N[a][0] * W[0][b] + N[a][1] * W[1][b] + N[a][2] * W[2][b] + N[a][3] * W[3][b];
 }
 
 // Most violated constraint outside the working set at z (scaled by the
-// constraint's 1-norm); -1 if none is violated beyond the tolerance.
+// constraint's 1-norm gn, ign = 1 / gn or 0); -1 if none is violated beyond
+// the tolerance.
 ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], const double hi[4],
-                              const double G[2][4], const double h[2], const double gn[2]) {
+                              const double G[2][4], const double h[2], const double gn[2], const double ign[2]) {
   const double zs = fabs(z[0]) + fabs(z[1]) + fabs(z[2]) + fabs(z[3]);
   int p = -1;
   double worst = 0.0;
@@ -145,7 +143,7 @@ ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], c
   for (int r = 0; r < 2; ++r) {
     const double gz = G[r][0] * z[0] + G[r][1] * z[1] + G[r][2] * z[2] + G[r][3] * z[3];
     const double s = h[r] - gz;
-    const double sc = s / fmax(gn[r], 1e-300);
+    const double sc = s * ign[r];
     const bool v = gn[r] > 0.0 && !((mask >> (8 + r)) & 1) && s < -1e-12 * (1.0 + fabs(h[r]) + gn[r] * zs) &&
                    sc < worst;
     worst = v ? sc : worst;
@@ -168,8 +166,8 @@ ACOPF_HD int gi_most_violated(const double z[4], int mask, const double lo[4], c
 // non-negative and its constraints hold): the dual active-set method may
 // then continue from it instead of starting over.
 ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double lo[4], const double hi[4],
-                         const double G[2][4], const double h[2], const double gn[2], int warm_mask, double cs,
-                         double z[4], double mu[2], double y[6], bool& dual_ok) {
+                         const double G[2][4], const double h[2], const double gn[2], const double ign[2],
+                         int warm_mask, double cs, double z[4], double mu[2], double y[6], bool& dual_ok) {
   double t[4], a[4], beta[4], ar[2];
   bool ok = (warm_mask & (warm_mask >> 4) & 0xF) == 0;  // a lower and an upper bound of one variable
 #pragma unroll
@@ -269,7 +267,7 @@ ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double 
     mu[r] = ar[r] * y[4 + r];
   }
   dual_ok = strict;
-  ok = ok && gi_most_violated(z, warm_mask, lo, hi, G, h, gn) < 0;
+  ok = ok && gi_most_violated(z, warm_mask, lo, hi, G, h, gn, ign) < 0;
   return ok;
 }
 
@@ -282,6 +280,7 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
   sym_unpack(Pp, P);
   const double gn[2] = {fabs(G[0][0]) + fabs(G[0][1]) + fabs(G[0][2]) + fabs(G[0][3]),
                         fabs(G[1][0]) + fabs(G[1][1]) + fabs(G[1][2]) + fabs(G[1][3])};
+  const double ign[2] = {gn[0] > 0.0 ? 1.0 / gn[0] : 0.0, gn[1] > 0.0 ? 1.0 / gn[1] : 0.0};
   double zu[4];
   matvec4(P, c, zu);
 #pragma unroll
@@ -303,7 +302,7 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
   if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
     double zw[4], muw[2], yw[6];
     bool dual_ok = false;
-    if (warm_check(P, zu, lo, hi, G, h, gn, warm_mask, cs, zw, muw, yw, dual_ok)) {
+    if (warm_check(P, zu, lo, hi, G, h, gn, ign, warm_mask, cs, zw, muw, yw, dual_ok)) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(zw[i], lo[i]), hi[i]);
       res.mu[0] = muw[0];
@@ -344,7 +343,7 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
   // 2. dual active-set method
   int steps = 0;
   while (!done) {
-    const int p = gi_most_violated(z, mask, lo, hi, G, h, gn);
+    const int p = gi_most_violated(z, mask, lo, hi, G, h, gn, ign);
     if (p < 0) break;
     double np_[4], bp;
     gi_constraint(p, G, lo, hi, h, np_, bp);
@@ -364,16 +363,18 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
 #pragma unroll
       for (int i = 0; i < 4; ++i) dz[i] = v[i] - (W[i][0] * r[0] + W[i][1] * r[1] + W[i][2] * r[2] + W[i][3] * r[3]);
       // dual step length: first active multiplier that would become negative
-      double t1 = INF;
+      // (smallest u_j / r_j over r_j > 0, compared as u_j r_k < u_k r_j)
       int kdrop = -1;
+      double un = 0.0, rd = 1.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool cand = (j < q) && (r[j] > 0.0);
-        const double ratio = cand ? u[j] / r[j] : INF;
-        const bool better = cand && ratio < t1;
-        t1 = better ? ratio : t1;
+        const bool better = cand && (kdrop < 0 || u[j] * rd < un * r[j]);
+        un = better ? u[j] : un;
+        rd = better ? r[j] : rd;
         kdrop = better ? j : kdrop;
       }
+      const double t1 = (kdrop >= 0) ? un / rd : INF;
       // primal step length: reach constraint p
       const double nz = dot4(np_, dz);
       const double t2 = (nz > 1e-14 * npn) ? -(dot4(np_, z) - bp) / nz : INF;
