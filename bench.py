@@ -189,7 +189,7 @@ def main():
                 "admm_ms": [r["admm_ms"] for r in recs], "delta": [r["delta"] for r in recs]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload),
-                     "kernel": "k_sweep_persistent" if mode == SWEEP_PERSISTENT else "k_line_phase+k_bus_phase",
+                     "kernel": "k_sweep_persistent" if mode == SWEEP_PERSISTENT else "k_line_phase+k_bus_items",
                      "bytes_per_sweep": bsweep, "avg_launch_ms": avg_launch_s * 1e3,
                      "us_per_sweep": avg_launch_s / avg_sweeps * 1e6},
         "cpu_baseline": cpu,
@@ -264,7 +264,7 @@ def bench_batch(args):
                   "accepted": int(sum(o[k]["accepted"] for o in outs for k in range(len(grids)))),
                   "primal_max": float(max(r["primal"] for r in res)), "block": bs},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload), "kernel": "k_line_phase+k_bus_phase",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload), "kernel": "k_line_phase+k_bus_items",
                      "bytes_per_sweep": bsweep, "us_per_sweep": float(per_sweep_ms.mean()) * 1e3},
         "cpu_baseline": None,
     }

@@ -183,7 +183,7 @@ __global__ void k_clear_flags(Workspace w) {
 
 // Start of a solve: per-scenario stop state, barrier flags, block tables of
 // both phases for block size bs.
-__global__ void k_reset_solve(Workspace w, int blocks, int bs) {
+__global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
   for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
     ScenState* sc = &w.scen[s];
@@ -214,6 +214,8 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs) {
     }
     w.line_blk_off[w.n_scen] = lb;
     w.bus_blk_off[w.n_scen] = bb;
+    if (items)  // the bus phase runs by item blocks: its partials follow them
+      for (int s = 0; s <= w.n_scen; ++s) w.bus_blk_off[s] = w.item_blk_off[s];
   }
 }
 
@@ -270,47 +272,79 @@ k_line_phase(acopf_grid g, Workspace w, int single) {
   if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
-// Bus phase of the launch-per-phase mode.  With `fold` (a single scenario
-// with a small grid) the last block to finish, by atomic ticket, ends the
-// sweep; each block then pays a device-scope fence, which only pays off for
-// small grids.  Otherwise k_finish_phase ends the sweep as a third launch.
+// Bus phase by coupling items (launch modes): one thread per line end or
+// generator, the items of a bus in consecutive threads of one block.  Each
+// thread loads its item's couplings and writes its terms of the bus sums to
+// LDS; the bus's first thread adds them (fixed order) and solves the bus's
+// closed form; then every thread updates its couplings.  A bus of degree d
+// costs one round of independent loads on d threads instead of a
+// dependent walk over its CSR on one.  Blocks past a scenario's last item
+// block exit at once; with `fold` the last block ends the sweep.
 template <bool kTrace>
-__global__ void __launch_bounds__(256) k_bus_phase(acopf_grid g, Workspace w, int single, int fold, int max_sweeps,
-                                                   double eps_pri, double eps_dual) {
+__global__ void __launch_bounds__(kItemBlock) k_bus_items(acopf_grid g, Workspace w, int single, int fold,
+                                                          int max_sweeps, double eps_pri, double eps_dual) {
+  __shared__ double terms[8][kItemBlock];
+  __shared__ double bres[6][kItemBlock];
   __shared__ double lds[16];
   __shared__ int s_last;
-  int s = 0, i, end;
-  if (single) {  // exactly ceil(n_bus / block) blocks
-    if (w.scen[0].done) return;
-    i = blockIdx.x * blockDim.x + threadIdx.x;
-    end = w.n_bus;
+  if (single) {
+    if (w.scen[0].done || (int)blockIdx.x >= w.item_blk_off[1]) return;
   } else {
     if (batch_done(w)) return;
-    s = scen_of_block(w.bus_blk_off, w.n_scen, blockIdx.x);
+    const int s = scen_of_block(w.item_blk_off, w.n_scen, blockIdx.x);
     if (s < 0 || w.scen[s].done) return;
-    i = w.scen_bus_off[s] + (blockIdx.x - w.bus_blk_off[s]) * blockDim.x + threadIdx.x;
-    end = w.scen_bus_off[s + 1];
   }
-  double r2 = 0.0, s2 = 0.0;
-  if (i < end) update_bus<kTrace>(g, w, i, r2, s2);
-  r2 = block_sum(r2, lds);
-  s2 = block_sum(s2, lds);
-  if (threadIdx.x == 0) {
-    w.partials[blockIdx.x] = r2;
-    w.partials[w.max_partials + blockIdx.x] = s2;
+  const int t = threadIdx.x;
+  const size_t slot = (size_t)blockIdx.x * kItemBlock + t;
+  const int code = w.item_code[slot], bus = w.item_bus[slot], head = w.item_head[slot], len = w.item_len[slot];
+  const bool lead = bus >= 0 && t == head;
+  double bc[7];
+  if (lead) bus_item_consts(g, w, bus, bc);
+  double v[14], a[8];
+  bus_item_terms(w, code, v, a);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) terms[m][t] = a[m];
+  __syncthreads();
+  if (lead) {
+    double sum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < len; ++j)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) sum[m] += terms[m][t + j];
+    double out[6];
+    bus_item_solve(sum, bc, out);
+    w.dw[bus] = out[2];
+    w.dth[bus] = out[3];
+    w.nu[bus] = out[0];
+    w.nu[w.n_bus + bus] = out[1];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) bres[m][t] = out[m];
+  }
+  __syncthreads();
+  double rr = 0.0, ss = 0.0;
+  if (bus >= 0) {
+    double res[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) res[m] = bres[m][head];
+    bus_item_update<kTrace>(w, code, v, res, rr, ss);
+  }
+  rr = block_sum(rr, lds);
+  ss = block_sum(ss, lds);
+  if (t == 0) {
+    w.partials[blockIdx.x] = rr;
+    w.partials[w.max_partials + blockIdx.x] = ss;
   }
   if (!fold) return;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     __threadfence();
     const unsigned int ticket = atomicAdd(&w.sync->count, 1u);
-    s_last = (ticket == gridDim.x - 1u) ? 1 : 0;  // fold runs with one scenario and exact blocks
+    s_last = (ticket == (unsigned int)w.item_blk_off[1] - 1u) ? 1 : 0;  // fold runs with one scenario
     if (s_last) __threadfence();
   }
   __syncthreads();
   if (s_last) {
-    finish_scenario(w, 0, 0, w.bus_blk_off[1], max_sweeps, eps_pri, eps_dual, lds);
-    if (threadIdx.x == 0) w.sync->count = 0;
+    finish_scenario(w, 0, 0, w.item_blk_off[1], max_sweeps, eps_pri, eps_dual, lds);
+    if (t == 0) w.sync->count = 0;
   }
 }
 
@@ -784,7 +818,50 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
     ends[fill[to[l]]++] = 2 * l + 1;
   }
   for (int q = 0; q < ng; ++q) gens[gfill[gb[q]]++] = q;
+  // coupling items of the bus phase: per scenario, bus by bus, its
+  // generators then its line ends (CSR order) in consecutive slots of one
+  // block; a bus that does not fit the current block starts the next one
+  const int32_t nib = item_blocks_bound(nl, ng, ns);
+  std::vector<int32_t> icode((size_t)nib * kItemBlock, kItemPad), ibus((size_t)nib * kItemBlock, -1),
+      ihead((size_t)nib * kItemBlock), ilen((size_t)nib * kItemBlock, 0), iblk(ns + 1);
+  for (size_t q = 0; q < ihead.size(); ++q) ihead[q] = (int32_t)(q % kItemBlock);
+  int32_t blk = 0;
+  for (int k = 0; k < ns; ++k) {
+    iblk[k] = blk;
+    int fill = 0;
+    bool open = false;
+    for (int i = bus_off_h[k]; i < bus_off_h[k + 1]; ++i) {
+      const int n = gdeg[i] + deg[i];
+      if (n > kItemBlock)
+        return fail(ACOPF_ERR_UNSUPPORTED, "acopf_setup: bus " + std::to_string(i) + " has " + std::to_string(n) +
+                                               " line ends and generators (at most " + std::to_string(kItemBlock) + ")");
+      if (!open || fill + n > kItemBlock) {
+        if (open) ++blk;
+        open = true;
+        fill = 0;
+      }
+      const size_t base = (size_t)blk * kItemBlock;
+      int j = fill;
+      for (int q = gptr[i]; q < gptr[i + 1]; ++q) icode[base + j++] = -(gens[q] + 1);
+      for (int e = eptr[i]; e < eptr[i + 1]; ++e) icode[base + j++] = ends[e];
+      for (int m = fill; m < fill + n; ++m) {
+        ibus[base + m] = i;
+        ihead[base + m] = fill;
+        ilen[base + m] = n;
+      }
+      fill += n;
+    }
+    if (open) ++blk;
+  }
+  iblk[ns] = blk;
+  if (blk > nib) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_setup: item blocks exceed their bound");
   Workspace w = ws_of(g, workspace);
+  const size_t used = (size_t)blk * kItemBlock * sizeof(int32_t);
+  HIP_TRY(hipMemcpy(w.item_code, icode.data(), used, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.item_bus, ibus.data(), used, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.item_head, ihead.data(), used, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.item_len, ilen.data(), used, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.item_blk_off, iblk.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.bus_end_ptr, eptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.bus_end, ends.data(), 2 * (size_t)nl * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.bus_gen_ptr, gptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -874,11 +951,11 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single);
     if (a.trace)
-      hipLaunchKernelGGL(k_bus_phase<true>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.single, a.fold,
-                         a.max_sweeps, a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL(k_bus_items<true>, dim3((unsigned)a.nbb), dim3(kItemBlock), 0, s, a.g, a.w, a.single,
+                         a.fold, a.max_sweeps, a.eps_pri, a.eps_dual);
     else
-      hipLaunchKernelGGL(k_bus_phase<false>, dim3((unsigned)a.nbb), dim3(a.bs), 0, s, a.g, a.w, a.single, a.fold,
-                         a.max_sweeps, a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL(k_bus_items<false>, dim3((unsigned)a.nbb), dim3(kItemBlock), 0, s, a.g, a.w, a.single,
+                         a.fold, a.max_sweeps, a.eps_pri, a.eps_dual);
     if (!a.fold)
       hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(256), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
   }
@@ -1032,7 +1109,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   const int ns = w.n_scen;
   const int reset_blocks = blocks_for(std::max(w.max_partials, ns), 256);
   if (p->max_sweeps == 0) {
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, 0, bs);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, 0, bs, 0);
     HIP_TRY(hipGetLastError());
     if (result) return acopf_admm_result_get(g, workspace, stream, result);
     return ACOPF_OK;
@@ -1055,7 +1132,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     // per-scenario block counts (excess blocks exit)
     const int single = ns == 1 ? 1 : 0;
     const long long nbl = (g->n_line + bs - 1) / bs + (single ? 0 : ns);
-    const long long nbb = (g->n_bus + bs - 1) / bs + (single ? 0 : ns);
+    // bus phase by item blocks (bound from the sizes; excess blocks exit)
+    const long long nbb = item_blocks_bound(g->n_line, g->n_gen, ns);
     if (nbb > w.max_partials || nbl > 65535 || nbb > 65535)
       return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: grid too large for the block size");
     SweepLaunch a;
@@ -1077,7 +1155,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
       HIP_TRY(hipStreamIsCapturing(s, &cap));
       use_graph = cap == hipStreamCaptureStatusNone;
     }
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs, 1);
     for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
       const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
       hipGraphExec_t ge = nullptr;
@@ -1114,7 +1192,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     if (p->max_blocks > 0) nblk = std::min<long long>(nblk, p->max_blocks);
     nblk = std::min<long long>(nblk, w.max_partials);
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nblk, bs);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nblk, bs, 0);
     acopf_grid gg = *g;
     int ms = p->max_sweeps;
     double ep = p->eps_pri, ed = p->eps_dual;

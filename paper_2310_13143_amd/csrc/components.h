@@ -575,6 +575,161 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
   s2 += ss;
 }
 
+// The bus update of update_bus split by coupling item (one line end or one
+// generator of the bus), for a bus phase that gives each item its own
+// thread.  Same formulas; the bus sums are added in the same order
+// (generators, then line ends in CSR order).
+//
+// First half: the item's terms of the bus sums (spp, sqq, rp, rq, qw, cw,
+// qt, ct); a generator is updated first (eq. gen_kernel).  v keeps the
+// item's values for the second half: a line end rho, x, lam of its p, q, w,
+// th couplings and the bus-side flow copies; a generator rho, x, lam and the
+// bus-side copies of p and q.
+ACOPF_HD void bus_item_terms(const Workspace& w, int code, double v[14], double a[8]) {
+#pragma unroll
+  for (int m = 0; m < 8; ++m) a[m] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 14; ++m) v[m] = 1.0;
+  if (code >= 0) {
+    const int l = code >> 1, sd = code & 1;
+    const int kp = 2 * sd, kw = 4 + 2 * sd;
+    v[0] = w.rho_l[lc8(l, kp)];
+    v[1] = w.rho_l[lc8(l, kp + 1)];
+    v[2] = w.rho_l[lc8(l, kw)];
+    v[3] = w.rho_l[lc8(l, kw + 1)];
+    v[4] = w.xl[lc8(l, kp)];
+    v[5] = w.xl[lc8(l, kp + 1)];
+    v[6] = w.xl[lc8(l, kw)];
+    v[7] = w.xl[lc8(l, kw + 1)];
+    v[8] = w.lam_l[lc8(l, kp)];
+    v[9] = w.lam_l[lc8(l, kp + 1)];
+    v[10] = w.lam_l[lc8(l, kw)];
+    v[11] = w.lam_l[lc8(l, kw + 1)];
+    v[12] = w.xbar_f[lc4(l, kp)];
+    v[13] = w.xbar_f[lc4(l, kp + 1)];
+    const double ip = 1.0 / v[0], iq = 1.0 / v[1];
+    a[0] = ip;
+    a[1] = iq;
+    a[2] = -(v[4] + v[8] * ip);
+    a[3] = -(v[5] + v[9] * iq);
+    a[4] = v[2];
+    a[5] = v[2] * v[6] + v[10];
+    a[6] = v[3];
+    a[7] = v[3] * v[7] + v[11];
+  } else if (code != kItemPad) {
+    const int G = w.n_gen, k = -code - 1;
+    update_gen(w, k);
+    v[0] = w.rho_g[k];
+    v[1] = w.rho_g[G + k];
+    v[2] = w.xg[k];
+    v[3] = w.xg[G + k];
+    v[4] = w.lam_g[k];
+    v[5] = w.lam_g[G + k];
+    v[6] = w.xbar_g[k];
+    v[7] = w.xbar_g[G + k];
+    const double ip = 1.0 / v[0], iq = 1.0 / v[1];
+    a[0] = ip;
+    a[1] = iq;
+    a[2] = v[2] + v[4] * ip;
+    a[3] = v[3] + v[5] * iq;
+  }
+}
+
+// Constants of bus i for its closed form: shunt g, b, p^{d,(k)}, q^{d,(k)},
+// reference flag, and the bus values of the previous sweep.
+ACOPF_HD void bus_item_consts(const acopf_grid& g, const Workspace& w, int i, double bc[7]) {
+  bc[0] = g.gsh[i];
+  bc[1] = g.bsh[i];
+  bc[2] = w.bus_pdk[i];
+  bc[3] = w.bus_qdk[i];
+  bc[4] = (w.bus_flags[i] & BUS_REF) ? 1.0 : 0.0;
+  bc[5] = w.dw[i];
+  bc[6] = w.dth[i];
+}
+
+// Closed form of bus i from its summed terms (as in update_bus):
+// out = (nu_p, nu_q, d_w, d_th, previous d_w, previous d_th).
+ACOPF_HD void bus_item_solve(const double sum[8], const double bc[7], double out[6]) {
+  double spp = sum[0], sqq = sum[1], rp = sum[2], rq = sum[3];
+  const double qw = sum[4], cw = sum[5], qt = sum[6], ct = sum[7];
+  const double gsh = bc[0], bsh = bc[1];
+  const double iqw = 1.0 / qw;
+  spp += gsh * gsh * iqw;
+  sqq += bsh * bsh * iqw;
+  const double spq = -gsh * bsh * iqw;
+  rp += -gsh * cw * iqw - bc[2];
+  rq += bsh * cw * iqw - bc[3];
+  const double idet = 1.0 / (spp * sqq - spq * spq);
+  const double nup = (sqq * rp - spq * rq) * idet;
+  const double nuq = (spp * rq - spq * rp) * idet;
+  out[0] = nup;
+  out[1] = nuq;
+  out[2] = (cw + gsh * nup - bsh * nuq) * iqw;
+  out[3] = (bc[4] != 0.0) ? 0.0 : ct / qt;
+  out[4] = bc[5];
+  out[5] = bc[6];
+}
+
+// Second half: the item's multiplier and bus-side copy updates (eq.
+// multiplier) given its bus's closed form, and its terms of ||r||^2 and
+// ||s||^2 (kTrace: also the trace sums).
+template <bool kTrace = false>
+ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], const double res[6], double& rr,
+                              double& ss) {
+  if (code >= 0) {
+    const int L = w.n_line;
+    const int l = code >> 1, sd = code & 1;
+    const int kp = 2 * sd, kw = 4 + 2 * sd;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double rho = v[m], xv = v[4 + m], lam = v[8 + m];
+      const double lam_new = -res[m];
+      const double xb = xv + (lam - lam_new) / rho;
+      const double ds = rho * (xb - v[12 + m]);
+      w.lam_l[lc8(l, kp + m)] = lam_new;
+      w.xbar_f[lc4(l, kp + m)] = xb;
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+      if (kTrace) {
+        w.tr_r_l[(kp + m) * L + l] += fabs(xv - xb);
+        w.tr_s_l[(kp + m) * L + l] += fabs(ds);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double rho = v[2 + m], xv = v[6 + m], lam = v[10 + m];
+      const double xb = res[2 + m];
+      const double ds = rho * (xb - res[4 + m]);
+      w.lam_l[lc8(l, kw + m)] = lam + rho * (xv - xb);
+      w.xbar_v[lc4(l, 2 * sd + m)] = xb;
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+      if (kTrace) {
+        w.tr_r_l[(kw + m) * L + l] += fabs(xv - xb);
+        w.tr_s_l[(kw + m) * L + l] += fabs(ds);
+      }
+    }
+  } else if (code != kItemPad) {
+    const int G = w.n_gen, k = -code - 1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int idx = j * G + k;
+      const double rho = v[j], xv = v[2 + j], lam = v[4 + j];
+      const double lam_new = res[j];
+      const double xb = xv + (lam - lam_new) / rho;
+      const double ds = rho * (xb - v[6 + j]);
+      w.lam_g[idx] = lam_new;
+      w.xbar_g[idx] = xb;
+      rr += (xv - xb) * (xv - xb);
+      ss += ds * ds;
+      if (kTrace) {
+        w.tr_r_g[idx] += fabs(xv - xb);
+        w.tr_s_g[idx] += fabs(ds);
+      }
+    }
+  }
+}
+
 // Step and multiplier estimates of line l (Section IV-B5).
 ACOPF_HD void step_line(const acopf_grid& g, const acopf_iterate& x, const Workspace& w,
                         const acopf_iterate& d, int l) {

@@ -96,6 +96,13 @@ struct Workspace {
   int32_t* scen_gen_off;   // [n_scen + 1]
   int32_t* line_blk_off;   // [n_scen + 1] first block of each scenario in the line phase
   int32_t* bus_blk_off;    // [n_scen + 1] same for the bus phase
+  // bus phase by coupling items (launch modes): the generators, then the
+  // line ends of each bus in consecutive slots of one kItemBlock-slot block
+  int32_t* item_code;      // [slots] 2 l + side for a line end, -(k + 1) for generator k, kItemPad
+  int32_t* item_bus;       // [slots] bus of the item (-1 for padding)
+  int32_t* item_head;      // [slots] slot (within the block) of the bus's first item
+  int32_t* item_len;       // [slots] number of items of the bus
+  int32_t* item_blk_off;   // [n_scen + 1] first item block of each scenario
   // QP data
   double* line;            // [LF_COUNT][n_line]
   double* gen;             // [GF_COUNT][n_gen]
@@ -130,10 +137,24 @@ struct Workspace {
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline int32_t max_partials_for(int32_t nb, int32_t nl, int32_t ns) {
-  // bus-phase blocks of 64 threads (plus one partial block per scenario)
-  // and the largest persistent grid
+// Item blocks of the bus phase: kItemBlock slots, one thread each.  A bus's
+// items never straddle two blocks, so two consecutive blocks of a scenario
+// hold more than kItemBlock items together; this bounds the block count by
+// the sizes alone (blocks past a scenario's last one exit at once).
+constexpr int32_t kItemBlock = 256;
+constexpr int32_t kItemPad = -0x7fffffff;
+
+inline int32_t item_blocks_bound(int32_t nl, int32_t ng, int32_t ns) {
+  const int64_t items = 2 * (int64_t)nl + ng;
+  return (int32_t)(2 * ((items + kItemBlock - 1) / kItemBlock) + 2 * (int64_t)ns + 1);
+}
+
+inline int32_t max_partials_for(int32_t nb, int32_t nl, int32_t ng, int32_t ns) {
+  // bus-phase blocks of 64 threads (plus one partial block per scenario),
+  // item blocks and the largest persistent grid
   int32_t need = (nb > nl ? nb : nl) / 64 + 2 * ns + 64;
+  const int32_t items = item_blocks_bound(nl, ng, ns);
+  need = need > items ? need : items;
   return need > 4096 ? need : 4096;
 }
 
@@ -148,7 +169,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
     return p;
   };
   const size_t D = sizeof(double), I = sizeof(int32_t);
-  const int32_t maxp = max_partials_for(nb, nl, ns);
+  const int32_t maxp = max_partials_for(nb, nl, ng, ns);
   Workspace t;
   t.n_bus = nb; t.n_line = nl; t.n_gen = ng; t.n_scen = ns; t.max_partials = maxp;
   t.bus_end_ptr = (int32_t*)take((size_t)(nb + 1) * I);
@@ -162,6 +183,12 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.scen_gen_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.line_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.bus_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
+  const size_t slots = (size_t)item_blocks_bound(nl, ng, ns) * kItemBlock;
+  t.item_code = (int32_t*)take(slots * I);
+  t.item_bus = (int32_t*)take(slots * I);
+  t.item_head = (int32_t*)take(slots * I);
+  t.item_len = (int32_t*)take(slots * I);
+  t.item_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.line = (double*)take((size_t)LF_COUNT * nl * D);
   t.gen = (double*)take((size_t)GF_COUNT * ng * D);
   t.bus_pdk = (double*)take((size_t)nb * D);

@@ -49,6 +49,32 @@ void emu_psd_project(int n, double* m) {
   }
 }
 
+// Bus phase used by emu_run: 0 = update_bus per bus, 1 = the per-item
+// decomposition of the launch-mode kernel (items of a bus: generators, then
+// line ends in CSR order), summed in item order.
+static int g_bus_items = 0;
+void emu_set_bus_items(int on) { g_bus_items = on; }
+
+static void bus_by_items(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2) {
+  std::vector<int> codes;
+  for (int e = w.bus_gen_ptr[i]; e < w.bus_gen_ptr[i + 1]; ++e) codes.push_back(-(w.bus_gen[e] + 1));
+  for (int e = w.bus_end_ptr[i]; e < w.bus_end_ptr[i + 1]; ++e) codes.push_back(w.bus_end[e]);
+  const size_t n = codes.size();
+  std::vector<double> v(14 * n), a(8 * n);
+  double bc[7];
+  bus_item_consts(g, w, i, bc);
+  for (size_t j = 0; j < n; ++j) bus_item_terms(w, codes[j], &v[14 * j], &a[8 * j]);
+  double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0}, out[6];
+  for (size_t j = 0; j < n; ++j)
+    for (int m = 0; m < 8; ++m) sum[m] += a[8 * j + m];
+  bus_item_solve(sum, bc, out);
+  w.dw[i] = out[2];
+  w.dth[i] = out[3];
+  w.nu[i] = out[0];
+  w.nu[w.n_bus + i] = out[1];
+  for (size_t j = 0; j < n; ++j) bus_item_update(w, codes[j], &v[14 * j], out, r2, s2);
+}
+
 // Full solve emulation: setup tables, QP build, init, `sweeps` sweeps, step.
 // The workspace is a host buffer of acopf_workspace_bytes-equivalent size.
 size_t emu_workspace_bytes(int nb, int nl, int ng) { return layout_workspace(nullptr, nb, nl, ng, 1, nullptr); }
@@ -113,7 +139,12 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
     infeasible = 0;
     for (int l = 0; l < nl; ++l) infeasible += update_line(*g, w, l) != 0;
     double r2 = 0.0, s2 = 0.0;
-    for (int i = 0; i < nb; ++i) update_bus(*g, w, i, r2, s2);
+    for (int i = 0; i < nb; ++i) {
+      if (g_bus_items)
+        bus_by_items(*g, w, i, r2, s2);
+      else
+        update_bus(*g, w, i, r2, s2);
+    }
     rs_out[2 * k] = r2;
     rs_out[2 * k + 1] = s2;
   }
