@@ -11,6 +11,9 @@
 //     when it satisfies every constraint and its multipliers are
 //     non-negative (the KKT conditions, which certify the minimiser of a
 //     strictly convex QP).  Between sweeps the working set rarely changes.
+//     Otherwise a primal-dual guess (that set without its constraints of
+//     negative multiplier, plus the constraints its minimiser violates) is
+//     checked the same way; it settles most working-set changes.
 //  2. otherwise the dual active-set method of Goldfarb and Idnani (Math.
 //     Programming 27, 1983) runs: add the most violated constraint, take the
 //     primal/dual step that keeps the active multipliers non-negative
@@ -271,6 +274,39 @@ ACOPF_HD bool warm_check(const double P[4][4], const double zu[4], const double 
   return ok;
 }
 
+// Primal-dual guess of the optimal working set from a working set `mask`,
+// its minimiser z and its multipliers y (by variable, then row, as
+// warm_check returns them): the active constraints with a negative
+// multiplier are dropped (a fixed variable keeps its bound) and the
+// constraints z violates are added (a violated bound replaces the opposite
+// bound of its variable).
+ACOPF_HD int pd_guess(int mask, const double z[4], const double y[6], const double lo[4], const double hi[4],
+                      const double G[2][4], const double h[2], const double gn[2]) {
+  int m = mask;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool drop = y[v] < 0.0 && !(lo[v] >= hi[v]);
+    m = drop ? (m & ~((1 << v) | (1 << (v + 4)))) : m;
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) m = (y[4 + r] < 0.0) ? (m & ~(1 << (8 + r))) : m;
+  const double zs = fabs(z[0]) + fabs(z[1]) + fabs(z[2]) + fabs(z[3]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool below = z[v] - lo[v] < -1e-12 * (1.0 + fabs(lo[v]) + zs);
+    const bool above = hi[v] - z[v] < -1e-12 * (1.0 + fabs(hi[v]) + zs);
+    m = below ? ((m | (1 << v)) & ~(1 << (v + 4))) : m;
+    m = above ? ((m | (1 << (v + 4))) & ~(1 << v)) : m;
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const double gz = G[r][0] * z[0] + G[r][1] * z[1] + G[r][2] * z[2] + G[r][3] * z[3];
+    const bool viol = gn[r] > 0.0 && h[r] - gz < -1e-12 * (1.0 + fabs(h[r]) + gn[r] * zs);
+    m = viol ? (m | (1 << (8 + r))) : m;
+  }
+  return m;
+}
+
 ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], const double lo[4],
                                     const double hi[4], const double G[2][4], const double h[2],
                                     int warm_mask) {
@@ -299,6 +335,8 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
   bool done = false;
 
   // 1. warm start from the previous working set
+  double zg[4] = {zu[0], zu[1], zu[2], zu[3]}, yg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  bool try_guess = false;
   if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
     double zw[4], muw[2], yw[6];
     bool dual_ok = false;
@@ -311,6 +349,11 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
       res.mask = warm_mask;
       return res;
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zg[i] = zw[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) yg[i] = yw[i];
+    try_guess = true;
     if (dual_ok) {
       // The working set's minimiser with non-negative multipliers is a valid
       // state of the dual active-set method: continue from it (it then only
@@ -337,6 +380,25 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
       mask = warm_mask;
 #pragma unroll
       for (int i = 0; i < 4; ++i) z[i] = zw[i];
+    }
+  } else if (warm_mask == 0) {
+    try_guess = gi_most_violated(zu, 0, lo, hi, G, h, gn, ign) >= 0;  // the unconstrained minimiser is infeasible
+  }
+  // 1b. primal-dual guess, checked like the warm start
+  if (try_guess) {
+    const int m1 = pd_guess(warm_mask, zg, yg, lo, hi, G, h, gn);
+    if (m1 != warm_mask && __builtin_popcount(m1) <= 4) {
+      double z1[4], mu1[2], y1[6];
+      bool d1 = false;
+      if (warm_check(P, zu, lo, hi, G, h, gn, ign, m1, cs, z1, mu1, y1, d1)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(z1[i], lo[i]), hi[i]);
+        res.mu[0] = mu1[0];
+        res.mu[1] = mu1[1];
+        res.status = 0;
+        res.mask = m1;
+        return res;
+      }
     }
   }
 
