@@ -34,7 +34,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("59a4b131816d3417", 4306094), "rgg70000": ("59a4b131816d3417", 124545914)}
+MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("7aa9fbfe5f2f8787", 4436488), "rgg70000": ("7aa9fbfe5f2f8787", 130246908)}
 
 
 def sweep_sources_sha() -> str:
