@@ -363,10 +363,18 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   h[1] = d[(LF_H + 1) * L + l];
   const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h, w.line_mask[l]);
   w.line_mask[l] = res.mask;
+  // The flow map is read again (from cache) for the flows rather than kept
+  // in registers across the solver, which spilled it; an opaque copy of the
+  // index keeps the compiler from reusing the first load.
+  int lf = l;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(lf));
+#endif
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const double fl = F[r][0] * res.z[0] + F[r][1] * res.z[1] + F[r][2] * res.z[2] +
-                      F[r][3] * res.z[3] + d[(LF_F0 + r) * L + l];
+    const double fl = d[(LF_F + 4 * r) * L + lf] * res.z[0] + d[(LF_F + 4 * r + 1) * L + lf] * res.z[1] +
+                      d[(LF_F + 4 * r + 2) * L + lf] * res.z[2] + d[(LF_F + 4 * r + 3) * L + lf] * res.z[3] +
+                      d[(LF_F0 + r) * L + l];
     w.xl[lc8(l, r)] = fl;
     w.xl[lc8(l, 4 + r)] = res.z[r];
   }
