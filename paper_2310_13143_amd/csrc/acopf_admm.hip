@@ -280,11 +280,11 @@ k_line_phase(acopf_grid g, Workspace w, int single) {
 // costs one round of independent loads on d threads instead of a
 // dependent walk over its CSR on one.  Blocks past a scenario's last item
 // block exit at once; with `fold` the last block ends the sweep.
-template <bool kTrace>
-__global__ void __launch_bounds__(kItemBlock) k_bus_items(acopf_grid g, Workspace w, int single, int fold,
-                                                          int max_sweeps, double eps_pri, double eps_dual) {
-  __shared__ double terms[8][kItemBlock];
-  __shared__ double bres[6][kItemBlock];
+template <bool kTrace, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w, int single, int fold,
+                                                      int max_sweeps, double eps_pri, double eps_dual) {
+  __shared__ double terms[8][kBlock];
+  __shared__ double bres[6][kBlock];
   __shared__ double lds[16];
   __shared__ int s_last;
   if (single) {
@@ -295,9 +295,10 @@ __global__ void __launch_bounds__(kItemBlock) k_bus_items(acopf_grid g, Workspac
     if (s < 0 || w.scen[s].done) return;
   }
   const int t = threadIdx.x;
-  const size_t slot = (size_t)blockIdx.x * kItemBlock + t;
+  const size_t slot = (size_t)blockIdx.x * kBlock + t;
   const int code = w.item_code[slot], bus = w.item_bus[slot], head = w.item_head[slot], len = w.item_len[slot];
-  const bool lead = bus >= 0 && t == head;
+  const bool whole = code == kItemBus;  // a bus wider than a block: its thread walks all its items
+  const bool lead = bus >= 0 && t == head && !whole;
   double bc[7];
   if (lead) bus_item_consts(g, w, bus, bc);
   double v[14], a[8];
@@ -321,7 +322,9 @@ __global__ void __launch_bounds__(kItemBlock) k_bus_items(acopf_grid g, Workspac
   }
   __syncthreads();
   double rr = 0.0, ss = 0.0;
-  if (bus >= 0) {
+  if (whole) {
+    bus_whole_update<kTrace>(g, w, bus, rr, ss);
+  } else if (bus >= 0) {
     double res[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) res[m] = bres[m][head];
@@ -820,30 +823,35 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
   for (int q = 0; q < ng; ++q) gens[gfill[gb[q]]++] = q;
   // coupling items of the bus phase: per scenario, bus by bus, its
   // generators then its line ends (CSR order) in consecutive slots of one
-  // block; a bus that does not fit the current block starts the next one
+  // block; a bus that does not fit the current block starts the next one,
+  // and a bus with more items than a block takes one whole-bus slot
+  const int32_t ib = item_block_for(nl);
   const int32_t nib = item_blocks_bound(nl, ng, ns);
-  std::vector<int32_t> icode((size_t)nib * kItemBlock, kItemPad), ibus((size_t)nib * kItemBlock, -1),
-      ihead((size_t)nib * kItemBlock), ilen((size_t)nib * kItemBlock, 0), iblk(ns + 1);
-  for (size_t q = 0; q < ihead.size(); ++q) ihead[q] = (int32_t)(q % kItemBlock);
+  std::vector<int32_t> icode((size_t)nib * ib, kItemPad), ibus((size_t)nib * ib, -1), ihead((size_t)nib * ib),
+      ilen((size_t)nib * ib, 0), iblk(ns + 1);
+  for (size_t q = 0; q < ihead.size(); ++q) ihead[q] = (int32_t)(q % ib);
   int32_t blk = 0;
   for (int k = 0; k < ns; ++k) {
     iblk[k] = blk;
     int fill = 0;
     bool open = false;
     for (int i = bus_off_h[k]; i < bus_off_h[k + 1]; ++i) {
-      const int n = gdeg[i] + deg[i];
-      if (n > kItemBlock)
-        return fail(ACOPF_ERR_UNSUPPORTED, "acopf_setup: bus " + std::to_string(i) + " has " + std::to_string(n) +
-                                               " line ends and generators (at most " + std::to_string(kItemBlock) + ")");
-      if (!open || fill + n > kItemBlock) {
+      const int items = gdeg[i] + deg[i];
+      const bool whole = items > ib;
+      const int n = whole ? 1 : items;
+      if (!open || fill + n > ib) {
         if (open) ++blk;
         open = true;
         fill = 0;
       }
-      const size_t base = (size_t)blk * kItemBlock;
+      const size_t base = (size_t)blk * ib;
       int j = fill;
-      for (int q = gptr[i]; q < gptr[i + 1]; ++q) icode[base + j++] = -(gens[q] + 1);
-      for (int e = eptr[i]; e < eptr[i + 1]; ++e) icode[base + j++] = ends[e];
+      if (whole) {
+        icode[base + j++] = kItemBus;
+      } else {
+        for (int q = gptr[i]; q < gptr[i + 1]; ++q) icode[base + j++] = -(gens[q] + 1);
+        for (int e = eptr[i]; e < eptr[i + 1]; ++e) icode[base + j++] = ends[e];
+      }
       for (int m = fill; m < fill + n; ++m) {
         ibus[base + m] = i;
         ihead[base + m] = fill;
@@ -856,7 +864,7 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
   iblk[ns] = blk;
   if (blk > nib) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_setup: item blocks exceed their bound");
   Workspace w = ws_of(g, workspace);
-  const size_t used = (size_t)blk * kItemBlock * sizeof(int32_t);
+  const size_t used = (size_t)blk * ib * sizeof(int32_t);
   HIP_TRY(hipMemcpy(w.item_code, icode.data(), used, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.item_bus, ibus.data(), used, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w.item_head, ihead.data(), used, hipMemcpyHostToDevice));
@@ -950,12 +958,20 @@ struct SweepLaunch {
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single);
-    if (a.trace)
-      hipLaunchKernelGGL(k_bus_items<true>, dim3((unsigned)a.nbb), dim3(kItemBlock), 0, s, a.g, a.w, a.single,
-                         a.fold, a.max_sweeps, a.eps_pri, a.eps_dual);
+    const bool small = item_block_for(a.g.n_line) == 64;
+    const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
+    if (a.trace && small)
+      hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
+                         a.eps_pri, a.eps_dual);
+    else if (a.trace)
+      hipLaunchKernelGGL((k_bus_items<true, 256>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
+                         a.eps_pri, a.eps_dual);
+    else if (small)
+      hipLaunchKernelGGL((k_bus_items<false, 64>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
+                         a.eps_pri, a.eps_dual);
     else
-      hipLaunchKernelGGL(k_bus_items<false>, dim3((unsigned)a.nbb), dim3(kItemBlock), 0, s, a.g, a.w, a.single,
-                         a.fold, a.max_sweeps, a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL((k_bus_items<false, 256>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
+                         a.eps_pri, a.eps_dual);
     if (!a.fold)
       hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(256), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
   }

@@ -624,7 +624,7 @@ ACOPF_HD void bus_item_terms(const Workspace& w, int code, double v[14], double 
     a[5] = v[2] * v[6] + v[10];
     a[6] = v[3];
     a[7] = v[3] * v[7] + v[11];
-  } else if (code != kItemPad) {
+  } else if (code != kItemPad && code != kItemBus) {
     const int G = w.n_gen, k = -code - 1;
     update_gen(w, k);
     v[0] = w.rho_g[k];
@@ -717,7 +717,7 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
         w.tr_s_l[(kw + m) * L + l] += fabs(ds);
       }
     }
-  } else if (code != kItemPad) {
+  } else if (code != kItemPad && code != kItemBus) {
     const int G = w.n_gen, k = -code - 1;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -735,6 +735,39 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
         w.tr_s_g[idx] += fabs(ds);
       }
     }
+  }
+}
+
+// A whole bus by the item functions, one item at a time (a bus with more
+// items than an item block): the same sums, closed form and updates in the
+// same order as update_bus, with the register footprint of one item.  Each
+// item's values are loaded again for its update; nothing has changed them
+// in between (a generator's own update is recomputed with the same result).
+template <bool kTrace = false>
+ACOPF_HD void bus_whole_update(const acopf_grid& g, const Workspace& w, int i, double& rr, double& ss) {
+  const int g0 = w.bus_gen_ptr[i], g1 = w.bus_gen_ptr[i + 1];
+  const int e0 = w.bus_end_ptr[i], e1 = w.bus_end_ptr[i + 1];
+  const int n = (g1 - g0) + (e1 - e0);
+  double sum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < n; ++j) {
+    const int code = (j < g1 - g0) ? -(w.bus_gen[g0 + j] + 1) : w.bus_end[e0 + j - (g1 - g0)];
+    double v[14], a[8];
+    bus_item_terms(w, code, v, a);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) sum[m] += a[m];
+  }
+  double bc[7], out[6];
+  bus_item_consts(g, w, i, bc);
+  bus_item_solve(sum, bc, out);
+  w.dw[i] = out[2];
+  w.dth[i] = out[3];
+  w.nu[i] = out[0];
+  w.nu[w.n_bus + i] = out[1];
+  for (int j = 0; j < n; ++j) {
+    const int code = (j < g1 - g0) ? -(w.bus_gen[g0 + j] + 1) : w.bus_end[e0 + j - (g1 - g0)];
+    double v[14], a[8];
+    bus_item_terms(w, code, v, a);
+    bus_item_update<kTrace>(w, code, v, out, rr, ss);
   }
 }
 

@@ -97,8 +97,8 @@ struct Workspace {
   int32_t* line_blk_off;   // [n_scen + 1] first block of each scenario in the line phase
   int32_t* bus_blk_off;    // [n_scen + 1] same for the bus phase
   // bus phase by coupling items (launch modes): the generators, then the
-  // line ends of each bus in consecutive slots of one kItemBlock-slot block
-  int32_t* item_code;      // [slots] 2 l + side for a line end, -(k + 1) for generator k, kItemPad
+  // line ends of each bus in consecutive slots of one block (item_block_for)
+  int32_t* item_code;      // [slots] 2 l + side for a line end, -(k + 1) for generator k, kItemBus, kItemPad
   int32_t* item_bus;       // [slots] bus of the item (-1 for padding)
   int32_t* item_head;      // [slots] slot (within the block) of the bus's first item
   int32_t* item_len;       // [slots] number of items of the bus
@@ -137,16 +137,22 @@ struct Workspace {
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Item blocks of the bus phase: kItemBlock slots, one thread each.  A bus's
-// items never straddle two blocks, so two consecutive blocks of a scenario
-// hold more than kItemBlock items together; this bounds the block count by
-// the sizes alone (blocks past a scenario's last one exit at once).
-constexpr int32_t kItemBlock = 256;
+// Item blocks of the bus phase, one thread per slot.  A bus's items never
+// straddle two blocks, so two consecutive blocks of a scenario hold more
+// slots than one block together; this bounds the block count by the sizes
+// alone (blocks past a scenario's last one exit at once).  A bus with more
+// items than a block takes one slot (kItemBus) whose thread runs the whole
+// per-bus update.  Small grids use 64-slot blocks (one wave: more blocks in
+// flight for a latency-bound sweep), larger ones 256-slot blocks.
 constexpr int32_t kItemPad = -0x7fffffff;
+constexpr int32_t kItemBus = -0x7ffffffe;
+constexpr int32_t kItemSmallLines = 16384;
+
+inline int32_t item_block_for(int32_t nl) { return nl < kItemSmallLines ? 64 : 256; }
 
 inline int32_t item_blocks_bound(int32_t nl, int32_t ng, int32_t ns) {
-  const int64_t items = 2 * (int64_t)nl + ng;
-  return (int32_t)(2 * ((items + kItemBlock - 1) / kItemBlock) + 2 * (int64_t)ns + 1);
+  const int64_t items = 2 * (int64_t)nl + ng, b = item_block_for(nl);
+  return (int32_t)(2 * ((items + b - 1) / b) + 2 * (int64_t)ns + 1);
 }
 
 inline int32_t max_partials_for(int32_t nb, int32_t nl, int32_t ng, int32_t ns) {
@@ -183,7 +189,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.scen_gen_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.line_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.bus_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
-  const size_t slots = (size_t)item_blocks_bound(nl, ng, ns) * kItemBlock;
+  const size_t slots = (size_t)item_blocks_bound(nl, ng, ns) * item_block_for(nl);
   t.item_code = (int32_t*)take(slots * I);
   t.item_bus = (int32_t*)take(slots * I);
   t.item_head = (int32_t*)take(slots * I);

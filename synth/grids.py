@@ -134,6 +134,18 @@ def _ring_topology(n_bus, n_line, rng):
     return np.array([e[0] for e in el]), np.array([e[1] for e in el]), None
 
 
+def _star_topology(n_bus, n_line, rng):
+    """Bus 0 joined to every other bus, plus random chords between the others
+    (a bus of very high degree)."""
+    spokes = [(0, i) for i in range(1, n_bus)]
+    edges = set(spokes)
+    while len(edges) < n_line:
+        a, b = rng.choice(np.arange(1, n_bus), size=2, replace=False)
+        edges.add((int(min(a, b)), int(max(a, b))))
+    el = spokes + sorted(edges - set(spokes))
+    return np.array([e[0] for e in el]), np.array([e[1] for e in el]), None
+
+
 def _rgg_topology(n_bus, n_line, n_clusters, sigma, knn, rng):
     from scipy.spatial import Delaunay, cKDTree
     from scipy.sparse import coo_matrix
@@ -237,6 +249,8 @@ def make_grid(n_bus: int, n_line: int, n_gen: int, seed: int, topology: str = "r
     rng = np.random.default_rng(seed)
     if topology == "ring":
         f, t, xy = _ring_topology(n_bus, n_line, rng)
+    elif topology == "star":
+        f, t, xy = _star_topology(n_bus, n_line, rng)
     elif topology == "rgg":
         nc = n_clusters if n_clusters is not None else max(1, n_bus // 100)
         f, t, xy = _rgg_topology(n_bus, n_line, nc, sigma, knn, rng)

@@ -51,7 +51,8 @@ void emu_psd_project(int n, double* m) {
 
 // Bus phase used by emu_run: 0 = update_bus per bus, 1 = the per-item
 // decomposition of the launch-mode kernel (items of a bus: generators, then
-// line ends in CSR order), summed in item order.
+// line ends in CSR order), summed in item order; 2 = the kernel's one-thread
+// walk over a bus wider than an item block.
 static int g_bus_items = 0;
 void emu_set_bus_items(int on) { g_bus_items = on; }
 
@@ -140,7 +141,9 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
     for (int l = 0; l < nl; ++l) infeasible += update_line(*g, w, l) != 0;
     double r2 = 0.0, s2 = 0.0;
     for (int i = 0; i < nb; ++i) {
-      if (g_bus_items)
+      if (g_bus_items == 2)
+        bus_whole_update(*g, w, i, r2, s2);
+      else if (g_bus_items)
         bus_by_items(*g, w, i, r2, s2);
       else
         update_bus(*g, w, i, r2, s2);

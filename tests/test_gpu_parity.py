@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from synth.grids import grid_14, grid_2000, grid_70000, tiny_grid
+from synth.grids import grid_14, grid_2000, grid_70000, make_grid, tiny_grid
 from oracle import acopf, admm, direct, qp as qpm, sqp
 from tests._util import rel_err, start_point
 
@@ -62,6 +62,8 @@ def _compare_state(st, ref, tol=TOL):
 CASES = {
     "ring14": lambda: grid_14(),
     "tiny_shunt": lambda: tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04),
+    # a bus of degree 89, wider than a 64-slot item block: one whole-bus slot
+    "star90": lambda: make_grid(90, 100, 6, seed=90, topology="star", name="star90"),
 }
 
 
@@ -167,8 +169,10 @@ def test_relaxed_lines_match_oracle():
 
 
 def test_rgg70000_sampled_line_and_bus_updates():
-    """At 70,000 buses (88,000 lines, the bench workload) the oracle checks one
-    sweep of sampled lines and all buses from the GPU's own previous state."""
+    """At 70,000 buses (88,000 lines, the bench workload, in the bench's graph
+    sweep mode) the oracle checks one sweep of sampled lines and all buses
+    from the GPU's own previous state."""
+    from paper_2310_13143_amd import _abi
     print("[gpu] rgg70000 sampled", flush=True)
     g = grid_70000()
     x, pi = start_point(g, pi_scale=20.0, seed=2)
@@ -178,9 +182,9 @@ def test_rgg70000_sampled_line_and_bus_updates():
     xi = dg.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pi)
     dg.qp_build(xi, 0.05, 0)
     dg.admm_init(*dg.rho_scalar(2e4))
-    dg.admm_solve(7, 0.0, 0.0)
+    dg.admm_solve(7, 0.0, 0.0, sweep_mode=_abi.SWEEP_GRAPH)
     s0 = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
-    dg.admm_solve(1, 0.0, 0.0)   # continues from the state: one more sweep
+    dg.admm_solve(1, 0.0, 0.0, sweep_mode=_abi.SWEEP_GRAPH)   # continues from the state: one more sweep
     s1 = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
     G, L, B = g.n_gen, g.n_line, g.n_bus
     st = admm.cold_state(g)

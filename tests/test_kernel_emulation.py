@@ -170,8 +170,9 @@ def _setup(g, delta, pi_scale, seed):
 def test_bus_items_match_per_bus_update(emu, case):
     """The bus phase split by coupling item (launch-mode kernel: per-item
     terms, summed in item order by the bus's first item, then per-item
-    multiplier updates) gives the bits of the per-bus update over whole
-    sweeps; residual norms agree to rounding."""
+    multiplier updates), and its one-thread walk over a bus wider than an
+    item block, give the bits of the per-bus update over whole sweeps;
+    residual norms agree to rounding."""
     g = grid_14() if case == "ring14" else tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04)
     delta = 0.05
     x, pi = _setup(g, delta, 50.0, 3)
@@ -184,7 +185,7 @@ def test_bus_items_match_per_bus_update(emu, case):
     cx, _ = hg.iterate(x, pi)
     nsw = 60
     out = []
-    for items in (0, 1):
+    for items in (0, 1, 2):
         emu.emu_set_bus_items(items)
         ws = np.zeros(emu.emu_workspace_bytes(g.n_bus, g.n_line, g.n_gen) // 8 + 64)
         base = (ws.ctypes.data + 255) // 256 * 256
@@ -198,10 +199,11 @@ def test_bus_items_match_per_bus_update(emu, case):
                                                     ("lam_g", 2 * g.n_gen), ("dw", g.n_bus), ("dth", g.n_bus),
                                                     ("nu", 2 * g.n_bus))}, rs.copy(), ws))
     emu.emu_set_bus_items(0)
-    (a, ra, _), (b, rb, _) = out
-    for k in a:
-        assert np.array_equal(a[k], b[k]), k
-    np.testing.assert_allclose(rb, ra, rtol=1e-12, atol=1e-300)
+    a, ra, _ = out[0]
+    for b, rb, _ in out[1:]:
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+        np.testing.assert_allclose(rb, ra, rtol=1e-12, atol=1e-300)
 
 
 @pytest.mark.parametrize("case", ["ring14", "tiny_shunt"])
