@@ -37,8 +37,6 @@ namespace {
 
 constexpr int kDefaultBlock = 256;
 constexpr long long kSpinLimit = 1LL << 25;
-// Largest single-scenario bus-phase grid whose last block also ends the sweep.
-constexpr int kFoldMaxBlocks = 64;
 // Sweeps enqueued between two looks at the stop flag (launch mode).
 constexpr int kSweepChunk = 64;
 // Learned warm start: multiplier scale and penalty-factor clip of the
@@ -199,7 +197,6 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
     SyncState* sy = w.sync;
     int failed = 0;
     for (int s = 0; s < w.n_scen; ++s) failed += w.scen[s].status != 0 ? 1 : 0;
-    sy->count = 0;
     sy->go = 0u;
     sy->done = failed == w.n_scen ? 1 : 0;
     sy->n_done = failed;
@@ -247,6 +244,52 @@ __device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int m
   }
 }
 
+// Launch modes end a sweep without a kernel of their own: the next line
+// phase evaluates the stop test of the sweep before it, every block from
+// the same partials, and one kernel per chunk of sweeps (k_finish_phase)
+// records the norms of the chunk's last sweep.  The bus phase counts the
+// sweeps, so the count a line block reads is never written during its
+// kernel.
+//
+// Residual sums of a scenario's last sweep from its bus-phase partials
+// [p0, p1): the first wave adds them lane-strided, then by a butterfly of
+// shuffles (every lane ends with the same bits), so each kernel that
+// evaluates the stop test gets the same value.  Valid in the first wave.
+__device__ void sweep_sums(const Workspace& w, int p0, int p1, double& r2, double& s2) {
+  double a = 0.0, b = 0.0;
+  if (threadIdx.x < 64) {
+#pragma unroll 4
+    for (int k = p0 + (int)threadIdx.x; k < p1; k += 64) {
+      a += w.partials[k];
+      b += w.partials[w.max_partials + k];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  r2 = a;
+  s2 = b;
+}
+
+__device__ __forceinline__ bool stop_met(double r2, double s2, double eps_pri, double eps_dual) {
+  return (eps_pri > 0.0 || eps_dual > 0.0) && sqrt(r2) <= eps_pri && sqrt(s2) <= eps_dual;
+}
+
+// Norms and stop state of scenario s after its last sweep (one thread).
+__device__ void record_sweep(const Workspace& w, int s, double r2, double s2, bool stop, double eps_pri,
+                             double eps_dual) {
+  ScenState* sc = &w.scen[s];
+  sc->r_norm = sqrt(r2);
+  sc->s_norm = sqrt(s2);
+  sc->converged = stop_met(r2, s2, eps_pri, eps_dual) ? 1 : 0;
+  if (stop) {
+    sc->done = 1;
+    if (atomicAdd(&w.sync->n_done, 1) + 1 == w.n_scen) w.sync->done = 1;
+  }
+}
+
 __device__ __forceinline__ bool batch_done(const Workspace& w) {
   return __hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
@@ -255,20 +298,33 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // block needs no table lookup (one flag read before the line work).  At
 // most 256 registers per lane: two waves per SIMD (measured faster than one
 // wave with 270 registers, despite a few spilled values).
+// `test`: first evaluate the stop test of the previous sweep (launch modes).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_line_phase(acopf_grid g, Workspace w, int single) {
-  int s = 0, l;
+k_line_phase(acopf_grid g, Workspace w, int single, int test, double eps_pri, double eps_dual) {
+  __shared__ int s_stop;
+  int s = 0;
   if (single) {
     if (w.scen[0].done) return;
-    l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= w.n_line) return;
   } else {
     if (batch_done(w)) return;
     s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
     if (s < 0 || w.scen[s].done) return;
-    l = w.scen_line_off[s] + (blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x;
-    if (l >= w.scen_line_off[s + 1]) return;
   }
+  if (test) {
+    double r2, s2;
+    sweep_sums(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+    if (threadIdx.x == 0) {
+      const bool stop = stop_met(r2, s2, eps_pri, eps_dual);
+      // the scenario's first block records the stop; every block obeys it
+      if (stop && (int)blockIdx.x == (single ? 0 : w.line_blk_off[s])) record_sweep(w, s, r2, s2, true, eps_pri, eps_dual);
+      s_stop = stop ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_stop) return;
+  }
+  const int l = single ? (int)(blockIdx.x * blockDim.x + threadIdx.x)
+                       : w.scen_line_off[s] + (int)((blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x);
+  if (l >= (single ? w.n_line : w.scen_line_off[s + 1])) return;
   if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
@@ -279,19 +335,18 @@ k_line_phase(acopf_grid g, Workspace w, int single) {
 // closed form; then every thread updates its couplings.  A bus of degree d
 // costs one round of independent loads on d threads instead of a
 // dependent walk over its CSR on one.  Blocks past a scenario's last item
-// block exit at once; with `fold` the last block ends the sweep.
+// block exit at once.  The scenario's first block counts the sweep.
 template <bool kTrace, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w, int single, int fold,
-                                                      int max_sweeps, double eps_pri, double eps_dual) {
+__global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w, int single) {
   __shared__ double terms[8][kBlock];
   __shared__ double bres[6][kBlock];
   __shared__ double lds[16];
-  __shared__ int s_last;
+  int s = 0;
   if (single) {
     if (w.scen[0].done || (int)blockIdx.x >= w.item_blk_off[1]) return;
   } else {
     if (batch_done(w)) return;
-    const int s = scen_of_block(w.item_blk_off, w.n_scen, blockIdx.x);
+    s = scen_of_block(w.item_blk_off, w.n_scen, blockIdx.x);
     if (s < 0 || w.scen[s].done) return;
   }
   const int t = threadIdx.x;
@@ -335,28 +390,27 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   if (t == 0) {
     w.partials[blockIdx.x] = rr;
     w.partials[w.max_partials + blockIdx.x] = ss;
-  }
-  if (!fold) return;
-  __syncthreads();
-  if (t == 0) {
-    __threadfence();
-    const unsigned int ticket = atomicAdd(&w.sync->count, 1u);
-    s_last = (ticket == (unsigned int)w.item_blk_off[1] - 1u) ? 1 : 0;  // fold runs with one scenario
-    if (s_last) __threadfence();
-  }
-  __syncthreads();
-  if (s_last) {
-    finish_scenario(w, 0, 0, w.item_blk_off[1], max_sweeps, eps_pri, eps_dual, lds);
-    if (t == 0) w.sync->count = 0;
+    if ((int)blockIdx.x == w.item_blk_off[s]) {
+      ScenState* sc = &w.scen[s];
+      const int k = sc->sweeps + 1;
+      sc->sweeps = k;
+      sc->infeasible[k & 1] = 0;  // counter of the next sweep
+    }
   }
 }
 
-// One block per scenario.
+// End of a chunk of launch-mode sweeps: records the norms of each running
+// scenario's last sweep and applies its stop test and the sweep cap.  One
+// 64-thread block per scenario.
 __global__ void k_finish_phase(Workspace w, int max_sweeps, double eps_pri, double eps_dual) {
-  __shared__ double lds[16];
   const int s = blockIdx.x;
   if (w.sync->done || w.scen[s].done) return;
-  finish_scenario(w, s, w.bus_blk_off[s], w.bus_blk_off[s + 1], max_sweeps, eps_pri, eps_dual, lds);
+  double r2, s2;
+  sweep_sums(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+  if (threadIdx.x == 0) {
+    const bool stop = stop_met(r2, s2, eps_pri, eps_dual) || w.scen[s].sweeps >= max_sweeps;
+    record_sweep(w, s, r2, s2, stop, eps_pri, eps_dual);
+  }
 }
 
 // Grid barrier for a cooperative launch (all blocks resident).  Each block
@@ -951,30 +1005,29 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
 struct SweepLaunch {
   acopf_grid g;
   Workspace w;
-  int nbl, nbb, bs, single, fold, ns, trace, max_sweeps;
+  int nbl, nbb, bs, single, ns, trace, max_sweeps;
   double eps_pri, eps_dual;
 };
 
+// n sweeps: each line phase but the first tests the sweep before it; the
+// chunk ends with k_finish_phase.
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
+  const bool small = item_block_for(a.g.n_line) == 64;
+  const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
+  const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single);
-    const bool small = item_block_for(a.g.n_line) == 64;
-    const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
+    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
+                       (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
     if (a.trace && small)
-      hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
-                         a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single);
     else if (a.trace)
-      hipLaunchKernelGGL((k_bus_items<true, 256>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
-                         a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL((k_bus_items<true, 256>), grid, block, 0, s, a.g, a.w, a.single);
     else if (small)
-      hipLaunchKernelGGL((k_bus_items<false, 64>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
-                         a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL((k_bus_items<false, 64>), grid, block, 0, s, a.g, a.w, a.single);
     else
-      hipLaunchKernelGGL((k_bus_items<false, 256>), grid, block, 0, s, a.g, a.w, a.single, a.fold, a.max_sweeps,
-                         a.eps_pri, a.eps_dual);
-    if (!a.fold)
-      hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(256), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
+      hipLaunchKernelGGL((k_bus_items<false, 256>), grid, block, 0, s, a.g, a.w, a.single);
   }
+  hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(64), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
 }
 
 // Instantiated graphs of n launch-per-phase sweeps, cached per process and
@@ -1008,7 +1061,7 @@ std::string graph_key(const SweepLaunch& a, int n, int dev) {
                         g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
                         g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
   put(ptrs, sizeof ptrs);
-  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.fold, a.ns, a.trace, a.max_sweeps};
+  const int shape[7] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps};
   put(shape, sizeof shape);
   put(&a.eps_pri, sizeof a.eps_pri);
   put(&a.eps_dual, sizeof a.eps_dual);
@@ -1159,7 +1212,6 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.nbb = (int)nbb;
     a.bs = bs;
     a.single = single;
-    a.fold = (single && nbb <= kFoldMaxBlocks) ? 1 : 0;
     a.ns = ns;
     a.trace = p->trace;
     a.max_sweeps = p->max_sweeps;

@@ -42,7 +42,6 @@ enum BusFlag { BUS_REF = 1 };
 
 // Whole-batch synchronisation and error state.
 struct SyncState {
-  unsigned int count;      // bus-phase blocks finished (folded sweep end)
   unsigned int go;         // grid-barrier release epoch (persistent kernel)
   int done;                // every scenario has stopped
   int n_done;              // scenarios stopped so far
