@@ -34,7 +34,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("7aa9fbfe5f2f8787", 4436488), "rgg70000": ("7aa9fbfe5f2f8787", 130246908)}
+MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("1865a1bc85a2fad7", 4544356), "rgg70000": ("1865a1bc85a2fad7", 118157612)}
 
 
 def sweep_sources_sha() -> str:
@@ -302,6 +302,8 @@ def bench_warmstart(args):
     Xl, Tl, Xg, Tg = W.collect(dg, x, args.sqp_iters, **sq)
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
+    progress = lambda msg: print(f"[warmstart] {msg} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    progress(f"traced {args.train_scen} training scenarios")
     net = W.WarmStart("cuda:0", seed=7)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     log = max(1, args.train_steps // 10)
@@ -313,6 +315,7 @@ def bench_warmstart(args):
     torch.cuda.synchronize()
     ms_line = ev[0].elapsed_time(ev[1])
     ms_gen = ev[1].elapsed_time(ev[2])
+    progress("trained the line and generator networks")
 
     variants = (("plain", dict(net=None)),
                 ("learned_lam_first_rho", dict(net=net, lam_policy="first", use_rho=True)),
@@ -327,6 +330,7 @@ def bench_warmstart(args):
                 dg, x = device_batch(seeds)
                 r = W.run_sqp(dg, x, args.sqp_iters, **sq, **kw)
             runs[name] = r
+            progress(f"{len(seeds)} scenarios with the {name} start")
         return runs
 
     # the policy is chosen on validation scenarios, then measured on held-out ones
