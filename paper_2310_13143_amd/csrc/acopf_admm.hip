@@ -258,10 +258,21 @@ __device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int m
 __device__ void sweep_sums(const Workspace& w, int p0, int p1, double& r2, double& s2) {
   double a = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
-#pragma unroll 4
-    for (int k = p0 + (int)threadIdx.x; k < p1; k += 64) {
-      a += w.partials[k];
-      b += w.partials[w.max_partials + k];
+    // up to 16 partials per lane are loaded before any is added (one round
+    // of memory latency for up to 1,024 bus blocks), then added in order
+    for (int k0 = p0 + (int)threadIdx.x; k0 < p1; k0 += 16 * 64) {
+      double ra[16], rb[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k = k0 + 64 * j;
+        ra[j] = k < p1 ? w.partials[k] : 0.0;
+        rb[j] = k < p1 ? w.partials[w.max_partials + k] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        a += ra[j];
+        b += rb[j];
+      }
     }
   }
 #pragma unroll
