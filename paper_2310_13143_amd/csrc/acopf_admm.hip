@@ -308,7 +308,7 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // `single`: one scenario, launched with exactly ceil(n / block) blocks, so a
 // block needs no table lookup (one flag read before the line work).  At
 // most 256 registers per lane: two waves per SIMD (measured faster than one
-// wave with 270 registers, despite a few spilled values).
+// wave with more registers; a cap of three waves spills hundreds of bytes).
 // `test`: first evaluate the stop test of the previous sweep (launch modes).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_line_phase(acopf_grid g, Workspace w, int single, int test, double eps_pri, double eps_dual) {
