@@ -37,6 +37,8 @@ namespace {
 
 constexpr int kDefaultBlock = 256;
 constexpr long long kSpinLimit = 1LL << 25;
+// Most lines per wave that the line phase's neighbour search serves.
+constexpr int kSearchLines = 2;
 // Sweeps enqueued between two looks at the stop flag (launch mode).
 constexpr int kSweepChunk = 64;
 // Learned warm start: multiplier scale and penalty-factor clip of the
@@ -311,7 +313,7 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // wave with more registers; a cap of three waves spills hundreds of bytes).
 // `test`: first evaluate the stop test of the previous sweep (launch modes).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_line_phase(acopf_grid g, Workspace w, int single, int test, double eps_pri, double eps_dual) {
+k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
   int s = 0;
   if (single) {
@@ -336,7 +338,43 @@ k_line_phase(acopf_grid g, Workspace w, int single, int test, double eps_pri, do
   const int l = single ? (int)(blockIdx.x * blockDim.x + threadIdx.x)
                        : w.scen_line_off[s] + (int)((blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x);
   if (l >= (single ? w.n_line : w.scen_line_off[s + 1])) return;
-  if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
+  if (!search) {  // one full solve per thread (the solver's own warm start and guess)
+    if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
+    return;
+  }
+  // 1. the warm working set or the primal-dual guess settles most lines
+  int base = 0;
+  bool left = !update_line_fast(w, l, base);
+  // 2. for each line they leave, the wave's threads check the neighbours of
+  // its last working set at once (one per thread; the line's data are
+  // loaded by every thread from the same addresses); the first thread
+  // whose set passes the KKT check stores the result.  The searches run one
+  // line after another while the dual method runs the wave's lines
+  // together, so only a wave with at most kSearchLines such lines searches.
+  // Used for small, latency-bound grids (`search`): there it shortens the
+  // wave's tail; on large grids and batches it measured slower.
+  const int lane = (int)__lane_id();
+  unsigned long long todo = __ballot(left);
+  if (__popcll(todo) > kSearchLines) todo = 0ull;
+  while (todo != 0ull) {
+    const int f = __ffsll((long long)todo) - 1;
+    todo &= todo - 1ull;
+    const int lf = __shfl(l, f), bf = __shfl(base, f);
+    LineQPResult r;
+    const bool ok = line_neighbour_check(w, lf, bf, lane, r);
+    const unsigned long long hit = __ballot(ok);
+    if (hit != 0ull) {
+      if (lane == __ffsll((long long)hit) - 1) line_sweep_store(w, lf, r);
+      if (lane == f) left = false;
+    }
+  }
+  // 3. the dual active-set method for the rest; an opaque copy of the index
+  // keeps the compiler from carrying step 1's values across steps 2 and 3
+  if (left) {
+    int lr = l;
+    asm volatile("" : "+v"(lr));
+    if (update_line(g, w, lr) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
+  }
 }
 
 // Bus phase by coupling items (launch modes): one thread per line end or
@@ -1028,7 +1066,7 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
-                       (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
+                       (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
     if (a.trace && small)
       hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single);
     else if (a.trace)

@@ -322,15 +322,13 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
   return ok;
 }
 
-// Line update of one ADMM sweep (eq. line_kernel): exact minimiser of the
-// line subproblem given the multipliers and the bus-side values of the
-// previous sweep.  Writes the line-side values of the 8 couplings and the
-// limit-row multipliers; returns the solver status (0 solved).
-ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
+// Data of line l's subproblem in this sweep (eq. line_kernel): the factor
+// P (packed), the linear term c from the multipliers and the bus-side
+// values of the previous sweep, the box and the limit rows.
+ACOPF_HD void line_sweep_data(const Workspace& w, int l, double Pp[10], double c[4], double lo[4], double hi[4],
+                              double G[2][4], double h[2]) {
   const int L = w.n_line;
   const double* d = w.line;
-  (void)g;
-  double Pp[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) Pp[k] = w.line_P[k * L + l];
   double F[4][4];
@@ -341,7 +339,6 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   // bus-side values of the voltage copies, stored in the line's record by
   // the last bus update (the end buses' d_w, d_th)
   const double xbv[4] = {w.xbar_v[lc4(l, 0)], w.xbar_v[lc4(l, 1)], w.xbar_v[lc4(l, 2)], w.xbar_v[lc4(l, 3)]};
-  double c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
     c[i] = w.line_cc[i * L + l] + w.lam_l[lc8(l, 4 + i)] - w.rho_l[lc8(l, 4 + i)] * xbv[i];
@@ -351,7 +348,6 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) c[i] += F[r][i] * a;
   }
-  double lo[4], hi[4], G[2][4], h[2];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     lo[k] = d[(LF_LO + k) * L + l];
@@ -361,11 +357,17 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   }
   h[0] = d[(LF_H + 0) * L + l];
   h[1] = d[(LF_H + 1) * L + l];
-  const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h, w.line_mask[l]);
+}
+
+// Line-side values of the 8 couplings (flows F z + f0, then z), the limit-
+// row multipliers and the working set of a solved line subproblem.  The
+// flow map is read again (from cache) rather than kept in registers across
+// the solver, which spilled it; an opaque copy of the index keeps the
+// compiler from reusing the first load.
+ACOPF_HD void line_sweep_store(const Workspace& w, int l, const LineQPResult& res) {
+  const int L = w.n_line;
+  const double* d = w.line;
   w.line_mask[l] = res.mask;
-  // The flow map is read again (from cache) for the flows rather than kept
-  // in registers across the solver, which spilled it; an opaque copy of the
-  // index keeps the compiler from reusing the first load.
   int lf = l;
 #if defined(__HIP_DEVICE_COMPILE__)
   asm volatile("" : "+v"(lf));
@@ -380,7 +382,43 @@ ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
   }
   w.mu[l] = res.mu[0];
   w.mu[L + l] = res.mu[1];
+}
+
+// Line update of one ADMM sweep (eq. line_kernel): exact minimiser of the
+// line subproblem given the multipliers and the bus-side values of the
+// previous sweep.  Writes the line-side values of the 8 couplings and the
+// limit-row multipliers; returns the solver status (0 solved).
+ACOPF_HD int update_line(const acopf_grid& g, const Workspace& w, int l) {
+  (void)g;
+  double Pp[10], c[4], lo[4], hi[4], G[2][4], h[2];
+  line_sweep_data(w, l, Pp, c, lo, hi, G, h);
+  const LineQPResult res = solve_line_qp(Pp, c, lo, hi, G, h, w.line_mask[l]);
+  line_sweep_store(w, l, res);
   return res.status;
+}
+
+// The line update when the previous working set or the primal-dual guess
+// settles it (the common case between sweeps): returns false, writing
+// nothing, with `base` the last working set checked, when a search or
+// update_line must run instead.
+ACOPF_HD bool update_line_fast(const Workspace& w, int l, int& base) {
+  double Pp[10], c[4], lo[4], hi[4], G[2][4], h[2];
+  line_sweep_data(w, l, Pp, c, lo, hi, G, h);
+  LineQPResult res;
+  if (!solve_line_qp_fast(Pp, c, lo, hi, G, h, w.line_mask[l], res, base)) return false;
+  line_sweep_store(w, l, res);
+  return true;
+}
+
+// Neighbour `idx` of working set `base` checked for line l (one thread of a
+// search over a line's neighbouring working sets): true, with the result
+// in res, if it is optimal.
+ACOPF_HD bool line_neighbour_check(const Workspace& w, int l, int base, int idx, LineQPResult& res) {
+  const int m = neighbour_mask(base, idx);
+  if (m < 0) return false;
+  double Pp[10], c[4], lo[4], hi[4], G[2][4], h[2];
+  line_sweep_data(w, l, Pp, c, lo, hi, G, h);
+  return check_working_set(Pp, c, lo, hi, G, h, m, res);
 }
 
 // Generator update (eq. gen_kernel, closed form clamp) of generator k.

@@ -307,6 +307,125 @@ ACOPF_HD int pd_guess(int mask, const double z[4], const double y[6], const doub
   return m;
 }
 
+// Quantities every check starts from (as at the start of solve_line_qp): P
+// unpacked, the rows' 1-norms, the unconstrained minimiser zu = -P c and the
+// scale of c.
+ACOPF_HD void line_qp_start(const double Pp[10], const double c[4], const double G[2][4], double P[4][4],
+                            double gn[2], double zu[4], double& cs) {
+  sym_unpack(Pp, P);
+  gn[0] = fabs(G[0][0]) + fabs(G[0][1]) + fabs(G[0][2]) + fabs(G[0][3]);
+  gn[1] = fabs(G[1][0]) + fabs(G[1][1]) + fabs(G[1][2]) + fabs(G[1][3]);
+  matvec4(P, c, zu);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zu[i] = -zu[i];
+  cs = 1.0 + fabs(c[0]) + fabs(c[1]) + fabs(c[2]) + fabs(c[3]);
+}
+
+// Steps 1 and 1b alone (no dual active-set method): true, with the result,
+// when the warm set or the primal-dual guess is optimal (or, with no warm
+// set, the unconstrained minimiser is feasible); otherwise false, with
+// `base` the last working set checked.  solve_line_qp repeats these checks
+// before its dual method (same result bits).
+ACOPF_HD bool solve_line_qp_fast(const double Pp[10], const double c[4], const double lo[4], const double hi[4],
+                                 const double G[2][4], const double h[2], int warm_mask, LineQPResult& res,
+                                 int& base) {
+  double P[4][4], gn[2], zu[4], cs;
+  line_qp_start(Pp, c, G, P, gn, zu, cs);
+  const double ign[2] = {gn[0] > 0.0 ? 1.0 / gn[0] : 0.0, gn[1] > 0.0 ? 1.0 / gn[1] : 0.0};
+  base = warm_mask;
+  double zg[4] = {zu[0], zu[1], zu[2], zu[3]}, yg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (warm_mask != 0 && __builtin_popcount(warm_mask) <= 4) {
+    double zw[4], muw[2];
+    bool dual_ok = false;
+    if (warm_check(P, zu, lo, hi, G, h, gn, ign, warm_mask, cs, zw, muw, yg, dual_ok)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(zw[i], lo[i]), hi[i]);
+      res.mu[0] = muw[0];
+      res.mu[1] = muw[1];
+      res.status = 0;
+      res.mask = warm_mask;
+      return true;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zg[i] = zw[i];
+  } else if (warm_mask == 0) {
+    if (gi_most_violated(zu, 0, lo, hi, G, h, gn, ign) < 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(zu[i], lo[i]), hi[i]);
+      res.mu[0] = 0.0;
+      res.mu[1] = 0.0;
+      res.status = 0;
+      res.mask = 0;
+      return true;
+    }
+  } else {
+    return false;
+  }
+  const int m1 = pd_guess(warm_mask, zg, yg, lo, hi, G, h, gn);
+  if (m1 == warm_mask || __builtin_popcount(m1) > 4) return false;
+  base = m1;
+  double z1[4], mu1[2], y1[6];
+  bool d1 = false;
+  if (!warm_check(P, zu, lo, hi, G, h, gn, ign, m1, cs, z1, mu1, y1, d1)) return false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(z1[i], lo[i]), hi[i]);
+  res.mu[0] = mu1[0];
+  res.mu[1] = mu1[1];
+  res.status = 0;
+  res.mask = m1;
+  return true;
+}
+
+// Neighbour `idx` of working set `base` for a search by many threads at
+// once: idx 0-9 toggle one constraint, idx 10-54 toggle a pair (a bound
+// that is added replaces the opposite bound of its variable); -1 when idx
+// is out of range or the set would hold more than four constraints.
+ACOPF_HD int neighbour_mask(int base, int idx) {
+  if (idx < 0 || idx >= 55) return -1;
+  int a = idx, b = -1;
+  if (idx >= 10) {
+    int p = idx - 10, i = 0;
+    while (p >= 9 - i) {
+      p -= 9 - i;
+      ++i;
+    }
+    a = i;
+    b = i + 1 + p;
+  }
+  int m = base;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int k = (t == 0) ? a : b;
+    if (k < 0) continue;
+    if ((m >> k) & 1) {
+      m &= ~(1 << k);
+    } else {
+      m |= 1 << k;
+      if (k < 8) m &= ~(1 << (k < 4 ? k + 4 : k - 4));
+    }
+  }
+  return __builtin_popcount(m) <= 4 ? m : -1;
+}
+
+// KKT check of working set `mask` for the subproblem (Pp, c, lo, hi, G, h):
+// true, with the result, if the set is optimal.
+ACOPF_HD bool check_working_set(const double Pp[10], const double c[4], const double lo[4], const double hi[4],
+                                const double G[2][4], const double h[2], int mask, LineQPResult& res) {
+  double P[4][4], gn[2], zu[4], cs;
+  line_qp_start(Pp, c, G, P, gn, zu, cs);
+  const double ign[2] = {gn[0] > 0.0 ? 1.0 / gn[0] : 0.0, gn[1] > 0.0 ? 1.0 / gn[1] : 0.0};
+  double z[4], mu[2], y[6];
+  bool d = false;
+  if (!warm_check(P, zu, lo, hi, G, h, gn, ign, mask, cs, z, mu, y, d)) return false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) res.z[i] = fmin(fmax(z[i], lo[i]), hi[i]);
+  res.mu[0] = mu[0];
+  res.mu[1] = mu[1];
+  res.status = 0;
+  res.mask = mask;
+  return true;
+}
+
 ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], const double lo[4],
                                     const double hi[4], const double G[2][4], const double h[2],
                                     int warm_mask) {

@@ -40,6 +40,9 @@ void emu_limit_relaxation(int n, const double* lo, const double* hi, const doubl
   }
 }
 
+// Neighbouring working sets of the line phase's wave search.
+int emu_neighbour_mask(int base, int idx) { return neighbour_mask(base, idx); }
+
 void emu_psd_project(int n, double* m) {
   for (int k = 0; k < n; ++k) {
     double a[4][4];

@@ -120,6 +120,26 @@ def test_limit_relaxation_matches_oracle(emu):
         assert (np.abs(out - ref) / scale).max() < 1e-14
 
 
+def test_neighbour_masks_of_the_wave_search(emu):
+    """The 55 neighbours a wave checks for a line: each is a valid working set
+    (at most four constraints, never both bounds of a variable), and together
+    they cover every valid set one constraint toggle away from the base."""
+    def valid(m):
+        return bin(m).count("1") <= 4 and (m & (m >> 4) & 0xF) == 0
+    rng = np.random.default_rng(3)
+    bases = [0] + [int(m) for m in rng.integers(0, 1 << 10, 400) if valid(int(m))]
+    for base in bases:
+        got = {emu.emu_neighbour_mask(base, i) for i in range(55)} - {-1}
+        assert all(valid(m) for m in got)
+        assert emu.emu_neighbour_mask(base, 55) == -1 and emu.emu_neighbour_mask(base, -1) == -1
+        for k in range(10):
+            m = base ^ (1 << k)
+            if not (base >> k) & 1 and k < 8:   # an added bound replaces the opposite one
+                m &= ~(1 << (k + 4 if k < 4 else k - 4))
+            if valid(m):
+                assert m in got, (base, k)
+
+
 def test_psd_projection_matches_oracle(emu):
     rng = np.random.default_rng(12)
     A = rng.standard_normal((50, 4, 4))
