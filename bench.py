@@ -34,7 +34,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("f11c12b988cb2e4b", 4564418), "rgg70000": ("f11c12b988cb2e4b", 118154892)}
+MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("1eb340448fcfd8bd", 4616981), "rgg70000": ("1eb340448fcfd8bd", 118202832)}
 
 
 def sweep_sources_sha() -> str:
