@@ -133,10 +133,19 @@ def psd_project(M):
 
 
 def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str = "psd",
-             rhs_shift=None) -> QP:
-    """Data of (QPsub) at iterate x with line multipliers pi and trust radius delta."""
+             rhs_shift=None, c_shift=None) -> QP:
+    """Data of (QPsub) at iterate x with line multipliers pi and trust radius delta.
+
+    ``c_shift`` (n_line, 4), if given, is added to the constraint values
+    c11..c14 of (opfc11-14) at x in their linearisations (opfqpc11-14): the
+    QP of a second-order correction, whose linearised constraints then read
+    c(x) + e + grad c(x)^T d with e the second-order error of a trial step."""
     f, t = grid.f, grid.t
     n = grid.n_line
+    if c_shift is not None:
+        # the elimination's right-hand sides are -c11 and -c12
+        cs = -np.asarray(c_shift, dtype=np.float64)[:, :2]
+        rhs_shift = cs if rhs_shift is None else rhs_shift + cs
     aR, bR, aI, bI = elimination(grid, x, rhs_shift)
     H = line_hessian(grid, x, pi)
     A, b = lift_matrix(aR, bR, aI, bI)
@@ -186,6 +195,9 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
     G[:, 1] = 2 * col(pji) * F[:, 2] + 2 * col(qji) * F[:, 3]
     h = np.stack([grid.smax_ij ** 2 - pij ** 2 - qij ** 2 - 2 * pij * f0[:, 0] - 2 * qij * f0[:, 1],
                   grid.smax_ji ** 2 - pji ** 2 - qji ** 2 - 2 * pji * f0[:, 2] - 2 * qji * f0[:, 3]], 1)
+    if c_shift is not None:
+        # c13 + e13 - 2 p_ij dp_ij - 2 q_ij dq_ij >= 0  <=>  G z <= h + e13
+        h = h + np.asarray(c_shift, dtype=np.float64)[:, 2:4]
     # a line whose box and limit rows do not intersect gets both rows relaxed
     # by the smallest common amount (plus a margin) that makes them intersect
     relax = limit_relaxation(lo, hi, G, h)

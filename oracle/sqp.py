@@ -16,8 +16,12 @@ Readings where the paper is silent (also listed in the design notes):
   doubles (up to Delta_max) after an accepted step that reached it with
   ared >= 0.75 pred, stays put after other accepted steps, and becomes
   0.5 min(Delta, ||d||_inf) after a rejection;
-* the model q(d) uses the Hessian the QP used (reduced M, possibly PSD
-  projected);
+* the model q(d; mu) of Section II-C takes the full step: its quadratic
+  term is 0.5 u^T H u over the lifted line steps u = A z + b of eq. elim
+  (d_wR, d_wI included), which in eliminated form is 0.5 z^T M z + q^T z +
+  0.5 b^T H b per line.  With the PSD projection the Hessian is the one
+  whose reduction is the projected M (H plus the change of M on the z
+  block), so the same three terms hold with the projected M;
 * pi and the ADMM multipliers are carried to the next iteration (warm
   start); pi is replaced only on acceptance;
 * optional safeguard (``pi_if_converged``, off by default): pi is replaced
@@ -52,6 +56,17 @@ class SqpParams:
     tol_step: float = 1e-6
     max_iter: int = 30
     hessian_mode: str = "psd"
+    # "admm": the QP is solved by the serial ADMM of Algorithm 2 (the method);
+    # "direct": by the interior-point solve of the same eliminated QP
+    # (``direct.solve``), which gives the SQP iterates of exact QP solutions
+    qp_solver: str = "admm"
+    # an accepted step that reached the radius doubles it when
+    # ared >= grow_ratio * pred
+    grow_ratio: float = 0.75
+    # second-order correction of a rejected step (the remedy the paper names
+    # as future work at the end of Section II-D): re-solve the QP with the
+    # second-order error of the step added to the linearised constraints
+    soc: bool = False
     # False: an accepted step always takes the new multiplier estimates
     # (Algorithm 1).  True: only when the ADMM solve met its stop test (a
     # safeguard for QPs without a feasible point; see the module docstring).
@@ -72,6 +87,7 @@ class SqpRecord:
     objective: float
     primal: float
     dual: float
+    soc: bool = False
 
 
 @dataclass
@@ -83,25 +99,32 @@ class SqpResult:
     records: list = field(default_factory=list)
 
 
-def assemble_step(grid, qp, st: admm.AdmmState) -> Iterate:
-    """Trial step d returned to SQP after the ADMM solve."""
-    z = np.stack([st.dw[grid.f], st.dth[grid.f], st.dw[grid.t], st.dth[grid.t]], 1)
+def step_from_bus_values(grid, qp, pg, qg, dw, dth) -> Iterate:
+    """Full step d from generator-side (d_pg, d_qg) and bus-side (d_w, d_th):
+    d_wR, d_wI by the elimination (eq. elim) of each line's end values."""
+    z = np.stack([dw[grid.f], dth[grid.f], dw[grid.t], dth[grid.t]], 1)
     L = qp.line
     dwR = np.einsum("li,li->l", L.aR, z) + L.bR
     dwI = np.einsum("li,li->l", L.aI, z) + L.bI
-    return Iterate(st.xg[:, 0].copy(), st.xg[:, 1].copy(), st.dw.copy(), st.dth.copy(), dwR, dwI)
+    return Iterate(np.array(pg, copy=True), np.array(qg, copy=True), np.array(dw, copy=True),
+                   np.array(dth, copy=True), dwR, dwI)
 
 
-def recover_pi(grid, x: Iterate, qp, st: admm.AdmmState) -> np.ndarray:
-    """Multipliers pi of (opfc11-14) from the KKT conditions of the line
-    subproblems (eq. line_kernel) at the line-side solution."""
+def assemble_step(grid, qp, st: admm.AdmmState) -> Iterate:
+    """Trial step d returned to SQP after the ADMM solve."""
+    return step_from_bus_values(grid, qp, st.xg[:, 0], st.xg[:, 1], st.dw, st.dth)
+
+
+def pi_from_line_kkt(grid, x: Iterate, qp, z, lam_f, mu) -> np.ndarray:
+    """Multipliers pi of (opfc11-14) from the stationarity of a line's QP in
+    (d_wR, d_wI) before elimination, given the line's voltage step z (n, 4),
+    the multipliers lam_f (n, 4) of its four flow terms and mu (n, 2) >= 0 of
+    its two linearised limit rows G z <= h."""
     L = qp.line
-    z = st.xl[:, 4:8]
     A, b = qpmod.lift_matrix(L.aR, L.bR, L.aI, L.bI)
     u = (A @ z[:, :, None])[:, :, 0] + b
     Hu = (L.H @ u[:, :, None])[:, :, 0]
-    lam = st.lam_l[:, :4]
-    mu = st.mu
+    lam = lam_f
     pij, qij, pji, qji = L.pk[:, 0], L.pk[:, 1], L.pk[:, 2], L.pk[:, 3]
     dfR = np.stack([grid.gij, -grid.bij, grid.gji, -grid.bji], 1)
     dfI = np.stack([grid.bij, grid.gij, -grid.bji, -grid.gji], 1)
@@ -119,8 +142,33 @@ def recover_pi(grid, x: Iterate, qp, st: admm.AdmmState) -> np.ndarray:
     return np.stack([p11, p12, -mu[:, 0], -mu[:, 1]], 1)
 
 
-def model_m(grid, x: Iterate, qp, d: Iterate) -> float:
-    """m(d) of Section II-C: l1 violation of the linearised nonlinear constraints."""
+def recover_pi(grid, x: Iterate, qp, st: admm.AdmmState) -> np.ndarray:
+    """Multipliers pi of (opfc11-14) from the KKT conditions of the line
+    subproblems (eq. line_kernel) at the line-side solution."""
+    return pi_from_line_kkt(grid, x, qp, st.xl[:, 4:8], st.lam_l[:, :4], st.mu)
+
+
+def direct_qp_step(grid, x: Iterate, qp):
+    """Step, pi and balance multipliers from the interior-point solve of the
+    eliminated QP.  The flow multipliers of a line are minus the balance
+    multipliers of the bus the flow leaves (a flow enters its bus's balance
+    with coefficient -1)."""
+    from . import direct
+    sol = direct.solve(grid, qp)
+    ix = direct.var_index(grid)
+    y = sol.y
+    d = step_from_bus_values(grid, qp, y[ix["pg"]], y[ix["qg"]], y[ix["w"]], y[ix["th"]])
+    B = grid.n_bus
+    nup, nuq = sol.nu[:B], sol.nu[B:]
+    f, t = grid.f, grid.t
+    lam_f = -np.stack([nup[f], nuq[f], nup[t], nuq[t]], 1)
+    mu = sol.mu.reshape(grid.n_line, 2)
+    pi = pi_from_line_kkt(grid, x, qp, np.stack([d.w[f], d.th[f], d.w[t], d.th[t]], 1), lam_f, mu)
+    return d, pi, nup, nuq
+
+
+def linearised_constraints(grid, x: Iterate, qp, d: Iterate):
+    """c_i(x) + grad c_i(x)^T d for (opfc11-14)."""
     f, t = grid.f, grid.t
     wi, wj = x.w[f], x.w[t]
     ph = x.th[f] - x.th[t]
@@ -133,14 +181,30 @@ def model_m(grid, x: Iterate, qp, d: Iterate) -> float:
     pk = qp.line.pk
     l13 = c13 - 2 * pk[:, 0] * dp[0] - 2 * pk[:, 1] * dp[1]
     l14 = c14 - 2 * pk[:, 2] * dp[2] - 2 * pk[:, 3] * dp[3]
+    return l11, l12, l13, l14
+
+
+def model_m(grid, x: Iterate, qp, d: Iterate) -> float:
+    """m(d) of Section II-C: l1 violation of the linearised nonlinear constraints."""
+    l11, l12, l13, l14 = linearised_constraints(grid, x, qp, d)
     neg = lambda v: np.maximum(0.0, -v)
     return float(np.abs(l11).sum() + np.abs(l12).sum() + neg(l13).sum() + neg(l14).sum())
 
 
+def second_order_error(grid, x: Iterate, qp, d: Iterate) -> np.ndarray:
+    """e = c(x + d) - c(x) - grad c(x)^T d of (opfc11-14) per line (n, 4):
+    the shift of the second-order correction QP."""
+    lin = linearised_constraints(grid, x, qp, d)
+    cn = acopf.nonlinear_constraints(grid, x.plus(d))
+    return np.stack([a - b for a, b in zip(cn, lin)], 1)
+
+
 def predicted_reduction(grid, x: Iterate, qp, d: Iterate, mu_merit: float) -> float:
-    """q(0; mu) - q(d; mu) of Section II-C."""
+    """q(0; mu) - q(d; mu) of Section II-C: q(d) = grad f^T d + 0.5 d^T H d
+    + mu m(d) with the full step d (the line quadratic in eliminated form
+    is 0.5 z^T M z + q^T z + 0.5 b^T H b, ``qp.qp_objective``)."""
     z = np.stack([d.w[grid.f], d.th[grid.f], d.w[grid.t], d.th[grid.t]], 1)
-    quad = qpmod.qp_objective(qp, d.pg, z) - float(qp.line.c0.sum())
+    quad = qpmod.qp_objective(qp, d.pg, z)
     return float(-quad + mu_merit * (acopf.infeas_h(grid, x) - model_m(grid, x, qp, d)))
 
 
@@ -158,32 +222,56 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
     lam_g = lam_l = None
     recs = []
     outcome = "MAX_ITER"
-    for k in range(params.max_iter):
-        qp = qpmod.build_qp(grid, x, pi, delta, params.hessian_mode)
+
+    def qp_solve(qp, lam_g, lam_l):
+        if params.qp_solver == "direct":
+            d, pi_new, nup, nuq = direct_qp_step(grid, x, qp)
+            return d, pi_new, nup, nuq, admm.AdmmResult(None, 0, 0.0, 0.0, True, 0), lam_g, lam_l
+        if params.qp_solver != "admm":
+            raise ValueError(params.qp_solver)
         start = admm.cold_state(grid) if lam_g is None else admm.warm_state(grid, lam_g, lam_l)
         res = admm.solve(grid, qp, rho, params.max_sweeps, params.eps_pri, params.eps_dual, start)
         st = res.state
-        lam_g, lam_l = st.lam_g, st.lam_l
-        d = assemble_step(grid, qp, st)
-        pi_new = recover_pi(grid, x, qp, st)
+        return (assemble_step(grid, qp, st), recover_pi(grid, x, qp, st), st.nu[:, 0], st.nu[:, 1], res,
+                st.lam_g, st.lam_l)
+
+    for k in range(params.max_iter):
+        qp = qpmod.build_qp(grid, x, pi, delta, params.hessian_mode)
+        d, pi_new, nup, nuq, res, lam_g, lam_l = qp_solve(qp, lam_g, lam_l)
         xt = x.plus(d)
-        ared = acopf.merit(grid, x, params.mu_merit) - acopf.merit(grid, xt, params.mu_merit)
+        phi0 = acopf.merit(grid, x, params.mu_merit)
+        ared = phi0 - acopf.merit(grid, xt, params.mu_merit)
         pred = predicted_reduction(grid, x, qp, d, params.mu_merit)
         dn = step_norm(d)
         accepted = ared > 0 and pred > 0
+        soc_used = False
+        if not accepted and params.soc and pred > 0:
+            # second-order correction: same model, constraints shifted by the
+            # step's second-order error; judged against the first model's pred
+            e = second_order_error(grid, x, qp, d)
+            qp2 = qpmod.build_qp(grid, x, pi, delta, params.hessian_mode, c_shift=e)
+            try:
+                d2, pi2, nup2, nuq2, res2, lg2, ll2 = qp_solve(qp2, lam_g, lam_l)
+                xt2 = x.plus(d2)
+                ared2 = phi0 - acopf.merit(grid, xt2, params.mu_merit)
+            except (RuntimeError, np.linalg.LinAlgError, FloatingPointError):
+                ared2 = -np.inf  # the correction QP has no solution: the step stays rejected
+            if ared2 > 0:
+                d, pi_new, nup, nuq, res, lam_g, lam_l = d2, pi2, nup2, nuq2, res2, lg2, ll2
+                xt, ared, accepted, soc_used = xt2, ared2, True, True
         if accepted:
             x = xt
             stop_set = params.eps_pri > 0 or params.eps_dual > 0
             if not params.pi_if_converged or (stop_set and res.converged):
                 pi = pi_new
-            if dn >= 0.99 * delta and ared >= 0.75 * pred:
+            if dn >= 0.99 * delta and ared >= params.grow_ratio * pred:
                 delta = min(2 * delta, params.delta_max)
         else:
             delta = 0.5 * min(delta, dn)
         pr = acopf.primal_infeasibility(grid, x)["primal"]
-        du = acopf.dual_infeasibility(grid, x, st.nu[:, 0], st.nu[:, 1], pi)
+        du = acopf.dual_infeasibility(grid, x, nup, nuq, pi)
         recs.append(SqpRecord(k, accepted, ared, pred, delta, dn, res.sweeps, res.r, res.s,
-                              acopf.objective(grid, x.pg), pr, du))
+                              acopf.objective(grid, x.pg), pr, du, soc_used))
         if accepted and pr <= params.tol_primal and du <= params.tol_dual:
             outcome = "CONVERGED"
             break

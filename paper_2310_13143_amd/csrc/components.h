@@ -866,7 +866,7 @@ namespace acopf {
 // Merit pieces of line l (Section II-C) at x and at the trial point x + d:
 // out[0] = h contribution at x, out[1] = at x + d, out[2] = m(d)
 // contribution (linearised constraints), out[3] = the line's model
-// quadratic 0.5 z^T M z + q^T z at the bus-side step z.
+// quadratic 0.5 z^T M z + q^T z + 0.5 b^T H b at the bus-side step z.
 ACOPF_HD void merit_line(const acopf_grid& g, const acopf_iterate& x, const Workspace& w,
                          const acopf_iterate& d, int l, double out[4]) {
   const int L = w.n_line;
@@ -904,13 +904,15 @@ ACOPF_HD void merit_line(const acopf_grid& g, const acopf_iterate& x, const Work
   const double dpji = gjj * dwj + gji * dR - bji * dI, dqji = -bjj * dwj - bji * dR - gji * dI;
   const double l13 = c13 - 2.0 * pij * dpij - 2.0 * qij * dqij;
   const double l14 = c14 - 2.0 * pji * dpji - 2.0 * qji * dqji;
-  // model quadratic with the QP's reduced Hessian
+  // model quadratic 0.5 u^T H u over the full step u = A z + b (eq. elim,
+  // Section II-C): 0.5 z^T M z + q^T z + 0.5 b^T H b with the QP's reduced
+  // (possibly projected) M
   const double z[4] = {d.w[f], d.th[f], d.w[t], d.th[t]};
   double Mp[10], M[4][4];
 #pragma unroll
   for (int k = 0; k < 10; ++k) Mp[k] = w.line[(LF_M + k) * L + l];
   sym_unpack(Mp, M);
-  double quad = 0.0;
+  double quad = w.line[LF_C0 * L + l];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double mz = M[i][0] * z[0] + M[i][1] * z[1] + M[i][2] * z[2] + M[i][3] * z[3];

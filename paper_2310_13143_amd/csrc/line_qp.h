@@ -558,7 +558,9 @@ ACOPF_HD LineQPResult solve_line_qp(const double Pp[10], const double c[4], cons
       const double t1 = (kdrop >= 0) ? un / rd : INF;
       // primal step length: reach constraint p
       const double nz = dot4(np_, dz);
-      const double t2 = (nz > 1e-14 * npn) ? -(dot4(np_, z) - bp) / nz : INF;
+      // (a full working set of four independent constraints leaves no primal
+      // direction: dz vanishes up to rounding)
+      const double t2 = (q < 4 && nz > 1e-14 * npn) ? -(dot4(np_, z) - bp) / nz : INF;
       const double t = fmin(t1, t2);
       if (t >= INF) { status = 1; break; }
 #pragma unroll

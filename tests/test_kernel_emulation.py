@@ -308,3 +308,54 @@ def _layout(emu, g, base):
     def get(name, n):
         return np.ctypeslib.as_array(where[name], (n,)).copy()
     return get
+
+
+@pytest.mark.parametrize("feasible", [True, False])
+def test_line_qp_vertex_with_a_fifth_violated_constraint(emu, feasible):
+    """The unconstrained minimiser lies beyond a vertex of the box (all four
+    variables past one of their bounds) and satisfies the first limit row,
+    which the vertex violates: the dual method reaches a full working set of
+    four bounds with a fifth constraint still violated.  Where the row meets
+    the box the result is the enumeration's minimiser; where it cannot, the
+    solver reports no feasible point (status 1)."""
+    rng = np.random.default_rng(21 if feasible else 22)
+    cases = []
+    while len(cases) < 300:
+        lo = -rng.uniform(0.01, 0.3, 4)
+        hi = rng.uniform(0.01, 0.3, 4)
+        sgn = rng.choice([-1.0, 1.0], 4)
+        v = np.where(sgn > 0, hi, lo)
+        zu = v + sgn * rng.uniform(0.5, 3.0, 4) * (hi - lo)
+        A = rng.standard_normal((4, 4))
+        Q = A @ A.T + 0.3 * np.eye(4)
+        Q *= rng.uniform(1.0, 1e5)
+        g = rng.standard_normal(4)
+        if g @ (zu - v) > 0:
+            g = -g
+        gmin = np.minimum(g * lo, g * hi).sum()
+        top, bot = g @ v, g @ zu
+        # h kept away from the interval ends: a row through a vertex of the
+        # box makes the minimiser's multipliers non-unique
+        lo_h, hi_h = (max(gmin, bot), top) if feasible else (bot, gmin)
+        if hi_h - lo_h < 1e-3 * (1.0 + abs(top)):
+            continue
+        h = rng.uniform(lo_h + 0.05 * (hi_h - lo_h), hi_h - 0.05 * (hi_h - lo_h))
+        G = np.stack([g, g])
+        hh = np.array([h, h + 100.0])
+        cases.append((Q, -Q @ zu, lo, hi, G, hh))
+    Q, c, lo, hi, G, h = (np.ascontiguousarray(np.stack(a)) for a in zip(*cases))
+    n = Q.shape[0]
+    P = np.linalg.inv(Q)
+    iu = np.triu_indices(4)
+    Pp = np.ascontiguousarray(P[:, iu[0], iu[1]])
+    z = np.zeros((n, 4)); mu = np.zeros((n, 2)); st = np.zeros(n, dtype=np.int32); m = np.zeros(n, dtype=np.int32)
+    emu.emu_line_qp(n, ptr(Pp), ptr(c), ptr(lo), ptr(hi), ptr(G), ptr(h), ptr(z), ptr(mu), ptr(st), None, ptr(m))
+    zr, mur, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h)
+    if feasible:
+        assert feas.all() and (st == 0).all()
+        scale = 1.0 + np.abs(zr).max(1)
+        assert (np.abs(z - zr).max(1) / scale).max() < 1e-8
+        assert (np.abs(mu - mur).max(1) / (1.0 + np.abs(mur).max(1))).max() < 1e-6
+    else:
+        assert not feas.any()
+        assert (st == 1).all()
