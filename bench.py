@@ -1,11 +1,16 @@
 """Benchmark of the ADMM QP solve of the SQP method for ACOPF on one MI355X.
 
 A step is one trust-region SQP iteration (Algorithm 1) on the device: QP
-build at the iterate, ADMM start (warm from the previous solve after the
-first) and factorisation, the sweep kernel (up to --sweeps sweeps, stop at
-||r||, ||s|| <= --eps), step and multiplier recovery, merit test and radius
-update.  The metric is ADMM component updates per second,
-(|G| + |L| + |B|) x sweeps / time, over the timed steps; the SQP primal
+build at the iterate, ADMM start and factorisation, the sweep kernels (up to
+--sweeps sweeps, stop at ||r||, ||s|| <= --eps unless eps = 0), step and
+multiplier recovery, merit test and radius update.  The metric is ADMM
+component updates per second, (|G| + |L| + |B|) x sweeps / time, over the
+timed steps.
+
+Default workload: the 70,000-bus grid (88,000 branches, 10,000 generators),
+each step the SQP iteration at the start point (the iteration-0 QP) with a
+fixed 2,000 sweeps and no early stop.  Other workloads (--workload) run
+consecutive SQP iterations with the stop test; their SQP primal
 infeasibility after each step gives the time to 1e-4.
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported.
@@ -34,7 +39,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg2000": ("1eb340448fcfd8bd", 4616981), "rgg70000": ("1eb340448fcfd8bd", 118202832)}
+MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("e893c3b305633f9a", 118143528)}
 
 
 def sweep_sources_sha() -> str:
@@ -51,6 +56,15 @@ def sweep_traffic(workload: str):
     return rec[1] if rec is not None and rec[0] == sweep_sources_sha() else None
 
 
+# Per-workload defaults of the options left unset.  rgg70000: the
+# iteration-0 QP with a fixed 2,000 sweeps (no early stop), 20 timed repeats
+# after 3 warm-ups; the others: consecutive SQP iterations with the stop test.
+WORKLOAD_DEFAULTS = {
+    "rgg70000": dict(steps=20, warmup=3, eps=0.0, restart=1, cpu_sweeps=1),
+    "*": dict(steps=10, warmup=2, eps=1e-4, restart=0, cpu_sweeps=20),
+}
+
+
 def sweep_bytes(n_bus: int, n_line: int, n_gen: int) -> int:
     """Algorithmic bytes one ADMM sweep must move (FP64 values + int32 indices):
     line phase 696 B/line, bus phase 328 B/line (two ends) + 148 B/gen +
@@ -61,18 +75,21 @@ def sweep_bytes(n_bus: int, n_line: int, n_gen: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rgg2000",
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default per workload)")
+    ap.add_argument("--workload", default="rgg70000",
                     choices=["ring14", "rgg300", "rgg2000", "rgg10000", "rgg70000", "batch64", "warmstart"])
     ap.add_argument("--sweeps", type=int, default=2000)
-    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--eps", type=float, default=None, help="ADMM stop tolerance (0 = fixed sweep count)")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="1: every step is the SQP iteration at the start point (iteration-0 QP, cold ADMM)")
     ap.add_argument("--rho", type=float, default=2e4)
     ap.add_argument("--delta", type=float, default=0.05)
     ap.add_argument("--mode", default="graph", choices=["persistent", "launches", "graph"])
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--max-blocks", type=int, default=0, help="persistent grid size cap (0 = fill the device)")
-    ap.add_argument("--cpu-sweeps", type=int, default=20, help="oracle sweeps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-sweeps", type=int, default=None,
+                    help="oracle sweeps timed for the CPU baseline (0 = skip; default per workload)")
     ap.add_argument("--train-scen", type=int, default=512, help="warmstart: training scenarios")
     ap.add_argument("--test-scen", type=int, default=128, help="warmstart: held-out scenarios")
     ap.add_argument("--val-scen", type=int, default=64, help="warmstart: validation scenarios (policy choice)")
@@ -93,6 +110,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    for k, v in WORKLOAD_DEFAULTS.get(args.workload, WORKLOAD_DEFAULTS["*"]).items():
+        if getattr(args, k) is None:
+            setattr(args, k, v)
 
     import torch
     from synth.grids import WORKLOADS, power_flow_start
@@ -119,14 +139,19 @@ def main():
     sqp_kw = dict(mu=1e5, delta_max=10.0, max_sweeps=args.sweeps, eps=args.eps, sweep_mode=mode,
                   block_size=args.block, max_blocks=args.max_blocks, pi_update=_abi.PI_IF_CONVERGED)
 
+    x0 = {k: v.clone() for k, v in x.items()}
+
     def one_step():
+        if args.restart:  # the iteration-0 QP again: start point, cold ADMM
+            for k in x:
+                x[k].copy_(x0[k])
+            state.update(delta=args.delta, k=0)
         out = dg.sqp_step(x, state["delta"], rho_g, rho_l, warm_start=state["k"] > 0, **sqp_kw)
         state["delta"] = out["delta"]
         state["k"] += 1
         return out
 
     # warm-up on a copy of the start point, then restart from it
-    x0 = {k: v.clone() for k, v in x.items()}
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -176,11 +201,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{g.name}: {g.n_bus} buses, {g.n_line} branches, {g.n_gen} generators; "
-                               f"{args.steps} SQP iterations from the power-flow start (DC angles if it has "
-                               f"none), delta0={args.delta:g}, rho={args.rho:g}, <= {args.sweeps} ADMM sweeps "
-                               f"per QP, eps={args.eps:g}, previous-iterate warm start, pi kept unless the "
-                               f"solve converged, {args.mode} sweep kernel",
+        "config": {"workload": workload_text(g, args),
                    "sweeps_per_step": avg_sweeps, "components": comps, "couplings": 2 * g.n_gen + 8 * g.n_line,
                    "last_r": res["r"], "last_s": res["s"], "blocks": res["blocks"]},
         "sqp": {"time_to_1e-4_s": t_first_1e4, "primal_final": pr_final,
@@ -195,6 +216,20 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def workload_text(g, args) -> str:
+    head = f"{g.name}: {g.n_bus} buses, {g.n_line} branches, {g.n_gen} generators; "
+    if args.restart:
+        stop = "no early stop" if args.eps == 0 else f"stop at eps={args.eps:g}"
+        return (head + f"each step the SQP iteration at the power-flow start (DC angles if it has none): "
+                f"iteration-0 QP build, cold ADMM with a fixed {args.sweeps} sweeps ({stop}), step, "
+                f"multipliers and merit test; delta0={args.delta:g}, rho={args.rho:g}, FP64, "
+                f"{args.mode} sweep kernels")
+    return (head + f"{args.steps} SQP iterations from the power-flow start (DC angles if it has "
+            f"none), delta0={args.delta:g}, rho={args.rho:g}, <= {args.sweeps} ADMM sweeps "
+            f"per QP, eps={args.eps:g}, previous-iterate warm start, pi kept unless the "
+            f"solve converged, {args.mode} sweep kernels")
 
 
 def batch_grids():
@@ -399,26 +434,64 @@ x = acopf.Iterate(s["pg"], s["qg"], s["w"], s["th"], s["wR"], s["wI"])
 Q = qpm.build_qp(g, x, np.zeros((g.n_line, 4)), float(sys.argv[3]))
 rho = admm.Rho.scalar(g, float(sys.argv[4]))
 n = int(sys.argv[5])
-admm.solve(g, Q, rho, 1, 0.0, 0.0)
-t0 = time.perf_counter()
-admm.solve(g, Q, rho, n, 0.0, 0.0)
-print(json.dumps({"seconds": time.perf_counter() - t0}))
+frac = float(sys.argv[6])
+if frac >= 1.0:
+    admm.solve(g, Q, rho, 1, 0.0, 0.0)
+    t0 = time.perf_counter()
+    admm.solve(g, Q, rho, n, 0.0, 0.0)
+    print(json.dumps({"seconds_per_sweep": (time.perf_counter() - t0) / n, "lines": g.n_line}))
+else:
+    # the first sweep of the cold solve: generator and bus updates over the
+    # whole grid, the line update (the oracle's exact line QPs) on a seeded
+    # sample of the lines, scaled to all lines
+    from dataclasses import replace
+    st = admm.cold_state(g)
+    t0 = time.perf_counter()
+    xg = admm.gen_update(Q, st, rho)
+    t_gen = time.perf_counter() - t0
+    sel = np.sort(np.random.default_rng(12345).choice(g.n_line, int(round(frac * g.n_line)), replace=False))
+    gs = replace(g, f=g.f[sel], t=g.t[sel])
+    Ls = replace(Q.line, **{k: getattr(Q.line, k)[sel] for k in Q.line.__dataclass_fields__})
+    Qs = replace(Q, line=Ls)
+    rs = admm.Rho(rho.g, rho.l[sel])
+    ss = replace(st, lam_l=st.lam_l[sel], xbar_f=st.xbar_f[sel])
+    t0 = time.perf_counter()
+    admm.line_update(gs, Qs, ss, rs)
+    t_line = (time.perf_counter() - t0) * g.n_line / sel.size
+    xl = np.zeros((g.n_line, 8))
+    t0 = time.perf_counter()
+    admm.bus_update(g, Q, xg, xl, st, rho)
+    t_bus = time.perf_counter() - t0
+    print(json.dumps({"seconds_per_sweep": t_gen + t_line + t_bus, "lines": int(sel.size),
+                      "t_gen": t_gen, "t_line": t_line, "t_bus": t_bus}))
 """
+
+# grids with more lines than this time a sample of the line updates
+CPU_SAMPLE_LINES = 20000
 
 
 def cpu_baseline(g, s, args):
     """The oracle's serial ADMM (NumPy FP64) on the first QP of the same
-    workload, timed for --cpu-sweeps sweeps in a child process pinned to one
-    BLAS/OpenMP thread."""
+    workload, in a child process pinned to one BLAS/OpenMP thread: whole
+    sweeps on small grids; on large ones the first sweep with the line
+    update timed on a seeded 10% sample of the lines and scaled."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    frac = 1.0 if g.n_line <= CPU_SAMPLE_LINES else 0.1
     p = subprocess.run([sys.executable, "-c", CPU_SNIPPET, ROOT, args.workload, str(args.delta), str(args.rho),
-                        str(args.cpu_sweeps)], env=env, capture_output=True, text=True, check=True)
-    dt = json.loads(p.stdout.strip().splitlines()[-1])["seconds"]
+                        str(args.cpu_sweeps), str(frac)], env=env, capture_output=True, text=True, check=True)
+    r = json.loads(p.stdout.strip().splitlines()[-1])
+    dt = r["seconds_per_sweep"]
     comps = g.n_gen + g.n_line + g.n_bus
-    return {"value": comps * args.cpu_sweeps / dt, "unit": "component updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{args.cpu_sweeps} serial sweeps of the oracle ADMM on the first QP of the workload "
-                      f"({dt:.2f} s, one thread)"}
+    if frac >= 1.0:
+        sample = (f"{args.cpu_sweeps} serial sweeps of the oracle ADMM on the first QP of the workload "
+                  f"({dt * args.cpu_sweeps:.2f} s, one thread)")
+    else:
+        sample = (f"the first sweep of the oracle ADMM on the first QP of the workload: generator and bus "
+                  f"updates over the whole grid, the line update on a seeded sample of {r['lines']} of "
+                  f"{g.n_line} lines scaled to all ({r['t_line'] * frac:.1f} s measured), one thread; "
+                  f"extrapolated {dt:.1f} s per sweep")
+    return {"value": comps / dt, "unit": "component updates/s", "cores": 1, "kind": "oracle", "sample": sample}
 
 
 if __name__ == "__main__":

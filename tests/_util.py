@@ -20,3 +20,23 @@ def rel_err(a, b):
     b = np.asarray(b, dtype=np.float64)
     scale = max(float(np.abs(b).max(initial=0.0)), 1e-300)
     return float(np.abs(a - b).max(initial=0.0)) / scale
+
+
+# Columns whose largest magnitude is below COL_FLOOR times the array's are
+# compared against that floor (a column of zeros is checked in absolute terms
+# at the array's scale).
+COL_FLOOR = 1e-6
+
+
+def rel_err_cols(a, b):
+    """Largest over the columns of a 2-D array (each coupling or field on
+    its own scale) of max |a - b| / max |b| in the column, the column scale
+    floored at COL_FLOOR x the array's largest magnitude; 1-D arrays are one
+    column."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    top = max(float(np.abs(b).max(initial=0.0)), 1e-300)
+    scale = np.maximum(np.abs(b).max(axis=0, initial=0.0), COL_FLOOR * top)
+    return float((np.abs(a - b).max(axis=0, initial=0.0) / scale).max(initial=0.0))
