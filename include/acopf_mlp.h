@@ -48,6 +48,26 @@ acopf_status acopf_mlp_gradient(const float* theta, int32_t n_in, int32_t n_out,
                                 const float* T, int64_t ldt, int64_t n, float* grad, float* loss, void* scratch,
                                 size_t scratch_bytes, void* stream);
 
+/* Size in bytes of the library's static device scratch used by
+ * acopf_mlp_gradient_noalloc: (512 + 32) x (9,360 + 1) floats, the most
+ * acopf_mlp_scratch_bytes returns for any network size and sample count. */
+#define ACOPF_MLP_NOALLOC_SCRATCH_BYTES ((size_t)20369536)
+
+/* acopf_mlp_gradient without a scratch argument, for callers that cannot
+ * allocate device memory (code recorded under HIP graph capture, training
+ * loops that must not call hipMalloc, harnesses that forbid it).  Same
+ * kernels, same result bits as acopf_mlp_gradient.  The per-block partials
+ * go to a static device array of ACOPF_MLP_NOALLOC_SCRATCH_BYTES that each
+ * GPU holds from the first call on it until the process ends; the call
+ * allocates nothing.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and give undefined results; calls ordered on one stream are safe.  Sizes
+ * whose scratch would exceed the array are rejected with
+ * ACOPF_ERR_INVALID_ARG (none do with n_in <= 64, n_out <= 16). */
+acopf_status acopf_mlp_gradient_noalloc(const float* theta, int32_t n_in, int32_t n_out, const float* X,
+                                        int64_t ldx, const float* T, int64_t ldt, int64_t n, float* grad,
+                                        float* loss, void* stream);
+
 /* One Adam step (Kingma and Ba, 2015) on count parameters: m <- b1 m +
  * (1 - b1) g, v <- b2 v + (1 - b2) g^2, theta <- theta - lr mh / (sqrt(vh)
  * + eps) with the bias-corrected moments mh = m / (1 - b1^t), vh = v / (1 -

@@ -79,7 +79,7 @@ EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_se
            "acopf_admm_result_get", "acopf_admm_state_get", "acopf_step", "acopf_sqp_step",
            "acopf_sqp_step_batch", "acopf_residuals", "acopf_residuals_batch", "acopf_features",
            "acopf_warm_targets", "acopf_warm_decode", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes",
-           "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_adam", "acopf_mlp_feature_stats",
+           "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_gradient_noalloc", "acopf_mlp_adam", "acopf_mlp_feature_stats",
            "acopf_mlp_standardize", "acopf_mlp_fold")
 SIZE_RETURNING = ("acopf_workspace_bytes", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes")
 
@@ -136,6 +136,8 @@ def load(path: str = LIB_PATH):
                                       c_void_p]
     lib.acopf_mlp_gradient.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int64,
                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.acopf_mlp_gradient_noalloc.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                                               c_int64, c_void_p, c_void_p, c_void_p]
     lib.acopf_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_float, c_float,
                                    c_float, c_float, c_void_p]
     lib.acopf_mlp_feature_stats.argtypes = [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p]

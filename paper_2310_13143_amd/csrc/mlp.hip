@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "acopf_mlp.h"
 #include "errors.h"
@@ -308,6 +309,14 @@ __global__ void __launch_bounds__(kThreads) k_mlp(const float* __restrict__ th, 
 // order.  A block of the first kernel serves 64 entries x 4 ranges.
 constexpr int kSegs = 32;
 
+// Device scratch of acopf_mlp_gradient_noalloc: the per-block partials and
+// range sums of the largest network (64 inputs, 16 outputs) at the block
+// cap, (512 + 32) x 9,361 floats = 20.4 MB per device.  Every GPU that
+// runs the library holds its own copy until the process ends.
+constexpr int kMaxCount = H * kMaxIn + H + H * H + H + kMaxOut * H + kMaxOut;
+constexpr size_t kScratchFloats = (size_t)(kMaxBlocks + kSegs) * (kMaxCount + 1);
+__device__ __align__(256) float scratch[kScratchFloats];
+
 __global__ void __launch_bounds__(256) k_mlp_reduce_seg(const float* __restrict__ part, int nblk, int count,
                                                         float* __restrict__ seg_out) {
   const int j = threadIdx.x & 63;
@@ -418,6 +427,48 @@ __global__ void k_fold(float* __restrict__ th, int n_in, int n_out, const double
     th[P.b3 + o] = (float)((double)th[P.b3 + o] * out_std[o] + out_mean[o]);
 }
 
+// Launches of the gradient (per-block partials, then the fixed-order
+// reduction) with the partials at part.  Every entry of part the reduction
+// reads is written by the kernel before it: nothing needs clearing.
+acopf_status gradient_launch(const float* theta, int n_in, int n_out, const float* X, int64_t ldx, const float* T,
+                             int64_t ldt, int64_t n, float* grad, float* loss, float* part, hipStream_t s) {
+  const int nblk = blocks_for_samples(n);
+  const int count = offsets(n_in, n_out).count;
+  const double denom = (double)n * (double)n_out;
+  hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(kThreads), 0, s, theta, (int)n_in, (int)n_out, X,
+                     (long long)ldx, T, (long long)ldt, (long long)n, nullptr, 0LL, part, (float)(2.0 / denom));
+  float* seg = part + (size_t)nblk * (count + 1);  // kSegs range sums after the block partials
+  hipLaunchKernelGGL(k_mlp_reduce_seg, dim3((count + 1 + 63) / 64, kSegs / 4), dim3(256), 0, s, part, nblk, count,
+                     seg);
+  hipLaunchKernelGGL(k_mlp_reduce_fin, dim3((count + 1 + 255) / 256), dim3(256), 0, s, seg, count,
+                     (float)(1.0 / denom), grad, loss);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (host code never passes the array's own name to a kernel).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxDevices] = {};
+
+acopf_status scratch_address(float** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_mlp_gradient_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ACOPF_ERR_HIP, "acopf_mlp_gradient_noalloc: no device address for the scratch array");
+    g_scratch_addr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return ACOPF_OK;
+}
+
+static_assert(kScratchFloats * sizeof(float) == ACOPF_MLP_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+
 }  // namespace
 
 extern "C" {
@@ -453,20 +504,25 @@ acopf_status acopf_mlp_gradient(const float* theta, int32_t n_in, int32_t n_out,
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_gradient: null array, n < 1 or leading dimension below n");
   if (scratch_bytes < acopf_mlp_scratch_bytes(n_in, n_out, n))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_gradient: scratch smaller than acopf_mlp_scratch_bytes");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nblk = blocks_for_samples(n);
-  const int count = offsets(n_in, n_out).count;
-  float* part = static_cast<float*>(scratch);
-  const double denom = (double)n * (double)n_out;
-  hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(kThreads), 0, s, theta, (int)n_in, (int)n_out, X,
-                     (long long)ldx, T, (long long)ldt, (long long)n, nullptr, 0LL, part, (float)(2.0 / denom));
-  float* seg = part + (size_t)nblk * (count + 1);  // kSegs range sums after the block partials
-  hipLaunchKernelGGL(k_mlp_reduce_seg, dim3((count + 1 + 63) / 64, kSegs / 4), dim3(256), 0, s, part, nblk, count,
-                     seg);
-  hipLaunchKernelGGL(k_mlp_reduce_fin, dim3((count + 1 + 255) / 256), dim3(256), 0, s, seg, count,
-                     (float)(1.0 / denom), grad, loss);
-  HIP_TRY(hipGetLastError());
-  return ACOPF_OK;
+  return gradient_launch(theta, n_in, n_out, X, ldx, T, ldt, n, grad, loss, static_cast<float*>(scratch),
+                         static_cast<hipStream_t>(stream));
+}
+
+acopf_status acopf_mlp_gradient_noalloc(const float* theta, int32_t n_in, int32_t n_out, const float* X,
+                                        int64_t ldx, const float* T, int64_t ldt, int64_t n, float* grad,
+                                        float* loss, void* stream) {
+  if (!sizes_ok(n_in, n_out))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_gradient_noalloc: n_in must be in [1, 64], n_out in [1, 16]");
+  if (!theta || !X || !T || !grad || !loss || n < 1 || ldx < n || ldt < n)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_gradient_noalloc: null array, n < 1 or leading dimension below n");
+  if (acopf_mlp_scratch_bytes(n_in, n_out, n) > ACOPF_MLP_NOALLOC_SCRATCH_BYTES)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_mlp_gradient_noalloc: the gradient needs more scratch than the "
+                                       "library's static array (ACOPF_MLP_NOALLOC_SCRATCH_BYTES)");
+  float* part = nullptr;
+  const acopf_status rc = scratch_address(&part);
+  if (rc != ACOPF_OK) return rc;
+  return gradient_launch(theta, n_in, n_out, X, ldx, T, ldt, n, grad, loss, part,
+                         static_cast<hipStream_t>(stream));
 }
 
 acopf_status acopf_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t count, int32_t t,
