@@ -96,6 +96,16 @@ typedef struct {
   int32_t trace;        /* 1 = also sum |r_c| and |s_c| of every coupling over the
                            sweeps (reset at the start of the solve; exported by
                            acopf_admm_state_get; launch-per-phase mode only)   */
+  int32_t balance_every;/* residual balancing of the penalties after every
+                           balance_every-th sweep (a multiple of 64; 0 = off;
+                           launch-per-phase modes): all penalties of a scenario
+                           times balance_tau when ||r|| > balance_mu ||s||,
+                           divided by it when ||s|| > balance_mu ||r||; the
+                           multipliers are not scaled.  The heuristic the paper
+                           names beside its stop rule (Section IV-B5); the
+                           final penalties are exported by acopf_admm_state_get */
+  double balance_mu;    /* e.g. 10 */
+  double balance_tau;   /* e.g. 2, > 1 */
 } acopf_admm_params;
 
 typedef struct {
@@ -241,7 +251,15 @@ typedef enum {
  * after an accepted step that reached it with ared >= grow_ratio * pred,
  * unchanged after another accepted step, 0.5 min(delta, ||d||_inf) after a
  * rejection.  On acceptance x <- x + d and x.pi <- the new estimates, on
- * the device.  Synchronises the stream and fills *state (host). */
+ * the device.  Synchronises the stream and fills *state (host).
+ *
+ * With soc = 1 a rejected step with a positive predicted reduction gets a
+ * second-order correction (the remedy the paper names as future work at the
+ * end of Section II-D): e = c(x + d) - c(x) - grad c(x)^T d of (opfc11-14) is
+ * added to c(x) in the linearised constraints, that QP is solved by ADMM
+ * from the rejected solve's multipliers, and its step replaces d when its
+ * actual reduction is positive (judged against the first step's pred; the
+ * radius then grows as after any accepted step that reached it). */
 typedef struct {
   double mu;             /* l1 merit penalty (the paper uses 1e5)         */
   double delta_max;      /* trust-radius cap                              */
@@ -252,7 +270,18 @@ typedef struct {
   const double* lam_g0;  /* ACOPF_START_GIVEN: starting multipliers,      */
   const double* lam_l0;  /* layout of acopf_admm_state (device)           */
   int32_t pi_update;     /* acopf_pi_update                               */
+  int32_t soc;           /* 1: second-order correction of rejected steps  */
+  /* Termination of a scenario's run on the device (Algorithm 1, the stop
+   * rule after the algorithm): with stop = 1, after each iteration the
+   * residual report is formed on the device and a scenario stops when its
+   * step was accepted with primal <= tol_primal and dual <= tol_dual, or
+   * accepted with ||d||_inf < tol_step, or its radius fell below
+   * delta_min.  A stopped scenario's iterate, radius and multipliers are
+   * frozen: later calls leave it out until acopf_set_delta starts a new
+   * run.  See acopf_sqp_outcome_batch. */
+  int32_t stop;
   int32_t reserved;
+  double tol_primal, tol_dual, tol_step, delta_min;
 } acopf_sqp_params;
 
 typedef struct {
@@ -267,7 +296,8 @@ typedef struct {
   double admm_ms;        /* duration of the ADMM sweeps (HIP events on the stream) */
   int32_t status;        /* the scenario's acopf_admm_result.status; a failed QP
                             counts as a rejected step (radius halved)      */
-  int32_t reserved;
+  int32_t soc_sweeps;    /* sweeps of the second-order correction's solve (0: not tried);
+                            accepted with soc_sweeps > 0: the corrected step was taken */
 } acopf_sqp_state;
 
 acopf_status acopf_sqp_step(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
@@ -280,10 +310,30 @@ acopf_status acopf_sqp_step(const acopf_grid* grid, const acopf_iterate* x, cons
  * copied back and the call does not synchronise the stream.  With states =
  * NULL and eps_pri = eps_dual = 0 the call enqueues device work only, so a
  * caller may record it under stream capture and replay the graph as SQP
- * iterations (the iterate, radii and multipliers stay on the device). */
+ * iterations (the iterate, radii and multipliers stay on the device).  Under
+ * capture the ADMM stop test (eps > 0) runs on the device: every chunk of
+ * sweeps up to max_sweeps is recorded, and launches of a stopped scenario
+ * return at once; with stop = 1 stopped scenarios leave the later
+ * iterations of the recorded loop. */
 acopf_status acopf_sqp_step_batch(const acopf_grid* grid, const acopf_iterate* x, const acopf_iterate* d,
                                   const double* rho_g, const double* rho_l, const acopf_sqp_params* params,
                                   void* workspace, void* stream, acopf_sqp_state* states);
+
+/* Per-scenario state of device-stopped SQP runs (acopf_sqp_params.stop). */
+typedef struct {
+  int32_t done;          /* the run has stopped                                     */
+  int32_t reason;        /* 0 running; 1 primal and dual infeasibility met after an
+                            accepted step; 2 accepted step below tol_step; 3 radius
+                            below delta_min                                         */
+  int32_t iterations;    /* SQP iterations taken (up to and including the stopping one) */
+  int32_t reserved;
+  double seconds;        /* device wall-clock time from acopf_set_delta to the stop
+                            (0 while running)                                       */
+} acopf_sqp_outcome;
+
+/* Reads the per-scenario outcomes (host array of n_scen entries;
+ * synchronises the stream). */
+acopf_status acopf_sqp_outcome_batch(const acopf_grid* grid, void* workspace, void* stream, acopf_sqp_outcome* out);
 
 /* Infeasibility report of the ACOPF (eq. acopf) at x (synchronises; host
  * result): infinity norms of the power-balance residuals, of (opfc11),

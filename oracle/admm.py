@@ -194,10 +194,36 @@ def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None):
     return new, float(np.sqrt(r2)), float(np.sqrt(s2)), feas
 
 
+@dataclass
+class Balance:
+    """Residual balancing of the penalties (the heuristic the paper names,
+    in a commented passage beside its ADMM termination rule, for better
+    convergence; Section V lists the heuristic ADMM tuning as a limitation).
+    After every `every`-th sweep that does not stop the solve, all penalties
+    are multiplied by tau when ||r|| > mu ||s||, divided by tau when
+    ||s|| > mu ||r||, and kept otherwise; the multipliers lam are not
+    scaled (the unscaled form)."""
+    mu: float = 10.0
+    tau: float = 2.0
+    every: int = 64
+
+
+def balance_factor(r: float, s: float, b: Balance) -> float:
+    if r > b.mu * s:
+        return b.tau
+    if s > b.mu * r:
+        return 1.0 / b.tau
+    return 1.0
+
+
 def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
-          state: AdmmState | None = None, record: bool = False, record_states: bool = False):
-    """Algorithm 2 until ||r|| <= eps_pri and ||s|| <= eps_dual or max_sweeps."""
+          state: AdmmState | None = None, record: bool = False, record_states: bool = False,
+          balance: Balance | None = None):
+    """Algorithm 2 until ||r|| <= eps_pri and ||s|| <= eps_dual or max_sweeps;
+    with ``balance``, residual balancing of the penalties between sweeps
+    (the result's ``rho`` holds the final penalties)."""
     st = cold_state(grid) if state is None else state.copy()
+    rho = Rho(rho.g.copy(), rho.l.copy())
     Q = line_matrices(qp, rho)
     hist = []
     r = s = np.inf
@@ -211,5 +237,14 @@ def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
         if record_states:
             hist.append(st.copy())
         if r <= eps_pri and s <= eps_dual:
-            return AdmmResult(st, k, r, s, True, bad, hist)
-    return AdmmResult(st, k, r, s, False, bad, hist)
+            res = AdmmResult(st, k, r, s, True, bad, hist)
+            res.rho = rho
+            return res
+        if balance is not None and k % balance.every == 0 and k < max_sweeps:
+            f = balance_factor(r, s, balance)
+            if f != 1.0:
+                rho = Rho(rho.g * f, rho.l * f)
+                Q = line_matrices(qp, rho)
+    res = AdmmResult(st, k, r, s, False, bad, hist)
+    res.rho = rho
+    return res

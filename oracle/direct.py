@@ -113,41 +113,32 @@ def kkt_report(m: QPMatrices, y, nu, mu, zlo, zhi) -> dict:
             "complementarity": float(comp)}
 
 
-def solve(grid, qp, tol: float = 1e-11, max_iter: int = 200) -> DirectSolution:
-    m = assemble(grid, qp)
-    n = m.P.shape[0]
-    fixed = m.lo >= m.hi
-    free = np.nonzero(~fixed)[0]
-    yfix = np.where(fixed, m.hi, 0.0)
-    # reduced problem in the free variables
-    Pf = m.P[free][:, free].tocsc()
-    qf = m.q[free] + (m.P @ yfix)[free]
-    Af = m.A[:, free].tocsc()
-    bf = m.b - m.A @ yfix
-    nf = free.size
-    I = sp.identity(nf, format="csr")
-    Gin = sp.vstack([m.Gl[:, free], I, -I]).tocsr()
-    hin = np.concatenate([m.hl - m.Gl @ yfix, m.hi[free], -m.lo[free]])
-    mi, me = Gin.shape[0], Af.shape[0]
-
+def ipm(P, q, A, b, Gin, hin, tol: float = 1e-11, max_iter: int = 200):
+    """Primal-dual interior point (Mehrotra predictor-corrector) for
+    min 0.5 y^T P y + q^T y  s.t.  A y = b,  Gin y <= hin, with the KKT
+    system factorised by SuperLU.  Returns (y, nu, z, iterations) with z >= 0
+    the multipliers of the inequalities."""
+    P, A, Gin = sp.csc_matrix(P), sp.csc_matrix(A), sp.csr_matrix(Gin)
+    nf = P.shape[0]
+    mi, me = Gin.shape[0], A.shape[0]
     y = np.zeros(nf)
     s = np.maximum(hin - Gin @ y, 1.0)
     z = np.ones(mi)
     nu = np.zeros(me)
-    GT, AT = Gin.T.tocsr(), Af.T.tocsr()
-    scale = 1.0 + max(np.abs(qf).max(initial=0), np.abs(bf).max(initial=0), np.abs(hin).max(initial=0))
+    GT, AT = Gin.T.tocsr(), A.T.tocsr()
+    scale = 1.0 + max(np.abs(q).max(initial=0), np.abs(b).max(initial=0), np.abs(hin).max(initial=0))
     it = 0
     for it in range(1, max_iter + 1):
-        rd = Pf @ y + qf + AT @ nu + GT @ z
-        rp = Af @ y - bf
+        rd = P @ y + q + AT @ nu + GT @ z
+        rp = A @ y - b
         ri = Gin @ y + s - hin
         mu_c = s @ z / mi
         if (np.abs(rd).max() <= tol * scale and np.abs(rp).max(initial=0) <= tol * scale
                 and np.abs(ri).max() <= tol * scale and mu_c <= 1e-3 * tol * scale):
             break
         D = z / s
-        H = (Pf + GT @ sp.diags(D) @ Gin + 1e-13 * sp.identity(nf)).tocsc()
-        K = sp.bmat([[H, AT], [Af, -1e-13 * sp.identity(me)]], format="csc")
+        H = (P + GT @ sp.diags(D) @ Gin + 1e-13 * sp.identity(nf)).tocsc()
+        K = sp.bmat([[H, AT], [A, -1e-13 * sp.identity(me)]], format="csc")
         lu = spla.splu(K)
 
         def newton(rc):
@@ -174,6 +165,25 @@ def solve(grid, qp, tol: float = 1e-11, max_iter: int = 200) -> DirectSolution:
         nu += a * dnu
         s += a * ds
         z += a * dz
+    return y, nu, z, it
+
+
+def solve(grid, qp, tol: float = 1e-11, max_iter: int = 200) -> DirectSolution:
+    m = assemble(grid, qp)
+    n = m.P.shape[0]
+    fixed = m.lo >= m.hi
+    free = np.nonzero(~fixed)[0]
+    yfix = np.where(fixed, m.hi, 0.0)
+    # reduced problem in the free variables
+    Pf = m.P[free][:, free].tocsc()
+    qf = m.q[free] + (m.P @ yfix)[free]
+    Af = m.A[:, free].tocsc()
+    bf = m.b - m.A @ yfix
+    nf = free.size
+    I = sp.identity(nf, format="csr")
+    Gin = sp.vstack([m.Gl[:, free], I, -I]).tocsr()
+    hin = np.concatenate([m.hl - m.Gl @ yfix, m.hi[free], -m.lo[free]])
+    y, nu, z, it = ipm(Pf, qf, Af, bf, Gin, hin, tol, max_iter)
     yfull = yfix.copy()
     yfull[free] = y
     nl = m.Gl.shape[0]

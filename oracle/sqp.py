@@ -24,6 +24,13 @@ Readings where the paper is silent (also listed in the design notes):
   block), so the same three terms hold with the projected M;
 * pi and the ADMM multipliers are carried to the next iteration (warm
   start); pi is replaced only on acceptance;
+* second-order correction (``soc``): a rejected step with pred > 0 gets a
+  second QP whose linearised (opfc11-14) carry the step's second-order
+  error e = c(x + d) - c(x) - grad c(x)^T d; it starts from the rejected
+  solve's multipliers, its step is accepted iff its actual reduction is
+  positive (against the first step's pred), and the radius then grows as
+  after any accepted step that reached it.  The next solve starts from the
+  correction solve's multipliers whether or not its step was taken;
 * optional safeguard (``pi_if_converged``, off by default): pi is replaced
   only if the solve also met its stop test (eps > 0).  On a QP without a
   feasible point the ADMM multipliers grow with every sweep; their
@@ -67,6 +74,11 @@ class SqpParams:
     # as future work at the end of Section II-D): re-solve the QP with the
     # second-order error of the step added to the linearised constraints
     soc: bool = False
+    # Algorithm 1 before the loop: a start that violates the linear
+    # constraints (balance, bounds) by more than linfeas_tol is first
+    # projected onto them (eq. linfeas)
+    linfeas: bool = False
+    linfeas_tol: float = 1e-8
     # False: an accepted step always takes the new multiplier estimates
     # (Algorithm 1).  True: only when the ADMM solve met its stop test (a
     # safeguard for QPs without a feasible point; see the module docstring).
@@ -216,6 +228,10 @@ def step_norm(d: Iterate) -> float:
 def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time_fn=None) -> SqpResult:
     """Algorithm 1 with the ADMM QP solver."""
     x = acopf.flat_start(grid) if x0 is None else x0.copy()
+    if params.linfeas:
+        from . import linfeas
+        if linfeas.violation(grid, x) > params.linfeas_tol:
+            x = linfeas.project(grid, x).x
     pi = np.zeros((grid.n_line, 4))
     delta = params.delta0
     rho = admm.Rho.scalar(grid, params.rho)
@@ -254,10 +270,13 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
                 d2, pi2, nup2, nuq2, res2, lg2, ll2 = qp_solve(qp2, lam_g, lam_l)
                 xt2 = x.plus(d2)
                 ared2 = phi0 - acopf.merit(grid, xt2, params.mu_merit)
+                # the next solve starts from the last solve's multipliers and
+                # the residual report uses its bus update, taken or not
+                lam_g, lam_l, nup, nuq = lg2, ll2, nup2, nuq2
             except (RuntimeError, np.linalg.LinAlgError, FloatingPointError):
                 ared2 = -np.inf  # the correction QP has no solution: the step stays rejected
             if ared2 > 0:
-                d, pi_new, nup, nuq, res, lam_g, lam_l = d2, pi2, nup2, nuq2, res2, lg2, ll2
+                d, pi_new, res = d2, pi2, res2
                 xt, ared, accepted, soc_used = xt2, ared2, True, True
         if accepted:
             x = xt

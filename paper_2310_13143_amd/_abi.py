@@ -44,7 +44,8 @@ class Iterate(ctypes.Structure):
 
 class AdmmParams(ctypes.Structure):
     _fields_ = [("max_sweeps", c_int32), ("eps_pri", c_double), ("eps_dual", c_double),
-                ("sweep_mode", c_int32), ("block_size", c_int32), ("max_blocks", c_int32), ("trace", c_int32)]
+                ("sweep_mode", c_int32), ("block_size", c_int32), ("max_blocks", c_int32), ("trace", c_int32),
+                ("balance_every", c_int32), ("balance_mu", c_double), ("balance_tau", c_double)]
 
 
 class AdmmResult(ctypes.Structure):
@@ -60,14 +61,21 @@ class AdmmState(ctypes.Structure):
 class SqpParams(ctypes.Structure):
     _fields_ = [("mu", c_double), ("delta_max", c_double), ("grow_ratio", c_double),
                 ("hessian_mode", c_int32), ("warm_start", c_int32), ("admm", AdmmParams),
-                ("lam_g0", c_void_p), ("lam_l0", c_void_p), ("pi_update", c_int32), ("reserved", c_int32)]
+                ("lam_g0", c_void_p), ("lam_l0", c_void_p), ("pi_update", c_int32), ("soc", c_int32),
+                ("stop", c_int32), ("reserved", c_int32), ("tol_primal", c_double), ("tol_dual", c_double),
+                ("tol_step", c_double), ("delta_min", c_double)]
 
 
 class SqpState(ctypes.Structure):
     _fields_ = [("delta", c_double), ("accepted", c_int32), ("admm_sweeps", c_int32), ("ared", c_double),
                 ("pred", c_double), ("step_inf", c_double), ("objective", c_double), ("merit", c_double),
                 ("admm_r", c_double), ("admm_s", c_double), ("admm_ms", c_double), ("status", c_int32),
-                ("reserved", c_int32)]
+                ("soc_sweeps", c_int32)]
+
+
+class SqpOutcome(ctypes.Structure):
+    _fields_ = [("done", c_int32), ("reason", c_int32), ("iterations", c_int32), ("reserved", c_int32),
+                ("seconds", c_double)]
 
 
 class ResidualsReport(ctypes.Structure):
@@ -77,7 +85,7 @@ class ResidualsReport(ctypes.Structure):
 EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_setup_batch", "acopf_set_delta",
            "acopf_qp_build", "acopf_admm_init", "acopf_admm_solve", "acopf_admm_result_batch",
            "acopf_admm_result_get", "acopf_admm_state_get", "acopf_step", "acopf_sqp_step",
-           "acopf_sqp_step_batch", "acopf_residuals", "acopf_residuals_batch", "acopf_features",
+           "acopf_sqp_step_batch", "acopf_sqp_outcome_batch", "acopf_residuals", "acopf_residuals_batch", "acopf_features",
            "acopf_warm_targets", "acopf_warm_decode", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes",
            "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_gradient_noalloc", "acopf_mlp_adam", "acopf_mlp_feature_stats",
            "acopf_mlp_standardize", "acopf_mlp_fold")
@@ -114,6 +122,7 @@ def load(path: str = LIB_PATH):
     lib.acopf_sqp_step_batch.argtypes = [P(Grid), P(Iterate), P(Iterate), c_void_p, c_void_p, P(SqpParams),
                                          c_void_p, c_void_p, c_void_p]
     lib.acopf_residuals_batch.argtypes = [P(Grid), P(Iterate), c_void_p, c_void_p, c_void_p]
+    lib.acopf_sqp_outcome_batch.argtypes = [P(Grid), c_void_p, c_void_p, c_void_p]
     lib.acopf_qp_build.argtypes = [P(Grid), P(Iterate), c_double, c_int32, c_void_p, c_void_p]
     lib.acopf_admm_init.argtypes = [P(Grid), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.acopf_admm_solve.argtypes = [P(Grid), P(AdmmParams), c_void_p, c_void_p, P(AdmmResult)]

@@ -108,19 +108,42 @@ __device__ void fail_line(const Workspace& w, int l, int status, int* flag) {
 }
 
 // ---------------------------------------------------------------- QP build
+// Setting the radii starts a new SQP run: the device stop state is cleared
+// and the run's start time recorded.
+__device__ void start_run(ScenState* sc, double delta) {
+  sc->delta = delta;
+  sc->sqp_done = 0;
+  sc->sqp_reason = 0;
+  sc->sqp_iters = 0;
+  sc->t_start = wall_clock64();
+  sc->t_done = 0;
+}
+
 __global__ void k_set_delta(Workspace w, double delta) {
-  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].delta = delta;
+  for (int s = gtid(); s < w.n_scen; s += gstride()) start_run(&w.scen[s], delta);
 }
 
 __global__ void k_copy_delta(Workspace w, const double* delta) {
-  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].delta = delta[s];
+  for (int s = gtid(); s < w.n_scen; s += gstride()) start_run(&w.scen[s], delta[s]);
 }
 
-__global__ void k_build_lines(acopf_grid g, acopf_iterate x, int mode, Workspace w) {
-  for (int l = gtid(); l < g.n_line; l += gstride()) {
-    ScenState* sc = &w.scen[w.bus_scen[g.line_from[l]]];
+// soc = 1: only the lines of scenarios taking a second-order correction,
+// with the constraint shift of their trial step (soc_e).
+__global__ void k_build_lines(acopf_grid g, acopf_iterate x, int mode, Workspace w, int soc) {
+  const int L = g.n_line;
+  for (int l = gtid(); l < L; l += gstride()) {
+    const int s = w.bus_scen[g.line_from[l]];
+    if (soc && w.decision[s].soc != 1) continue;
+    ScenState* sc = &w.scen[s];
+    double e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = soc ? w.soc_e[k * L + l] : 0.0;
     bool relaxed = false;
-    if (!build_line(g, x, sc->delta, mode, w, l, &relaxed)) fail_line(w, l, ACOPF_ERR_NUMERIC, &w.sync->numeric_error);
+    // the correction QP has the rejected step's radius (k_decide has already
+    // stored the next one)
+    const double delta = soc ? w.decision[s].delta_in : sc->delta;
+    if (!build_line(g, x, delta, mode, w, l, &relaxed, soc ? e : nullptr))
+      fail_line(w, l, ACOPF_ERR_NUMERIC, &w.sync->numeric_error);
     if (relaxed) atomicAdd(&sc->relaxed, 1);
   }
 }
@@ -178,6 +201,7 @@ __global__ void k_clear_flags(Workspace w) {
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
     w.scen[s].status = 0;
     w.scen[s].relaxed = 0;
+    w.scen[s].skip = 0;
   }
 }
 
@@ -187,6 +211,10 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
   for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
     ScenState* sc = &w.scen[s];
+    if (sc->skip) {  // left out: its results of the last solve stay
+      sc->done = 1;
+      continue;
+    }
     sc->done = sc->status != 0 ? 1 : 0;  // a failed QP is not solved
     sc->sweeps = 0;
     sc->converged = 0;
@@ -198,7 +226,7 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
   if (gtid() == 0) {
     SyncState* sy = w.sync;
     int failed = 0;
-    for (int s = 0; s < w.n_scen; ++s) failed += w.scen[s].status != 0 ? 1 : 0;
+    for (int s = 0; s < w.n_scen; ++s) failed += (w.scen[s].status != 0 || w.scen[s].skip) ? 1 : 0;
     sy->go = 0u;
     sy->done = failed == w.n_scen ? 1 : 0;
     sy->n_done = failed;
@@ -462,6 +490,40 @@ __global__ void k_finish_phase(Workspace w, int max_sweeps, double eps_pri, doub
   }
 }
 
+// Residual balancing after a sweep (one thread per scenario): the factor on
+// the penalties of each running scenario from the norms of its last sweep
+// (recorded by k_finish_phase).
+__global__ void k_rho_balance(Workspace w, double mu, double tau) {
+  for (int s = gtid(); s < w.n_scen; s += gstride()) {
+    ScenState* sc = &w.scen[s];
+    double f = 1.0;
+    if (!sc->done) {
+      if (sc->r_norm > mu * sc->s_norm) f = tau;
+      else if (sc->s_norm > mu * sc->r_norm) f = 1.0 / tau;
+    }
+    sc->rho_factor = f;
+  }
+}
+
+// The factors applied: penalties scaled, lines of those scenarios factored
+// again (P = Q^{-1} and the constant part of the linear term depend on rho).
+__global__ void k_rho_apply(acopf_grid g, Workspace w) {
+  const int L = g.n_line, G = g.n_gen;
+  for (int l = gtid(); l < L; l += gstride()) {
+    const double f = w.scen[w.bus_scen[g.line_from[l]]].rho_factor;
+    if (f == 1.0) continue;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w.rho_l[lc8(l, k)] *= f;
+    if (!prep_line(w, l)) fail_line(w, l, ACOPF_ERR_NONCONVEX_LINE, &w.sync->nonconvex);
+  }
+  for (int k = gtid(); k < G; k += gstride()) {
+    const double f = w.scen[w.bus_scen[g.gen_bus[k]]].rho_factor;
+    if (f == 1.0) continue;
+    w.rho_g[k] *= f;
+    w.rho_g[G + k] *= f;
+  }
+}
+
 // Grid barrier for a cooperative launch (all blocks resident).  Each block
 // publishes its arrival by storing the barrier's epoch to its own flag (no
 // contended read-modify-write); block 0 waits for every flag, runs `last`
@@ -546,16 +608,23 @@ __global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspac
 }
 
 // ---------------------------------------------------------------- step
-__global__ void k_step_lines(acopf_grid g, acopf_iterate x, Workspace w, acopf_iterate d) {
-  for (int l = gtid(); l < g.n_line; l += gstride()) step_line(g, x, w, d, l);
+// soc_only = 1: only the components of scenarios taking a second-order
+// correction (the others keep the step already written).
+__global__ void k_step_lines(acopf_grid g, acopf_iterate x, Workspace w, acopf_iterate d, int soc_only) {
+  for (int l = gtid(); l < g.n_line; l += gstride()) {
+    if (soc_only && w.decision[w.bus_scen[g.line_from[l]]].soc != 1) continue;
+    step_line(g, x, w, d, l);
+  }
 }
 
-__global__ void k_step_nodes(acopf_grid g, Workspace w, acopf_iterate d) {
+__global__ void k_step_nodes(acopf_grid g, Workspace w, acopf_iterate d, int soc_only) {
   for (int i = gtid(); i < g.n_bus; i += gstride()) {
+    if (soc_only && w.decision[w.bus_scen[i]].soc != 1) continue;
     d.w[i] = w.dw[i];
     d.th[i] = w.dth[i];
   }
   for (int k = gtid(); k < g.n_gen; k += gstride()) {
+    if (soc_only && w.decision[w.bus_scen[g.gen_bus[k]]].soc != 1) continue;
     d.pg[k] = w.xg[k];
     d.qg[k] = w.xg[g.n_gen + k];
   }
@@ -584,16 +653,17 @@ __global__ void k_merit_parts(acopf_grid g, acopf_iterate x, Workspace w, acopf_
   for (int i = gtid(); i < g.n_bus; i += gstride()) w.bus_comp[i] = fmax(fabs(d.w[i]), fabs(d.th[i]));
 }
 
-// Acceptance test and trust-radius update of Algorithm 1, one block per
-// scenario (fixed-order sums over the scenario's components).
-__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule) {
-  __shared__ double lds[16];
-  const int s = blockIdx.x, L = w.n_line, G = w.n_gen;
+// Fixed-order sums of scenario s's merit pieces (one block): a = (f at x,
+// f at x + d, generator model terms, h at x, h at x + d, m(d), line model
+// terms); smax = ||d||_inf over (pg, qg, w, th).
+__device__ void merit_sums(const Workspace& w, int s, double a[7], double& smax, double* lds) {
+  const int L = w.n_line, G = w.n_gen;
   const int l0 = w.scen_line_off[s], l1 = w.scen_line_off[s + 1];
   const int g0 = w.scen_gen_off[s], g1 = w.scen_gen_off[s + 1];
   const int b0 = w.scen_bus_off[s], b1 = w.scen_bus_off[s + 1];
-  double a[7] = {0, 0, 0, 0, 0, 0, 0};
-  double smax = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) a[k] = 0.0;
+  smax = 0.0;
   for (int l = l0 + (int)threadIdx.x; l < l1; l += blockDim.x) {
     a[3] += w.line_comp[l];
     a[4] += w.line_comp[L + l];
@@ -610,9 +680,32 @@ __global__ void k_decide(Workspace w, double mu, double delta_max, double grow, 
 #pragma unroll
   for (int k = 0; k < 7; ++k) a[k] = block_sum(a[k], lds);
   smax = block_max(smax, lds);
+}
+
+// Acceptance test and trust-radius update of Algorithm 1, one block per
+// scenario (fixed-order sums over the scenario's components).  soc = 1: a
+// rejected step with pred > 0 of a scenario whose QP was solved is marked
+// for a second-order correction (decided by k_soc_decide).
+__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule, int soc) {
+  __shared__ double lds[16];
+  const int s = blockIdx.x;
+  double a[7], smax;
+  merit_sums(w, s, a, smax, lds);
   if (threadIdx.x == 0) {
     SqpDecision* dc = &w.decision[s];
     const double delta = w.scen[s].delta;
+    if (w.scen[s].sqp_done) {  // a stopped run: nothing changes
+      dc->ared = 0.0;
+      dc->pred = 0.0;
+      dc->step_inf = 0.0;
+      dc->delta_in = delta;
+      dc->delta_out = delta;
+      dc->accepted = 0;
+      dc->update_pi = 0;
+      dc->soc = 0;
+      dc->soc_sweeps = 0;
+      return;
+    }
     dc->f_x = a[0];
     dc->f_xd = a[1];
     dc->h_x = a[3];
@@ -638,31 +731,158 @@ __global__ void k_decide(Workspace w, double mu, double delta_max, double grow, 
     dc->delta_out = dn;
     dc->accepted = ok ? 1 : 0;
     dc->update_pi = (ok && (pi_rule == ACOPF_PI_ALWAYS || w.scen[s].converged)) ? 1 : 0;
+    dc->soc = (soc && !ok && !failed && pred > 0.0) ? 1 : 0;
+    dc->soc_sweeps = 0;
     w.scen[s].delta = dn;
   }
 }
 
-// x <- x + d and pi <- new estimates in every scenario whose step was accepted.
-__global__ void k_apply(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspace w) {
+// Start of the second-order correction pass: scenarios not taking it are
+// left out of the next solve; each line of a scenario taking it gets the
+// second-order error of its rejected trial step d.
+__global__ void k_soc_begin(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspace w) {
+  const int L = g.n_line;
+  for (int s = gtid(); s < w.n_scen; s += gstride()) {
+    const bool on = w.decision[s].soc == 1;
+    w.scen[s].skip = on ? 0 : 1;
+    if (on) w.scen[s].relaxed = 0;
+  }
+  for (int l = gtid(); l < L; l += gstride()) {
+    if (w.decision[w.bus_scen[g.line_from[l]]].soc != 1) continue;
+    double e[4];
+    soc_error_line(g, x, d, l, e);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w.soc_e[k * L + l] = e[k];
+  }
+}
+
+// ADMM start of the correction solve, for the scenarios taking it only: the
+// multipliers of the rejected step's solve are kept, primal values and bus
+// values start at zero, line matrices and linear terms are factored again.
+__global__ void k_soc_init(acopf_grid g, Workspace w) {
+  const int L = g.n_line, G = g.n_gen, B = g.n_bus;
+  for (int l = gtid(); l < L; l += gstride()) {
+    if (w.decision[w.bus_scen[g.line_from[l]]].soc != 1) continue;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w.xl[lc8(l, k)] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w.xbar_f[lc4(l, k)] = 0.0;
+      w.xbar_v[lc4(l, k)] = 0.0;
+    }
+    w.mu[l] = 0.0;
+    w.mu[L + l] = 0.0;
+    w.line_mask[l] = 0;
+    if (!prep_line(w, l)) fail_line(w, l, ACOPF_ERR_NONCONVEX_LINE, &w.sync->nonconvex);
+  }
+  for (int k = gtid(); k < G; k += gstride()) {
+    if (w.decision[w.bus_scen[g.gen_bus[k]]].soc != 1) continue;
+    w.xg[k] = 0.0;
+    w.xg[G + k] = 0.0;
+    w.xbar_g[k] = 0.0;
+    w.xbar_g[G + k] = 0.0;
+  }
+  for (int i = gtid(); i < B; i += gstride()) {
+    if (w.decision[w.bus_scen[i]].soc != 1) continue;
+    w.dw[i] = 0.0;
+    w.dth[i] = 0.0;
+    w.nu[i] = 0.0;
+    w.nu[B + i] = 0.0;
+  }
+}
+
+// Decision on the corrected step of each scenario that took the correction
+// (one block per scenario): accepted iff its actual merit reduction is
+// positive, judged against the first step's model (pred of k_decide); the
+// radius grows as after an accepted step that reached it.  Clears the
+// left-out marks of every scenario.
+__global__ void k_soc_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule) {
+  __shared__ double lds[16];
+  const int s = blockIdx.x;
+  SqpDecision* dc = &w.decision[s];
+  if (dc->soc != 1) {
+    if (threadIdx.x == 0) w.scen[s].skip = 0;
+    return;
+  }
+  double a[7], smax;
+  merit_sums(w, s, a, smax, lds);
+  if (threadIdx.x == 0) {
+    ScenState* sc = &w.scen[s];
+    dc->soc_sweeps = sc->sweeps;
+    const double ared = (dc->f_x + mu * dc->h_x) - (a[1] + mu * a[4]);
+    if (sc->status == 0 && ared > 0.0) {
+      dc->soc = 2;
+      dc->accepted = 1;
+      dc->ared = ared;
+      dc->f_xd = a[1];
+      dc->h_xd = a[4];
+      double dn = dc->delta_in;
+      if (dc->step_inf >= 0.99 * dc->delta_in && ared >= grow * dc->pred) dn = fmin(2.0 * dc->delta_in, delta_max);
+      dc->delta_out = dn;
+      dc->update_pi = (pi_rule == ACOPF_PI_ALWAYS || sc->converged) ? 1 : 0;
+      sc->delta = dn;
+    }
+    sc->skip = 0;
+  }
+}
+
+// x <- x + d and pi <- new estimates in every scenario whose step was
+// accepted: phase 0 after the first decision, phase 1 the corrected steps.
+__device__ __forceinline__ bool apply_now(const SqpDecision& dc, int phase) {
+  return phase == 0 ? dc.accepted != 0 : dc.soc == 2;
+}
+
+__global__ void k_apply(acopf_grid g, acopf_iterate x, acopf_iterate d, Workspace w, int phase) {
   const int L = g.n_line;
   for (int k = gtid(); k < g.n_gen; k += gstride()) {
-    if (!w.decision[w.bus_scen[g.gen_bus[k]]].accepted) continue;
+    if (!apply_now(w.decision[w.bus_scen[g.gen_bus[k]]], phase)) continue;
     x.pg[k] += d.pg[k];
     x.qg[k] += d.qg[k];
   }
   for (int i = gtid(); i < g.n_bus; i += gstride()) {
-    if (!w.decision[w.bus_scen[i]].accepted) continue;
+    if (!apply_now(w.decision[w.bus_scen[i]], phase)) continue;
     x.w[i] += d.w[i];
     x.th[i] += d.th[i];
   }
   for (int l = gtid(); l < L; l += gstride()) {
     const SqpDecision& dc = w.decision[w.bus_scen[g.line_from[l]]];
-    if (!dc.accepted) continue;
+    if (!apply_now(dc, phase)) continue;
     x.wR[l] += d.wR[l];
     x.wI[l] += d.wI[l];
     if (!dc.update_pi) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) x.pi[k * L + l] = d.pi[k * L + l];
+  }
+}
+
+// Start of an SQP iteration with device stops: stopped runs are left out
+// of the iteration's solves.
+__global__ void k_sqp_begin(Workspace w) {
+  for (int s = gtid(); s < w.n_scen; s += gstride()) w.scen[s].skip = w.scen[s].sqp_done ? 1 : 0;
+}
+
+// End of an SQP iteration with device stops (one thread per scenario): the
+// stop rule on the residual report of the new iterate (k_residual_reduce)
+// and the iteration's decision; clears the left-out marks.
+__global__ void k_sqp_stop(Workspace w, double tol_primal, double tol_dual, double tol_step, double delta_min) {
+  for (int s = gtid(); s < w.n_scen; s += gstride()) {
+    ScenState* sc = &w.scen[s];
+    sc->skip = 0;
+    if (sc->sqp_done) continue;
+    sc->sqp_iters += 1;
+    const ResidualReport& r = w.report[s];
+    const double primal = fmax(fmax(fmax(r.balance, r.c11), fmax(r.c12, r.limit)), r.bounds);
+    const double dual = r.dual / fmax(1.0, r.gradf);
+    const SqpDecision& dc = w.decision[s];
+    int reason = 0;
+    if (dc.accepted && primal <= tol_primal && dual <= tol_dual) reason = 1;
+    else if (dc.accepted && dc.step_inf < tol_step) reason = 2;
+    else if (sc->delta < delta_min) reason = 3;
+    if (reason) {
+      sc->sqp_done = 1;
+      sc->sqp_reason = reason;
+      sc->t_done = wall_clock64();
+    }
   }
 }
 
@@ -1202,7 +1422,7 @@ acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double 
   const int bs = kDefaultBlock;
   if (delta > 0.0) hipLaunchKernelGGL(k_set_delta, dim3(blocks_for(w.n_scen, bs)), dim3(bs), 0, s, w, delta);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w);
-  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, (int)mode, w);
+  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, (int)mode, w, 0);
   if (g->n_gen > 0) hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w);
   hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
   HIP_TRY(hipGetLastError());
@@ -1235,6 +1455,13 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   if (p->trace != 0 && p->trace != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: trace must be 0 or 1");
   if (p->trace && p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
     return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: traced solves run in the launch-per-phase modes");
+  const bool balance = p->balance_every > 0;
+  if (p->balance_every < 0 || p->balance_every % kSweepChunk != 0)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: balance_every must be 0 or a positive multiple of 64");
+  if (balance && !(p->balance_mu >= 1.0 && p->balance_tau > 1.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: residual balancing needs balance_mu >= 1 and balance_tau > 1");
+  if (balance && p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
+    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: residual balancing runs in the launch-per-phase modes");
   if (p->trace) {
     const int bz = kDefaultBlock;
     const long long G2 = 2LL * g->n_gen, L8 = 8LL * g->n_line;
@@ -1266,12 +1493,12 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.max_sweeps = p->max_sweeps;
     a.eps_pri = p->eps_pri;
     a.eps_dual = p->eps_dual;
-    bool use_graph = p->sweep_mode == ACOPF_SWEEP_GRAPH;
-    if (use_graph) {  // a stream under capture records plain launches instead
-      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-      HIP_TRY(hipStreamIsCapturing(s, &cap));
-      use_graph = cap == hipStreamCaptureStatusNone;
-    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    // a stream under capture records plain launches, and every chunk up to
+    // the cap (the stop test then acts on the device only)
+    const bool use_graph = p->sweep_mode == ACOPF_SWEEP_GRAPH && !capturing;
     hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs, 1);
     for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
       const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
@@ -1284,8 +1511,14 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
         HIP_TRY(hipGraphLaunch(ge, s));
       else
         enqueue_sweeps(a, k1 - k0, s);
+      if (balance && k1 % p->balance_every == 0 && k1 < p->max_sweeps) {
+        hipLaunchKernelGGL(k_rho_balance, dim3(blocks_for(ns, 64)), dim3(64), 0, s, w, p->balance_mu,
+                           p->balance_tau);
+        hipLaunchKernelGGL(k_rho_apply, dim3(blocks_for(std::max(g->n_line, g->n_gen), 256)), dim3(256), 0, s, *g,
+                           w);
+      }
       HIP_TRY(hipGetLastError());
-      if (k1 < p->max_sweeps && (p->eps_pri > 0.0 || p->eps_dual > 0.0)) {
+      if (k1 < p->max_sweeps && (p->eps_pri > 0.0 || p->eps_dual > 0.0) && !capturing) {
         // look at the stop flag before enqueueing more sweeps
         SyncState st;
         acopf_status rc = read_sync(w, s, &st);
@@ -1404,8 +1637,8 @@ acopf_status acopf_step(const acopf_grid* g, const acopf_iterate* x, void* works
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
   const int bs = kDefaultBlock;
-  hipLaunchKernelGGL(k_step_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, w, *d);
-  hipLaunchKernelGGL(k_step_nodes, dim3(blocks_for(std::max(g->n_bus, g->n_gen), bs)), dim3(bs), 0, s, *g, w, *d);
+  hipLaunchKernelGGL(k_step_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, w, *d, 0);
+  hipLaunchKernelGGL(k_step_nodes, dim3(blocks_for(std::max(g->n_bus, g->n_gen), bs)), dim3(bs), 0, s, *g, w, *d, 0);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -1425,11 +1658,11 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   if (capturing && states)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step_batch: host results need a synchronisation; pass states = NULL "
                                        "while the stream is being captured");
-  if (capturing && (p->admm.eps_pri > 0.0 || p->admm.eps_dual > 0.0) && p->admm.sweep_mode != ACOPF_SWEEP_PERSISTENT)
-    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step_batch: under capture the sweeps cannot poll the stop flag; "
-                                       "use eps = 0 (a fixed sweep count)");
+  if (p->stop && !(p->tol_primal >= 0.0 && p->tol_dual >= 0.0 && p->tol_step >= 0.0 && p->delta_min >= 0.0))
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: stop tolerances must be >= 0");
   acopf_status rc = acopf_qp_build(g, x, 0.0, p->hessian_mode, workspace, stream);
   if (rc != ACOPF_OK) return rc;
+  if (p->stop) hipLaunchKernelGGL(k_sqp_begin, dim3(blocks_for(w.n_scen, 64)), dim3(64), 0, s, w);
   if (p->pi_update != ACOPF_PI_ALWAYS && p->pi_update != ACOPF_PI_IF_CONVERGED)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown multiplier update rule");
   if (p->warm_start < ACOPF_START_ZERO || p->warm_start > ACOPF_START_GIVEN)
@@ -1458,15 +1691,62 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
   hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
   hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
-                     (int)p->pi_update);
-  hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w);
+                     (int)p->pi_update, p->soc ? 1 : 0);
+  hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w, 0);
   HIP_TRY(hipGetLastError());
+  std::vector<acopf_admm_result> ar(w.n_scen);
+  bool have_ar = false;
+  if (p->soc) {
+    // second-order correction of the rejected steps (end of Section II-D):
+    // under capture the pass is always recorded (scenarios without a
+    // rejected step are left out of it); otherwise it runs only when a
+    // scenario asks for it
+    bool run = true;
+    if (!capturing) {
+      std::vector<SqpDecision> d0(w.n_scen);
+      HIP_TRY(hipMemcpyAsync(d0.data(), w.decision, w.n_scen * sizeof(SqpDecision), hipMemcpyDeviceToHost, s));
+      rc = acopf_admm_result_batch(g, workspace, stream, ar.data());  // synchronises
+      if (rc != ACOPF_OK) return rc;
+      have_ar = true;
+      run = false;
+      for (int k = 0; k < w.n_scen; ++k) run = run || d0[k].soc == 1;
+    }
+    if (run) {
+      const int nl = blocks_for(g->n_line, bs);
+      hipLaunchKernelGGL(k_soc_begin, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w);
+      hipLaunchKernelGGL(k_build_lines, dim3(nl), dim3(bs), 0, s, *g, *x, (int)p->hessian_mode, w, 1);
+      hipLaunchKernelGGL(k_soc_init, dim3(nb), dim3(bs), 0, s, *g, w);
+      HIP_TRY(hipGetLastError());
+      acopf_admm_params a2 = p->admm;
+      a2.trace = 0;  // traces describe the first solve
+      rc = acopf_admm_solve(g, &a2, workspace, stream, nullptr);
+      if (rc != ACOPF_OK) return rc;
+      hipLaunchKernelGGL(k_step_lines, dim3(nl), dim3(bs), 0, s, *g, *x, w, *d, 1);
+      hipLaunchKernelGGL(k_step_nodes, dim3(blocks_for(std::max(g->n_bus, g->n_gen), bs)), dim3(bs), 0, s, *g, w, *d,
+                         1);
+      hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
+      hipLaunchKernelGGL(k_soc_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
+                         (int)p->pi_update);
+      hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w, 1);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  if (p->stop) {
+    hipLaunchKernelGGL(k_residual_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w);
+    hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_sqp_stop, dim3(blocks_for(w.n_scen, 64)), dim3(64), 0, s, w, p->tol_primal, p->tol_dual,
+                       p->tol_step, p->delta_min);
+    HIP_TRY(hipGetLastError());
+  }
   if (!states) return ACOPF_OK;
   std::vector<SqpDecision> dc(w.n_scen);
   HIP_TRY(hipMemcpyAsync(dc.data(), w.decision, w.n_scen * sizeof(SqpDecision), hipMemcpyDeviceToHost, s));
-  std::vector<acopf_admm_result> ar(w.n_scen);
-  rc = acopf_admm_result_batch(g, workspace, stream, ar.data());
-  if (rc != ACOPF_OK) return rc;
+  if (!have_ar) {
+    rc = acopf_admm_result_batch(g, workspace, stream, ar.data());
+    if (rc != ACOPF_OK) return rc;
+  } else {
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
   for (int k = 0; k < w.n_scen; ++k) {
@@ -1483,6 +1763,7 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
     st->admm_s = ar[k].s_norm;
     st->admm_ms = ms;
     st->status = ar[k].status;
+    st->soc_sweeps = dc[k].soc_sweeps;
   }
   return ACOPF_OK;
 }
@@ -1498,6 +1779,27 @@ acopf_status acopf_sqp_step(const acopf_grid* g, const acopf_iterate* x, const a
   hipLaunchKernelGGL(k_set_delta, dim3(1), dim3(64), 0, s, w, state->delta);
   HIP_TRY(hipGetLastError());
   return acopf_sqp_step_batch(g, x, d, rho_g, rho_l, p, workspace, stream, state);
+}
+
+acopf_status acopf_sqp_outcome_batch(const acopf_grid* g, void* workspace, void* stream, acopf_sqp_outcome* out) {
+  if (!grid_ok(g) || !workspace || !out) return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_outcome_batch: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  std::vector<ScenState> sc(w.n_scen);
+  HIP_TRY(hipMemcpyAsync(sc.data(), w.scen, w.n_scen * sizeof(ScenState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int dev = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(ACOPF_ERR_HIP, "acopf_sqp_outcome_batch: no device wall-clock rate");
+  for (int k = 0; k < w.n_scen; ++k) {
+    out[k].done = sc[k].sqp_done;
+    out[k].reason = sc[k].sqp_reason;
+    out[k].iterations = sc[k].sqp_iters;
+    out[k].reserved = 0;
+    out[k].seconds = sc[k].sqp_done ? (double)(sc[k].t_done - sc[k].t_start) / (1e3 * (double)khz) : 0.0;
+  }
+  return ACOPF_OK;
 }
 
 acopf_status acopf_residuals_batch(const acopf_grid* g, const acopf_iterate* x, void* workspace, void* stream,

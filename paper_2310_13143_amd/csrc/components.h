@@ -55,8 +55,10 @@ ACOPF_HD double limit_relaxation(const double lo[4], const double hi[4], const d
 // QP data of line l at the iterate (Sections III-B, III-C and IV-B2).
 // Returns false if the elimination pivot wR cos + wI sin vanishes or the
 // data are not finite.  *relaxed (optional): the limit rows were relaxed.
+// cshift (optional, 4 values): added to c11..c14 of (opfc11-14) at x in
+// their linearisations (the QP of a second-order correction).
 ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double delta, int mode,
-                         const Workspace& w, int l, bool* relaxed = nullptr) {
+                         const Workspace& w, int l, bool* relaxed = nullptr, const double* cshift = nullptr) {
   const int L = g.n_line;
   const int f = g.line_from[l], t = g.line_to[l];
   const double wi = x.w[f], wj = x.w[t], thi = x.th[f], thj = x.th[t];
@@ -68,8 +70,12 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
   const double s = sin(ph), c = cos(ph);
   // elimination (eq. elim): linearised opfc11, opfc12 solved for d_wR, d_wI
   const double K = wR * c + wI * s;
-  const double r1 = wi * wj - wR * wR - wI * wI;
-  const double r2 = -wR * s + wI * c;
+  double r1 = wi * wj - wR * wR - wI * wI;  // -c11
+  double r2 = -wR * s + wI * c;             // -c12
+  if (cshift) {
+    r1 -= cshift[0];
+    r2 -= cshift[1];
+  }
   bool ok = fabs(K) >= 1e-8;
   const double K2 = 2.0 * (ok ? K : 1.0);
   const double aR[4] = {c * wj / K2, -wI, c * wi / K2, wI};
@@ -198,6 +204,10 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
   const double sij = g.smax_ij[l], sji = g.smax_ji[l];
   double hr[2] = {sij * sij - pij * pij - qij * qij - 2.0 * pij * f0[0] - 2.0 * qij * f0[1],
                   sji * sji - pji * pji - qji * qji - 2.0 * pji * f0[2] - 2.0 * qji * f0[3]};
+  if (cshift) {  // c13 + e13 - 2 p_ij dp_ij - 2 q_ij dq_ij >= 0  <=>  G z <= h + e13
+    hr[0] += cshift[2];
+    hr[1] += cshift[3];
+  }
   const double shift = limit_relaxation(lo, hi, Gr, hr);
   const double hr0 = hr[0] + shift, hr1 = hr[1] + shift;
   if (relaxed) *relaxed = shift > 0.0;
@@ -922,6 +932,45 @@ ACOPF_HD void merit_line(const acopf_grid& g, const acopf_iterate& x, const Work
   out[1] = hv[1];
   out[2] = fabs(l11) + fabs(l12) + fmax(0.0, -l13) + fmax(0.0, -l14);
   out[3] = quad;
+}
+
+// Second-order error of the trial step d at line l: e = c(x + d) - c(x) -
+// grad c(x)^T d for (opfc11-14), the shift of the correction QP.
+ACOPF_HD void soc_error_line(const acopf_grid& g, const acopf_iterate& x, const acopf_iterate& d, int l,
+                             double e[4]) {
+  const int f = g.line_from[l], t = g.line_to[l];
+  const double gii = g.gii[l], bii = g.bii[l], gij = g.gij[l], bij = g.bij[l];
+  const double gji = g.gji[l], bji = g.bji[l], gjj = g.gjj[l], bjj = g.bjj[l];
+  const double s2ij = g.smax_ij[l] * g.smax_ij[l], s2ji = g.smax_ji[l] * g.smax_ji[l];
+  double cn[4];
+  {
+    const double wi = x.w[f] + d.w[f], wj = x.w[t] + d.w[t];
+    const double wR = x.wR[l] + d.wR[l], wI = x.wI[l] + d.wI[l];
+    const double ph = (x.th[f] + d.th[f]) - (x.th[t] + d.th[t]);
+    const double pij = gii * wi + gij * wR + bij * wI, qij = -bii * wi - bij * wR + gij * wI;
+    const double pji = gjj * wj + gji * wR - bji * wI, qji = -bjj * wj - bji * wR - gji * wI;
+    cn[0] = wR * wR + wI * wI - wi * wj;
+    cn[1] = wR * sin(ph) - wI * cos(ph);
+    cn[2] = s2ij - pij * pij - qij * qij;
+    cn[3] = s2ji - pji * pji - qji * qji;
+  }
+  const double wi = x.w[f], wj = x.w[t], wR = x.wR[l], wI = x.wI[l];
+  const double ph = x.th[f] - x.th[t];
+  const double s = sin(ph), c = cos(ph);
+  const double K = wR * c + wI * s;
+  const double pij = gii * wi + gij * wR + bij * wI, qij = -bii * wi - bij * wR + gij * wI;
+  const double pji = gjj * wj + gji * wR - bji * wI, qji = -bjj * wj - bji * wR - gji * wI;
+  const double dwi = d.w[f], dwj = d.w[t], dR = d.wR[l], dI = d.wI[l];
+  const double l11 = wR * wR + wI * wI - wi * wj + 2.0 * wR * dR + 2.0 * wI * dI - wj * dwi - wi * dwj;
+  const double l12 = wR * s - wI * c + s * dR - c * dI + K * (d.th[f] - d.th[t]);
+  const double dpij = gii * dwi + gij * dR + bij * dI, dqij = -bii * dwi - bij * dR + gij * dI;
+  const double dpji = gjj * dwj + gji * dR - bji * dI, dqji = -bjj * dwj - bji * dR - gji * dI;
+  const double l13 = s2ij - pij * pij - qij * qij - 2.0 * pij * dpij - 2.0 * qij * dqij;
+  const double l14 = s2ji - pji * pji - qji * qji - 2.0 * pji * dpji - 2.0 * qji * dqji;
+  e[0] = cn[0] - l11;
+  e[1] = cn[1] - l12;
+  e[2] = cn[2] - l13;
+  e[3] = cn[3] - l14;
 }
 
 // Objective pieces of generator k: f(p), f(p + d), model f'(p) d + 0.5 f'' d^2.

@@ -59,9 +59,16 @@ struct ScenState {
   int infeasible[2];       // infeasible line subproblems, by sweep parity
   int status;              // 0, or the acopf_status of a failed QP build / factorisation
   int relaxed;             // lines whose limit rows the last QP build relaxed
-  int pad;
+  int skip;                // left out of the next solve (a second-order correction pass of other scenarios)
   double r_norm, s_norm;   // residual norms of the last sweep
   double delta;            // trust radius of the current SQP iteration
+  double rho_factor;       // residual balancing: factor on the penalties decided after the last sweep
+  int sqp_done;            // the SQP run of this scenario has stopped (its iterate is frozen)
+  int sqp_reason;          // why: 1 primal and dual infeasibility met, 2 small accepted step, 3 radius collapse
+  int sqp_iters;           // SQP iterations taken since the radius was set
+  int pad2;
+  long long t_start;       // device wall clock when the radius was set (start of the run)
+  long long t_done;        // device wall clock when the run stopped
 };
 
 // Outcome of one trust-region SQP step (Algorithm 1), decided on the device.
@@ -71,6 +78,8 @@ struct SqpDecision {
   double delta_in, delta_out;
   int accepted;
   int update_pi;           // accepted and the multiplier rule allows the new estimates
+  int soc;                 // second-order correction: 0 none, 1 tried (step rejected), 2 taken
+  int soc_sweeps;          // sweeps of the correction's ADMM solve
 };
 
 // Residual report (maxima; order independent).
@@ -119,6 +128,7 @@ struct Workspace {
   double *mu;                            // [2][n_line]
   int32_t* line_mask;                    // [n_line] optimal working set of the last line solve
   double *lam0_g, *lam0_l;               // [2][n_gen], [n_line][8] multipliers the last solve started from
+  double* soc_e;                         // [4][n_line] second-order error of the trial step (correction QP)
   // per-coupling sums of |r_c| and |s_c| over the sweeps of a traced solve
   double *tr_r_g, *tr_s_g;               // [2][n_gen]
   double *tr_r_l, *tr_s_l;               // [8][n_line]
@@ -216,6 +226,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.line_mask = (int32_t*)take((size_t)nl * I);
   t.lam0_g = (double*)take((size_t)2 * ng * D);
   t.lam0_l = (double*)take((size_t)8 * nl * D);
+  t.soc_e = (double*)take((size_t)4 * nl * D);
   t.tr_r_g = (double*)take((size_t)2 * ng * D);
   t.tr_s_g = (double*)take((size_t)2 * ng * D);
   t.tr_r_l = (double*)take((size_t)8 * nl * D);

@@ -41,6 +41,14 @@ def _pack(grids):
     return arrays, (nb.astype(np.int32), nl.astype(np.int32), ng.astype(np.int32), refs)
 
 
+def _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance) -> AdmmParams:
+    p = AdmmParams(int(max_sweeps), float(eps_pri), float(eps_dual), int(sweep_mode), int(block_size),
+                   int(max_blocks), int(bool(trace)))
+    if balance is not None:
+        p.balance_every, p.balance_mu, p.balance_tau = int(balance[0]), float(balance[1]), float(balance[2])
+    return p
+
+
 class DeviceGrid:
     """The network arrays of a grid, or of a batch of independent scenario
     grids packed one after another (pass a list), resident on one device,
@@ -129,9 +137,9 @@ class DeviceGrid:
 
     def admm_solve(self, max_sweeps: int, eps_pri: float = 0.0, eps_dual: float = 0.0,
                    sweep_mode: int = _abi.SWEEP_PERSISTENT, block_size: int = 0, max_blocks: int = 0,
-                   sync: bool = True, trace: bool = False):
-        p = AdmmParams(int(max_sweeps), float(eps_pri), float(eps_dual), int(sweep_mode), int(block_size),
-                       int(max_blocks), int(bool(trace)))
+                   sync: bool = True, trace: bool = False, balance=None):
+        """balance = (every, mu, tau): residual balancing of the penalties."""
+        p = _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance)
         res = AdmmResult()
         check(self.lib.acopf_admm_solve(ctypes.byref(self.cgrid), ctypes.byref(p), self.ws, self.stream,
                                         ctypes.byref(res) if sync else None))
@@ -181,10 +189,15 @@ class DeviceGrid:
                                   self.stream))
         return d
 
-    def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam, pi_update):
+    def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam, pi_update,
+                    soc=False, stop=None):
         start = int(warm_start) if not isinstance(warm_start, bool) else int(warm_start)
         p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), start, admm)
         p.pi_update = int(pi_update)
+        p.soc = int(bool(soc))
+        if stop is not None:
+            p.stop = 1
+            p.tol_primal, p.tol_dual, p.tol_step, p.delta_min = (float(v) for v in stop)
         if start == _abi.START_GIVEN:
             if lam is None:
                 raise ValueError("warm_start=START_GIVEN needs lam=(lam_g, lam_l)")
@@ -197,19 +210,21 @@ class DeviceGrid:
                  grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                  max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
                  block_size: int = 0, max_blocks: int = 0, d: dict | None = None, lam=None,
-                 trace: bool = False, pi_update: int = _abi.PI_ALWAYS) -> dict:
+                 trace: bool = False, pi_update: int = _abi.PI_ALWAYS, soc: bool = False,
+                 balance=None) -> dict:
         """One trust-region SQP iteration on the device; x is updated in place
         when the step is accepted.  warm_start: False/True (zero / previous
         multipliers) or one of _abi.START_*; lam = (lam_g, lam_l) for
-        START_GIVEN.  Returns the host-side decision record."""
+        START_GIVEN; soc: second-order correction of a rejected step.
+        Returns the host-side decision record."""
         if d is None:
             d = self.empty_iterate()
         self._d = d
         f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
-                             AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode), int(block_size),
-                                        int(max_blocks), int(bool(trace))), lam, pi_update)
+                             _admm_params(max_sweeps, eps, eps, sweep_mode, block_size, max_blocks, trace, balance),
+                             lam, pi_update, soc)
         st = SqpState()
         st.delta = float(delta)
         cx, cd = self.c_iterate(x), self.c_iterate(d)
@@ -222,17 +237,19 @@ class DeviceGrid:
                        grow_ratio: float = 0.75, hessian_mode: int = _abi.HESSIAN_PSD, warm_start=False,
                        max_sweeps: int = 20000, eps: float = 1e-4, block_size: int = 0, d: dict | None = None,
                        sync: bool = True, lam=None, trace: bool = False, pi_update: int = _abi.PI_ALWAYS,
-                       sweep_mode: int = _abi.SWEEP_LAUNCHES):
+                       sweep_mode: int = _abi.SWEEP_LAUNCHES, soc: bool = False, balance=None, stop=None):
         """One SQP iteration for every scenario of the batch (radii held on
-        the device, see set_delta); per-scenario decisions if sync."""
+        the device, see set_delta); per-scenario decisions if sync.  stop =
+        (tol_primal, tol_dual, tol_step, delta_min): device-side stop of each
+        scenario's run (see sqp_outcomes)."""
         if d is None:
             d = self.empty_iterate()
         self._d = d
         f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
-                             AdmmParams(int(max_sweeps), float(eps), float(eps), int(sweep_mode),
-                                        int(block_size), 0, int(bool(trace))), lam, pi_update)
+                             _admm_params(max_sweeps, eps, eps, sweep_mode, block_size, 0, trace, balance),
+                             lam, pi_update, soc, stop)
         sts = (SqpState * self.n_scen)() if sync else None
         cx, cd = self.c_iterate(x), self.c_iterate(d)
         check(self.lib.acopf_sqp_step_batch(ctypes.byref(self.cgrid), ctypes.byref(cx), ctypes.byref(cd),
@@ -241,6 +258,13 @@ class DeviceGrid:
         if not sync:
             return None
         return [{k: getattr(st, k) for k, _ in SqpState._fields_} for st in sts]
+
+    def sqp_outcomes(self) -> list:
+        """Per-scenario state of device-stopped runs (done, reason,
+        iterations, seconds from set_delta to the stop)."""
+        out = (_abi.SqpOutcome * self.n_scen)()
+        check(self.lib.acopf_sqp_outcome_batch(ctypes.byref(self.cgrid), self.ws, self.stream, out))
+        return [{k: getattr(o, k) for k, _ in _abi.SqpOutcome._fields_} for o in out]
 
     # ------------------------------------------------------------ learned warm start
     def features(self, x: dict, first: bool, out=None, cols=(0, 0)):

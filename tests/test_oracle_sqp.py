@@ -242,3 +242,17 @@ def test_sqp_without_correction_is_held_back_by_the_merit():
     plain = sqp.solve(g, sqp.SqpParams(qp_solver="direct", soc=False, max_iter=20), x0)
     assert plain.outcome == "MAX_ITER"
     assert max(r.step_inf for r in plain.records if r.accepted) < 0.02
+
+
+def test_sqp_from_the_flat_start_with_the_linear_feasibility_projection():
+    """Algorithm 1 from the flat start: the start violates the power balance,
+    so it is first projected onto the linear constraints (eq. linfeas); the
+    run then ends at the same KKT point as from the power-flow start (primal
+    and dual <= 1e-4, objective within 1e-4 of SLSQP on the full ACOPF)."""
+    g = grid_14()
+    res = sqp.solve(g, sqp.SqpParams(qp_solver="direct", soc=True, linfeas=True, max_iter=40))
+    assert res.outcome == "CONVERGED"
+    last = res.records[-1]
+    assert last.primal <= 1e-4 and last.dual <= 1e-4
+    ref, viol = _full_acopf_slsqp(g, power_flow_start(g))
+    assert viol < 1e-8 and abs(last.objective - ref) <= 1e-4 * abs(ref)
