@@ -86,7 +86,8 @@ def main():
     ap.add_argument("--rho", type=float, default=2e4)
     ap.add_argument("--delta", type=float, default=0.05)
     ap.add_argument("--mode", default="graph", choices=["persistent", "launches", "graph"])
-    ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--block", type=int, default=None,
+                    help="threads per line-phase block (default: 64 for one grid; batch64: tuned, 0 = tune)")
     ap.add_argument("--max-blocks", type=int, default=0, help="persistent grid size cap (0 = fill the device)")
     ap.add_argument("--cpu-sweeps", type=int, default=None,
                     help="oracle sweeps timed for the CPU baseline (0 = skip; default per workload)")
@@ -95,6 +96,9 @@ def main():
     ap.add_argument("--val-scen", type=int, default=64, help="warmstart: validation scenarios (policy choice)")
     ap.add_argument("--sqp-iters", type=int, default=15, help="warmstart: SQP iterations per scenario")
     ap.add_argument("--train-steps", type=int, default=3000, help="warmstart: full-batch Adam steps")
+    ap.add_argument("--sqp-compare", type=int, default=1,
+                    help="1: add the SQP time-to-1e-4 of the learned and the plain start on held-out 14-bus "
+                         "scenarios (trained on the device first) to the line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB FP32 tensor three times (memory counter calibration)")
     args = ap.parse_args()
@@ -113,6 +117,8 @@ def main():
     for k, v in WORKLOAD_DEFAULTS.get(args.workload, WORKLOAD_DEFAULTS["*"]).items():
         if getattr(args, k) is None:
             setattr(args, k, v)
+    if args.block is None:
+        args.block = 0 if args.workload == "batch64" else 64
 
     import torch
     from synth.grids import WORKLOADS, power_flow_start
@@ -187,6 +193,10 @@ def main():
     cpu = None
     if args.cpu_sweeps > 0:
         cpu = cpu_baseline(g, s, args)
+    sqp_cmp = None
+    if args.sqp_compare:
+        progress = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+        sqp_cmp = sqp_learned_vs_plain(96, 32, 1500, 10, 1e3, 0.05, 20000, 1e-4, progress)
 
     out = {
         "metric": "ADMM component updates/s + SQP time-to-1e-4 residual (learned vs plain), 1 GPU",
@@ -215,6 +225,8 @@ def main():
                      "us_per_sweep": avg_launch_s / avg_sweeps * 1e6},
         "cpu_baseline": cpu,
     }
+    if sqp_cmp is not None:
+        out["sqp_learned_vs_plain"] = sqp_cmp
     print(json.dumps(out), flush=True)
 
 
@@ -243,7 +255,10 @@ def batch_grids():
 
 def bench_batch(args):
     """Batched SQP: every step is one SQP iteration of all 64 scenarios in
-    shared launches (per-scenario stop tests, radii and decisions)."""
+    shared launches (per-scenario ADMM stop tests, radii and decisions); a
+    scenario stops on the device once its primal infeasibility is <= 1e-4
+    (its time is then read from the device clock).  The line-phase block
+    size is tuned on the batch first (--block 0)."""
     import torch
     from synth.grids import power_flow_start
     from paper_2310_13143_amd.solver import DeviceGrid, autotune_block
@@ -254,7 +269,12 @@ def bench_batch(args):
     cat = lambda k: np.concatenate([st[k] for st in starts])
     x = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
     x0 = {k: v.clone() for k, v in x.items()}
-    bs = autotune_block(dg, x, args.delta, args.rho) if args.block == 0 else args.block
+    mode = SWEEP_GRAPH if args.mode == "graph" else SWEEP_LAUNCHES
+    tuned = None
+    if args.block == 0:
+        bs, tuned = autotune_block(dg, x, args.delta, args.rho, sweep_mode=mode)
+    else:
+        bs = args.block
     rho_g, rho_l = dg.rho_scalar(args.rho)
 
     def run(steps):
@@ -265,7 +285,7 @@ def bench_batch(args):
         for it in range(steps):
             outs.append(dg.sqp_step_batch(x, rho_g, rho_l, warm_start=it > 0, max_sweeps=args.sweeps,
                                           eps=args.eps, block_size=bs, pi_update=PI_IF_CONVERGED,
-                                          sweep_mode=SWEEP_GRAPH if args.mode == "graph" else SWEEP_LAUNCHES))
+                                          sweep_mode=mode, stop=(1e-4, 1e300, 0.0, 0.0)))
         return outs
 
     run(args.warmup)
@@ -274,16 +294,16 @@ def bench_batch(args):
     outs = run(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    oc = dg.sqp_outcomes()
     comps = np.array([g.n_gen + g.n_line + g.n_bus for g in grids])
     sweeps = np.array([[o[k]["admm_sweeps"] for k in range(len(grids))] for o in outs])  # (steps, scen)
     admm_ms = np.array([o[0]["admm_ms"] for o in outs])
-    # a scenario's solve time: its sweeps at the batch's per-sweep time of that step
     per_sweep_ms = admm_ms / np.maximum(sweeps.max(axis=1), 1)
-    per_scen_ms = sweeps * per_sweep_ms[:, None]
     value = float((sweeps * comps[None, :]).sum()) / wall
     bsweep = sum(sweep_bytes(g.n_bus, g.n_line, g.n_gen) for g in grids)
     achieved = bsweep / (float(per_sweep_ms.mean()) / 1e3) / 1e9
     res = dg.residuals_batch(x)
+    t_stop = np.array([o["seconds"] for o in oc if o["done"]])
     out = {
         "metric": "batched ADMM component updates/s (64 scenarios per launch), 1 GPU",
         "value": value, "unit": "component updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -291,15 +311,20 @@ def bench_batch(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batch64: 64 load scenarios (N(1,0.1) per-bus factors) over the 300-, 2,000- and "
                                "10,000-bus grids (22/21/21), shared launches, per-scenario stop tests and SQP "
-                               f"decisions; <= {args.sweeps} sweeps per QP, eps={args.eps:g}, block {bs}",
+                               f"decisions; <= {args.sweeps} sweeps per QP, eps={args.eps:g}, block {bs}"
+                               + (" (tuned)" if tuned else ""),
                    "buses": dg.n_bus, "lines": dg.n_line, "generators": dg.n_gen},
         "batch": {"scenarios_per_s": len(grids) * args.steps / wall,
-                  "p50_scenario_solve_ms": float(np.percentile(per_scen_ms, 50)),
-                  "p99_scenario_solve_ms": float(np.percentile(per_scen_ms, 99)),
+                  "stopped_at_1e-4": int(len(t_stop)),
+                  "p50_stop_s": float(np.median(t_stop)) if len(t_stop) else None,
+                  "p99_stop_s": float(np.percentile(t_stop, 99)) if len(t_stop) else None,
+                  "run_s": wall,
                   "accepted": int(sum(o[k]["accepted"] for o in outs for k in range(len(grids)))),
-                  "primal_max": float(max(r["primal"] for r in res)), "block": bs},
+                  "primal_max": float(max(r["primal"] for r in res)), "primal_min": float(min(r["primal"] for r in res)),
+                  "block": bs, "tuning_ms": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload), "kernel": "k_line_phase+k_bus_items",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload),
+                     "kernel": "k_line_phase+k_bus_items",
                      "bytes_per_sweep": bsweep, "us_per_sweep": float(per_sweep_ms.mean()) * 1e3},
         "cpu_baseline": None,
     }
@@ -310,6 +335,65 @@ def ring14_scenarios(seeds):
     from synth.grids import grid_14, perturb_loads, power_flow_start
     grids = [perturb_loads(grid_14(), int(s)) for s in seeds]
     return grids, [power_flow_start(g) for g in grids]
+
+
+def sqp_learned_vs_plain(n_train: int, n_test: int, train_steps: int, sqp_iters: int, rho: float, delta: float,
+                         sweeps: int, eps: float, progress=None) -> dict:
+    """SQP time-to-1e-4 with the learned and the plain ADMM start on the same
+    device: trace the plain batched SQP on n_train perturbed-load scenarios
+    of the 14-bus grid, train the line and generator networks on the device,
+    then run n_test held-out scenarios as one batch with each start; every
+    scenario stops on the device once its primal infeasibility is <= 1e-4,
+    and its time is read from the device clock."""
+    import torch
+    from paper_2310_13143_amd.solver import DeviceGrid
+    from paper_2310_13143_amd import warmstart as W
+
+    def device_batch(seeds):
+        grids, starts = ring14_scenarios(seeds)
+        dg = DeviceGrid(grids, "cuda:0")
+        cat = lambda k: np.concatenate([st[k] for st in starts])
+        return dg, dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
+
+    sq = dict(rho=rho, delta0=delta, max_sweeps=sweeps, eps=eps)
+    t0 = time.perf_counter()
+    dg, x = device_batch(50000 + np.arange(n_train))
+    Xl, Tl, Xg, Tg = W.collect(dg, x, min(sqp_iters, 6), **sq)
+    torch.cuda.synchronize()
+    t_trace = time.perf_counter() - t0
+    if progress:
+        progress(f"traced {n_train} training scenarios")
+    net = W.WarmStart("cuda:0", seed=7)
+    net.line.fit_standardized(Xl, Tl, train_steps, lr=3e-3, lr_end=3e-5)
+    net.gen.fit_standardized(Xg, Tg, train_steps, lr=3e-3, lr_end=3e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0 - t_trace
+    if progress:
+        progress("trained the networks")
+    held = 60000 + np.arange(n_test)
+    out = {"workload": f"ring14 (14 buses, 20 branches, 5 generators) with per-bus load factors N(1,0.1): "
+                       f"{n_train} training and {n_test} held-out scenarios; batched SQP of the held-out "
+                       f"scenarios, <= {sqp_iters} iterations, <= {sweeps} ADMM sweeps per QP, eps={eps:g}, "
+                       f"rho={rho:g}, delta0={delta:g}; a scenario stops on the device at primal "
+                       "infeasibility <= 1e-4 and its time is read from the device clock",
+           "trace_s": t_trace, "train_s": t_train}
+    for name, kw in (("plain", dict(net=None)), ("learned", dict(net=net, lam_policy="none", use_rho=True))):
+        for rep in range(2):  # the first pass warms up the launches
+            dg, x = device_batch(held)
+            r = W.run_sqp(dg, x, sqp_iters, **sq, **kw, device_stop=True)
+        t = r["t_device"]
+        hit = np.isfinite(t)
+        upto = [r["sweeps"][:k, s].sum() for s, k in enumerate(r["it_device"]) if k > 0]
+        out[name] = {"solved": int(hit.sum()),
+                     "time_to_1e-4_s": {"p50": float(np.median(t[hit])) if hit.any() else None,
+                                        "p99": float(np.percentile(t[hit], 99)) if hit.any() else None,
+                                        "max": float(t[hit].max()) if hit.any() else None},
+                     "iterations_mean": float(r["it_device"][hit].mean()) if hit.any() else None,
+                     "sweeps_to_1e-4_mean": float(np.mean(upto)) if upto else None,
+                     "wall_s": r["wall"]}
+        if progress:
+            progress(f"{n_test} held-out scenarios with the {name} start")
+    return out
 
 
 def bench_warmstart(args):

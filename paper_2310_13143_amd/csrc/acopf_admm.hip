@@ -170,21 +170,30 @@ __global__ void k_copy(double* dst, const double* src, long long n) {
   for (long long i = gtid(); i < n; i += gstride()) dst[i] = src[i];
 }
 
-// Line-by-line state [n][F] from / to the field-by-field layout [F][n] of
-// the C ABI.
-__global__ void k_fields_to_lines(double* dst, const double* src, int n, int F) {
-  const long long total = (long long)n * F;
+// Line-by-line coupling state (8 slots per line, lc8) from / to the
+// field-by-field layout [8][n] of the C ABI.
+__global__ void k_fields_to_lines(double* dst, const double* src, int n) {
+  const long long total = 8LL * n;
   for (long long e = gtid(); e < total; e += gstride()) {
-    const long long i = e / F, f = e - i * F;
-    dst[e] = src[f * n + i];
+    const int i = (int)(e / 8), f = (int)(e - 8LL * i);
+    dst[lc8(i, f)] = src[(long long)f * n + i];
   }
 }
 
-__global__ void k_lines_to_fields(double* dst, const double* src, int n, int F) {
-  const long long total = (long long)n * F;
+__global__ void k_lines_to_fields(double* dst, const double* src, int n) {
+  const long long total = 8LL * n;
   for (long long e = gtid(); e < total; e += gstride()) {
-    const long long f = e / n, i = e - f * n;
-    dst[e] = src[i * F + f];
+    const int f = (int)(e / n), i = (int)(e - (long long)f * n);
+    dst[e] = src[lc8(i, f)];
+  }
+}
+
+// Line-by-line [n][4] arrays (bus-side copies) to the layout [4][n].
+__global__ void k_lines4_to_fields(double* dst, const double* src, int n) {
+  const long long total = 4LL * n;
+  for (long long e = gtid(); e < total; e += gstride()) {
+    const int f = (int)(e / n), i = (int)(e - (long long)f * n);
+    dst[e] = src[lc4(i, f)];
   }
 }
 
@@ -1237,16 +1246,16 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
   auto copy = [&](double* d, const double* src, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, bs)), dim3(bs), 0, s, d, src, n);
   };
-  auto to_lines = [&](double* d, const double* src, int n, int F) {
-    hipLaunchKernelGGL(k_fields_to_lines, dim3(blocks_for((long long)n * F, bs)), dim3(bs), 0, s, d, src, n, F);
+  auto to_lines = [&](double* d, const double* src, int n) {
+    hipLaunchKernelGGL(k_fields_to_lines, dim3(blocks_for(8LL * n, bs)), dim3(bs), 0, s, d, src, n);
   };
   copy(w.rho_g, rho_g, G2);
-  to_lines(w.rho_l, rho_l, g->n_line, 8);
+  to_lines(w.rho_l, rho_l, g->n_line);
   if (keep_lam) {
     // multipliers of the previous solve stay in place (previous-iterate warm start)
   } else if (lam_l) {
     copy(w.lam_g, lam_g, G2);
-    to_lines(w.lam_l, lam_l, g->n_line, 8);
+    to_lines(w.lam_l, lam_l, g->n_line);
   } else {
     fill(w.lam_g, G2, 0.0);
     fill(w.lam_l, L8, 0.0);
@@ -1606,7 +1615,10 @@ acopf_status acopf_admm_state_get(const acopf_grid* g, void* workspace, const ac
   auto fields = [&](double* dst, const double* src, int F) -> hipError_t {  // line-by-line -> caller layout
     if (!dst) return hipSuccess;
     const long long n = (long long)g->n_line * F;
-    hipLaunchKernelGGL(k_lines_to_fields, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, src, g->n_line, F);
+    if (F == 8)
+      hipLaunchKernelGGL(k_lines_to_fields, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, src, g->n_line);
+    else
+      hipLaunchKernelGGL(k_lines4_to_fields, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, src, g->n_line);
     return hipGetLastError();
   };
   (void)L8;

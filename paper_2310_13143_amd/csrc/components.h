@@ -12,9 +12,16 @@
 namespace acopf {
 
 // The coupling state of the lines (x, lambda, rho and the starting
-// multipliers: 8 couplings per line; the bus-side flow copies: 4) is stored
-// line by line, so the values one line end needs share a cache line.
-ACOPF_HD size_t lc8(int l, int k) { return 8 * (size_t)l + k; }
+// multipliers: 8 couplings per line) is stored line by line, each line's 8
+// slots ordered by line end: the from end's (p_ij, q_ij, w_i, th_i), then
+// the to end's (p_ji, q_ji, w_j, th_j), so the bus update of one line end
+// reads and writes one aligned 32-byte half of each record.  Couplings are
+// numbered 0-3 for the flows (p_ij, q_ij, p_ji, q_ji) and 4-7 for the
+// voltage copies (w_i, th_i, w_j, th_j); slot8 maps that number to its
+// slot.  The bus-side copies are two arrays of 4 per line (flows; the end
+// buses' d_w, d_th), in coupling order.
+ACOPF_HD constexpr int slot8(int k) { return (k & 1) | ((k & 2) << 1) | ((k & 4) >> 1); }
+ACOPF_HD size_t lc8(int l, int k) { return 8 * (size_t)l + slot8(k); }
 ACOPF_HD size_t lc4(int l, int k) { return 4 * (size_t)l + k; }
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;

@@ -7,7 +7,7 @@
 // threads touch consecutive addresses (field k of an array with n entries per
 // field at [k * n + index]), except the lines' coupling state, which the bus
 // update gathers per line end and which is therefore stored line by line
-// ([index * fields + k]).
+// (8 slots per line, ordered by line end; see lc8).
 #pragma once
 
 #include <stddef.h>

@@ -326,27 +326,28 @@ class DeviceGrid:
 _TUNED = {}
 
 
-def autotune_block(dg: DeviceGrid, x: dict, delta: float = 0.05, rho: float = 2e4, sweeps: int = 50,
-                   candidates=(64, 128, 256)) -> int:
-    """Block size of the sweep kernels (launch mode) that runs fastest on this
-    grid or batch, timed with HIP events over a few sweeps of the QP at x;
-    cached per (buses, lines, scenarios) for the process."""
-    key = (dg.n_bus, dg.n_line, dg.n_scen)
+def autotune_block(dg: DeviceGrid, x: dict, delta: float = 0.05, rho: float = 2e4, sweeps: int = 128,
+                   candidates=(64, 128, 256), sweep_mode: int = _abi.SWEEP_GRAPH):
+    """Block size of the line phase that runs fastest on this grid or batch
+    in the given sweep mode, timed with HIP events over a few sweeps of the
+    QP at x (after one untimed pass per candidate); cached per (buses, lines,
+    scenarios, mode) for the process.  Returns (block size, {candidate: ms})."""
+    key = (dg.n_bus, dg.n_line, dg.n_scen, sweep_mode)
     if key in _TUNED:
         return _TUNED[key]
     stream = torch.cuda.current_stream(dg.device)
     dg.qp_build(x, delta)
-    best, best_ms = candidates[0], float("inf")
+    times = {}
     for bs in candidates:
         dg.admm_init(*dg.rho_scalar(rho))
-        dg.admm_solve(5, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=bs, sync=False)
+        dg.admm_solve(sweeps, sweep_mode=sweep_mode, block_size=bs, sync=False)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dg.admm_init(*dg.rho_scalar(rho))
         a.record(stream)
-        dg.admm_solve(sweeps, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=bs, sync=False)
+        dg.admm_solve(sweeps, sweep_mode=sweep_mode, block_size=bs, sync=False)
         b.record(stream)
         b.synchronize()
-        ms = a.elapsed_time(b)
-        if ms < best_ms:
-            best, best_ms = bs, ms
-    _TUNED[key] = best
-    return best
+        times[bs] = a.elapsed_time(b)
+    best = min(times, key=times.get)
+    _TUNED[key] = (best, times)
+    return _TUNED[key]

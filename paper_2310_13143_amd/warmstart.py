@@ -188,14 +188,19 @@ def collect(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int,
 
 def run_sqp(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int, eps: float,
             net: WarmStart | None = None, lam_policy: str = "first", use_rho: bool = True, block_size: int = 64,
-            tol: float = 1e-4, **sqp_kw):
+            tol: float = 1e-4, device_stop: bool = False, **sqp_kw):
     """Batched SQP from x for up to `iters` iterations, with the plain start
     (net=None: zero, then the previous multipliers) or the learned start:
     penalties from the network if use_rho, multipliers corrected by the
     network at the first QP (lam_policy "first"), at every QP ("all") or
     never ("none").  Returns per-scenario records: ADMM sweeps per
     iteration, primal infeasibility after each iteration, the iteration and
-    wall time at which it first reached tol, and the total wall time."""
+    wall time at which it first reached tol, and the total wall time.  With
+    device_stop, each scenario stops on the device once its primal
+    infeasibility is <= tol (its iterate is then frozen) and "t_device" holds
+    its stop time read from the device clock (NaN if it did not stop)."""
+    if device_stop:
+        sqp_kw = dict(sqp_kw, stop=(tol, 1e300, 0.0, 0.0))
     S = dg.n_scen
     rho_g, rho_l = dg.rho_scalar(rho)
     dg.set_delta(delta0)
@@ -223,5 +228,9 @@ def run_sqp(dg, x: dict, iters: int, rho: float, delta0: float, max_sweeps: int,
             if it_hit[k] < 0 and rep[k]["primal"] <= tol:
                 it_hit[k], t_hit[k] = it, now
     torch.cuda.synchronize(dg.device)
-    return {"sweeps": sweeps, "primal": primal, "it_hit": it_hit, "t_hit": t_hit,
-            "wall": time.perf_counter() - t0}
+    out = {"sweeps": sweeps, "primal": primal, "it_hit": it_hit, "t_hit": t_hit, "wall": time.perf_counter() - t0}
+    if device_stop:
+        oc = dg.sqp_outcomes()
+        out["t_device"] = np.array([o["seconds"] if o["done"] else np.nan for o in oc])
+        out["it_device"] = np.array([o["iterations"] if o["done"] else -1 for o in oc])
+    return out

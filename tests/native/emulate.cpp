@@ -40,6 +40,9 @@ void emu_limit_relaxation(int n, const double* lo, const double* hi, const doubl
   }
 }
 
+// Slot of coupling k in a line's 8-entry record.
+int emu_slot8(int k) { return slot8(k); }
+
 // Neighbouring working sets of the line phase's wave search.
 int emu_neighbour_mask(int base, int idx) { return neighbour_mask(base, idx); }
 
@@ -118,11 +121,11 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   std::memcpy(w.rho_g, rho_g, sizeof(double) * 2 * ng);
   // caller layout [field][line] -> the workspace's line-by-line state
   for (int l = 0; l < nl; ++l)
-    for (int k = 0; k < 8; ++k) w.rho_l[8 * l + k] = rho_l[k * nl + l];
+    for (int k = 0; k < 8; ++k) w.rho_l[lc8(l, k)] = rho_l[k * nl + l];
   if (lam_l) {
     std::memcpy(w.lam_g, lam_g, sizeof(double) * 2 * ng);
     for (int l = 0; l < nl; ++l)
-      for (int k = 0; k < 8; ++k) w.lam_l[8 * l + k] = lam_l[k * nl + l];
+      for (int k = 0; k < 8; ++k) w.lam_l[lc8(l, k)] = lam_l[k * nl + l];
   } else {
     std::memset(w.lam_g, 0, sizeof(double) * 2 * ng);
     std::memset(w.lam_l, 0, sizeof(double) * 8 * nl);
@@ -163,7 +166,8 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
 }
 
 // Addresses of the ADMM state arrays inside a host workspace, in the order
-// xl, lam_l, xbar_f, xg, lam_g, dw, dth, nu.
+// xl, lam_l, xbar_f, xg, lam_g, dw, dth, nu (xl, lam_l: 8 slots per line,
+// emu_slot8 maps a coupling to its slot; xbar_f: 4 per line).
 void emu_state_ptrs(void* base, int nb, int nl, int ng, double** out) {
   Workspace w;
   layout_workspace(base, nb, nl, ng, 1, &w);

@@ -259,8 +259,11 @@ def test_sweeps_and_step_match_oracle(emu, case):
         scale = max(np.abs(b).max(), 1e-300)
         assert np.abs(a - b).max() <= tol * scale, (np.abs(a - b).max(), scale)
 
-    close(lay("xl", 8 * g.n_line).reshape(-1, 8), st.xl)  # line by line in the workspace
-    close(lay("lam_l", 8 * g.n_line).reshape(-1, 8), st.lam_l)
+    # line by line in the workspace, 8 slots per line ordered by line end
+    slots = [emu.emu_slot8(k) for k in range(8)]
+    assert sorted(slots) == list(range(8)) and slots[:4] == [0, 1, 4, 5]
+    close(lay("xl", 8 * g.n_line).reshape(-1, 8)[:, slots], st.xl)
+    close(lay("lam_l", 8 * g.n_line).reshape(-1, 8)[:, slots], st.lam_l)
     close(lay("xbar_f", 4 * g.n_line).reshape(-1, 4), st.xbar_f)
     close(lay("xg", 2 * g.n_gen).reshape(2, -1).T, st.xg)
     close(lay("lam_g", 2 * g.n_gen).reshape(2, -1).T, st.lam_g)
