@@ -36,7 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was measured with (sha256 prefix over SWEEP_SOURCES); otherwise the bench
 # reports null.
 SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_amd/csrc/components.h",
-                 "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/small_linalg.h",
+                 "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/line_alm.h",
+                 "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
 MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("e893c3b305633f9a", 118143528)}

@@ -43,7 +43,17 @@ typedef enum {
   ACOPF_ADMM_FAILED = 2           /* not solved: the scenario's QP build or factorisation failed (status) */
 } acopf_admm_outcome;
 
-typedef enum { ACOPF_HESSIAN_PSD = 0, ACOPF_HESSIAN_RAW = 1 } acopf_hessian_mode;
+/* Line Hessians and line solver.  PSD: the reduced line Hessians are
+ * projected onto the positive semidefinite cone and each line subproblem is
+ * solved exactly.  RAW: the unmodified Hessians, solved exactly; a line
+ * whose subproblem matrix is not positive definite fails the solve with
+ * ACOPF_ERR_NONCONVEX_LINE.  RAW_LOCAL: the unmodified Hessians, every line
+ * subproblem solved by the paper's local method, the augmented Lagrangian
+ * over the slack form with a projected trust-region Newton inner solver
+ * (Section IV-B2, eqs. line_kernel_simp1, line_kernel_alm), started from
+ * the previous sweep's solution: on nonconvex lines it finds a local
+ * minimiser. */
+typedef enum { ACOPF_HESSIAN_PSD = 0, ACOPF_HESSIAN_RAW = 1, ACOPF_HESSIAN_RAW_LOCAL = 2 } acopf_hessian_mode;
 /* How the sweeps of a solve are issued: one cooperative kernel for all
  * sweeps (single scenario); kernel launches per phase; or the same launches
  * replayed from an instantiated HIP graph of one chunk of sweeps (64; the

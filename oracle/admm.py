@@ -107,8 +107,11 @@ def line_matrices(qp, rho: Rho):
     return Q
 
 
-def line_update(grid, qp, st: AdmmState, rho: Rho, Q=None):
-    """Exact solve of (eq. line_kernel) for every line; returns (x (L,8), mu, feasible)."""
+def line_update(grid, qp, st: AdmmState, rho: Rho, Q=None, solver: str = "exact"):
+    """Solve of (eq. line_kernel) for every line: exact (enumeration), or
+    "alm": the paper's local method (ALM + TRON, ``alm.solve_line``) from the
+    previous sweep's solution and limit-row multipliers.  Returns
+    (x (L,8), mu, solved)."""
     L = qp.line
     if Q is None:
         Q = line_matrices(qp, rho)
@@ -116,7 +119,17 @@ def line_update(grid, qp, st: AdmmState, rho: Rho, Q=None):
     lam_f, lam_v = st.lam_l[:, :4], st.lam_l[:, 4:]
     xbar_v = np.stack([st.dw[grid.f], st.dth[grid.f], st.dw[grid.t], st.dth[grid.t]], 1)
     c = L.q + np.einsum("lf,lfi->li", lam_f + rf * (L.f0 - st.xbar_f), L.F) + lam_v - rv * xbar_v
-    z, mu, _, feas = solve_line_qps(Q, c, L.lo, L.hi, L.G, L.h)
+    if solver == "alm":
+        from . import alm
+        n = Q.shape[0]
+        z, mu, feas = np.zeros((n, 4)), np.zeros((n, 2)), np.zeros(n, dtype=bool)
+        for l in range(n):
+            r = alm.solve_line(Q[l], c[l], L.lo[l], L.hi[l], L.G[l], L.h[l], z0=st.xl[l, 4:8], u0=st.mu[l])
+            z[l], mu[l], feas[l] = r.z, r.u, r.converged
+    elif solver == "exact":
+        z, mu, _, feas = solve_line_qps(Q, c, L.lo, L.hi, L.G, L.h)
+    else:
+        raise ValueError(solver)
     flows = np.einsum("lfi,li->lf", L.F, z) + L.f0
     return np.concatenate([flows, z], 1), mu, feas
 
@@ -178,10 +191,10 @@ def bus_update(grid, qp, xg, xl, st: AdmmState, rho: Rho):
     return xbar_g, xbar_f, dw, dth, nu
 
 
-def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None):
+def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None, line_solver: str = "exact"):
     """One ADMM iteration of Algorithm 2; returns (new state, r, s, feasible)."""
     xg = gen_update(qp, st, rho)
-    xl, mu, feas = line_update(grid, qp, st, rho, Q)
+    xl, mu, feas = line_update(grid, qp, st, rho, Q, line_solver)
     xbar_g, xbar_f, dw, dth, nu = bus_update(grid, qp, xg, xl, st, rho)
     f, t = grid.f, grid.t
     xbar_l = np.concatenate([xbar_f, np.stack([dw[f], dth[f], dw[t], dth[t]], 1)], 1)
@@ -218,7 +231,7 @@ def balance_factor(r: float, s: float, b: Balance) -> float:
 
 def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
           state: AdmmState | None = None, record: bool = False, record_states: bool = False,
-          balance: Balance | None = None):
+          balance: Balance | None = None, line_solver: str = "exact"):
     """Algorithm 2 until ||r|| <= eps_pri and ||s|| <= eps_dual or max_sweeps;
     with ``balance``, residual balancing of the penalties between sweeps
     (the result's ``rho`` holds the final penalties)."""
@@ -230,7 +243,7 @@ def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
     bad = 0
     k = 0
     for k in range(1, max_sweeps + 1):
-        st, r, s, feas = sweep(grid, qp, st, rho, Q)
+        st, r, s, feas = sweep(grid, qp, st, rho, Q, line_solver)
         bad = int((~feas).sum())
         if record:
             hist.append((r, s))

@@ -67,6 +67,11 @@ class SqpParams:
     # "direct": by the interior-point solve of the same eliminated QP
     # (``direct.solve``), which gives the SQP iterates of exact QP solutions
     qp_solver: str = "admm"
+    # line subproblems of the ADMM: "exact" (enumeration; needs a positive
+    # definite line matrix, so hessian_mode "psd" or a convex "raw"), or
+    # "alm": the paper's local method (Section IV-B2) on the unmodified
+    # Hessians (hessian_mode "raw")
+    line_solver: str = "exact"
     # an accepted step that reached the radius doubles it when
     # ared >= grow_ratio * pred
     grow_ratio: float = 0.75
@@ -246,7 +251,8 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
         if params.qp_solver != "admm":
             raise ValueError(params.qp_solver)
         start = admm.cold_state(grid) if lam_g is None else admm.warm_state(grid, lam_g, lam_l)
-        res = admm.solve(grid, qp, rho, params.max_sweeps, params.eps_pri, params.eps_dual, start)
+        res = admm.solve(grid, qp, rho, params.max_sweeps, params.eps_pri, params.eps_dual, start,
+                         line_solver=params.line_solver)
         st = res.state
         return (assemble_step(grid, qp, st), recover_pi(grid, x, qp, st), st.nu[:, 0], st.nu[:, 1], res,
                 st.lam_g, st.lam_l)

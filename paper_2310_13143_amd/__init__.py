@@ -4,6 +4,6 @@ The computation runs in the HIP library ``libacopf_admm.so`` (C ABI declared
 in ``include/acopf_admm.h``); this package only marshals arguments to it,
 with PyTorch providing device memory and streams.
 """
-from ._abi import AcopfError, HESSIAN_PSD, HESSIAN_RAW, SWEEP_GRAPH, SWEEP_LAUNCHES, SWEEP_PERSISTENT  # noqa: F401
+from ._abi import AcopfError, HESSIAN_PSD, HESSIAN_RAW, HESSIAN_RAW_LOCAL, SWEEP_GRAPH, SWEEP_LAUNCHES, SWEEP_PERSISTENT  # noqa: F401
 
-__all__ = ["AcopfError", "HESSIAN_PSD", "HESSIAN_RAW", "SWEEP_GRAPH", "SWEEP_LAUNCHES", "SWEEP_PERSISTENT"]
+__all__ = ["AcopfError", "HESSIAN_PSD", "HESSIAN_RAW", "HESSIAN_RAW_LOCAL", "SWEEP_GRAPH", "SWEEP_LAUNCHES", "SWEEP_PERSISTENT"]

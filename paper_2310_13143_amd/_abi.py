@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libacopf_admm.so")
 ACOPF_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "NONCONVEX_LINE", -4: "NUMERIC",
                 -5: "UNSUPPORTED", -6: "BARRIER"}
-HESSIAN_PSD, HESSIAN_RAW = 0, 1
+HESSIAN_PSD, HESSIAN_RAW, HESSIAN_RAW_LOCAL = 0, 1, 2
 SWEEP_PERSISTENT, SWEEP_LAUNCHES, SWEEP_GRAPH = 0, 1, 2
 ADMM_CONVERGED, ADMM_MAX_SWEEPS, ADMM_FAILED = 0, 1, 2
 START_ZERO, START_PREVIOUS, START_GIVEN = 0, 1, 2

@@ -202,10 +202,11 @@ __global__ void k_prep_lines(Workspace w) {
     if (!prep_line(w, l)) fail_line(w, l, ACOPF_ERR_NONCONVEX_LINE, &w.sync->nonconvex);
 }
 
-__global__ void k_clear_flags(Workspace w) {
+__global__ void k_clear_flags(Workspace w, int mode) {
   if (gtid() == 0) {
     w.sync->numeric_error = 0;
     w.sync->nonconvex = 0;
+    w.sync->hessian_mode = mode;
   }
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
     w.scen[s].status = 0;
@@ -348,17 +349,18 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // block needs no table lookup (one flag read before the line work).  At
 // most 256 registers per lane: two waves per SIMD (measured faster than one
 // wave with more registers; a cap of three waves spills hundreds of bytes).
-// `test`: first evaluate the stop test of the previous sweep (launch modes).
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
-  __shared__ int s_stop;
-  int s = 0;
+// Start of a line-phase block: its scenario s and, with `test`, the stop
+// test of the previous sweep (launch modes).  False when the block has
+// nothing to do (scenario done or stopped now).
+__device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single, int test, double eps_pri,
+                                                 double eps_dual, int& s, int* s_stop) {
+  s = 0;
   if (single) {
-    if (w.scen[0].done) return;
+    if (w.scen[0].done) return false;
   } else {
-    if (batch_done(w)) return;
+    if (batch_done(w)) return false;
     s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
-    if (s < 0 || w.scen[s].done) return;
+    if (s < 0 || w.scen[s].done) return false;
   }
   if (test) {
     double r2, s2;
@@ -367,15 +369,31 @@ k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double
       const bool stop = stop_met(r2, s2, eps_pri, eps_dual);
       // the scenario's first block records the stop; every block obeys it
       if (stop && (int)blockIdx.x == (single ? 0 : w.line_blk_off[s])) record_sweep(w, s, r2, s2, true, eps_pri, eps_dual);
-      s_stop = stop ? 1 : 0;
+      *s_stop = stop ? 1 : 0;
     }
     __syncthreads();
-    if (s_stop) return;
+    if (*s_stop) return false;
   }
+  return true;
+}
+
+// Line of this thread in scenario s, -1 past the scenario's lines.
+__device__ __forceinline__ int line_of_thread(const Workspace& w, int single, int s) {
   const int l = single ? (int)(blockIdx.x * blockDim.x + threadIdx.x)
                        : w.scen_line_off[s] + (int)((blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x);
-  if (l >= (single ? w.n_line : w.scen_line_off[s + 1])) return;
-  if (!search) {  // one full solve per thread (the solver's own warm start and guess)
+  return l < (single ? w.n_line : w.scen_line_off[s + 1]) ? l : -1;
+}
+
+// `test`: first evaluate the stop test of the previous sweep (launch modes).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
+  __shared__ int s_stop;
+  int s;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
+  const int l = line_of_thread(w, single, s);
+  if (l < 0) return;
+  // one full solve per thread (the exact solver's own warm start and guess)
+  if (!search) {
     if (update_line(g, w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
     return;
   }
@@ -412,6 +430,19 @@ k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double
     asm volatile("" : "+v"(lr));
     if (update_line(g, w, lr) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
   }
+}
+
+// Line phase with the local line solver (hessian mode RAW_LOCAL): one
+// ALM + TRON solve per thread.  A kernel of its own, so that the exact
+// solver's kernel keeps its register budget.
+__global__ void __launch_bounds__(256)
+k_line_phase_local(Workspace w, int single, int test, double eps_pri, double eps_dual) {
+  __shared__ int s_stop;
+  int s;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
+  const int l = line_of_thread(w, single, s);
+  if (l < 0) return;
+  if (update_line_local(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
 // Bus phase by coupling items (launch modes): one thread per line end or
@@ -585,7 +616,8 @@ __device__ void grid_barrier(const Workspace& w, unsigned int epoch, F&& last) {
   __syncthreads();
 }
 
-// Persistent sweep loop of a single scenario.
+// Persistent sweep loop of a single scenario (LOCAL: the local line solver).
+template <bool LOCAL>
 __global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspace w, int max_sweeps,
                                                           double eps_pri, double eps_dual) {
   __shared__ double lds[16];
@@ -595,7 +627,7 @@ __global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspac
   if (__hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;  // failed QP: same for all blocks
   for (int k = 0; k < max_sweeps; ++k) {
     for (int l = gtid(); l < g.n_line; l += gstride())
-      if (update_line(g, w, l) != 0) atomicAdd(&sc->infeasible[k & 1], 1);
+      if ((LOCAL ? update_line_local(w, l) : update_line(g, w, l)) != 0) atomicAdd(&sc->infeasible[k & 1], 1);
     grid_barrier(w, 2u * k + 1u, [] {});
     double r2 = 0.0, s2 = 0.0;
     for (int i = gtid(); i < g.n_bus; i += gstride()) update_bus(g, w, i, r2, s2);
@@ -1095,6 +1127,36 @@ acopf_status read_sync(const Workspace& w, hipStream_t s, SyncState* out) {
   return ACOPF_OK;
 }
 
+// ---------------------------------------------------------------- line solver per workspace
+// Hessian mode of the last QP build on each workspace, kept on the host:
+// it picks the line kernels of the solves that follow (the local line
+// solver's kernels are separate instantiations).  acopf_setup resets it.
+struct ModeTable {
+  std::mutex mu;
+  std::map<const void*, int> mode;
+};
+
+ModeTable& mode_table() {
+  static ModeTable* t = new ModeTable();
+  return *t;
+}
+
+void set_hessian_mode(const void* workspace, int mode) {
+  ModeTable& t = mode_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (mode == ACOPF_HESSIAN_PSD)
+    t.mode.erase(workspace);
+  else
+    t.mode[workspace] = mode;
+}
+
+bool local_line_solver(const void* workspace) {
+  ModeTable& t = mode_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  auto it = t.mode.find(workspace);
+  return it != t.mode.end() && it->second == ACOPF_HESSIAN_RAW_LOCAL;
+}
+
 acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int32_t* line_off_h,
                         const int32_t* gen_off_h, const int32_t* ref_h, void* workspace, size_t bytes,
                         void* stream) {
@@ -1227,6 +1289,7 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
   if (ng > 0) HIP_TRY(hipMemset(w.tr_s_g, 0, 2 * (size_t)ng * D));
   HIP_TRY(hipMemset(w.tr_r_l, 0, 8 * (size_t)nl * D));
   HIP_TRY(hipMemset(w.tr_s_l, 0, 8 * (size_t)nl * D));
+  set_hessian_mode(workspace, ACOPF_HESSIAN_PSD);
   return ACOPF_OK;
 }
 
@@ -1284,6 +1347,7 @@ struct SweepLaunch {
   acopf_grid g;
   Workspace w;
   int nbl, nbb, bs, single, ns, trace, max_sweeps;
+  int local;  // the local line solver's kernel
   double eps_pri, eps_dual;
 };
 
@@ -1294,8 +1358,12 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
   const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
-                       (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
+    if (a.local)
+      hipLaunchKernelGGL(k_line_phase_local, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
+                         (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
+    else
+      hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
+                         (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
     if (a.trace && small)
       hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single);
     else if (a.trace)
@@ -1339,7 +1407,7 @@ std::string graph_key(const SweepLaunch& a, int n, int dev) {
                         g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
                         g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
   put(ptrs, sizeof ptrs);
-  const int shape[7] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps};
+  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps, a.local};
   put(shape, sizeof shape);
   put(&a.eps_pri, sizeof a.eps_pri);
   put(&a.eps_dual, sizeof a.eps_dual);
@@ -1424,13 +1492,14 @@ acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double 
   if (!grid_ok(g) || !iterate_ok(x) || !workspace)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: null argument");
   if (!(delta >= 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: trust radius must be >= 0");
-  if (mode != ACOPF_HESSIAN_PSD && mode != ACOPF_HESSIAN_RAW)
+  if (mode != ACOPF_HESSIAN_PSD && mode != ACOPF_HESSIAN_RAW && mode != ACOPF_HESSIAN_RAW_LOCAL)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: unknown Hessian mode");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace w = ws_of(g, workspace);
   const int bs = kDefaultBlock;
   if (delta > 0.0) hipLaunchKernelGGL(k_set_delta, dim3(blocks_for(w.n_scen, bs)), dim3(bs), 0, s, w, delta);
-  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w);
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w, (int)mode);
+  set_hessian_mode(workspace, mode);
   hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, (int)mode, w, 0);
   if (g->n_gen > 0) hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w);
   hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
@@ -1471,6 +1540,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: residual balancing needs balance_mu >= 1 and balance_tau > 1");
   if (balance && p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
     return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: residual balancing runs in the launch-per-phase modes");
+  const bool local = local_line_solver(workspace);
   if (p->trace) {
     const int bz = kDefaultBlock;
     const long long G2 = 2LL * g->n_gen, L8 = 8LL * g->n_line;
@@ -1500,6 +1570,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.ns = ns;
     a.trace = p->trace;
     a.max_sweeps = p->max_sweeps;
+    a.local = local ? 1 : 0;
     a.eps_pri = p->eps_pri;
     a.eps_dual = p->eps_dual;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1544,7 +1615,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: device has no cooperative launch");
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_persistent, bs, 0));
+    const void* kern = local ? (const void*)k_sweep_persistent<true> : (const void*)k_sweep_persistent<false>;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, bs, 0));
     if (per_cu < 1) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: persistent kernel does not fit a CU");
     long long want = std::max(blocks_for(g->n_line, bs), blocks_for(g->n_bus, bs));
     long long nblk = std::min<long long>(want, (long long)per_cu * cus);
@@ -1556,7 +1628,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     int ms = p->max_sweeps;
     double ep = p->eps_pri, ed = p->eps_dual;
     void* args[] = {&gg, &w, &ms, &ep, &ed};
-    HIP_TRY(hipLaunchCooperativeKernel((const void*)k_sweep_persistent, dim3((unsigned)nblk), dim3(bs), args, 0, s));
+    HIP_TRY(hipLaunchCooperativeKernel(kern, dim3((unsigned)nblk), dim3(bs), args, 0, s));
   } else {
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: unknown sweep mode");
   }

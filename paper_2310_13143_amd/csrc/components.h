@@ -4,6 +4,7 @@
 // that the same source can be compiled for the host to test its arithmetic.
 #pragma once
 
+#include "line_alm.h"
 #include "line_qp.h"
 #include "small_linalg.h"
 #include "workspace.h"
@@ -299,7 +300,8 @@ ACOPF_HD void build_bus(const acopf_grid& g, const acopf_iterate& x, const Works
 // Factorisation of line l's subproblem matrix for the current penalties:
 // P = Q^{-1}, Q = M + sum_f rho_f F_f^T F_f + diag(rho_v), and the constant
 // part of its linear term, q + sum_f rho_f f0_f F_f.  False if Q is not
-// positive definite.
+// positive definite.  With the local line solver (RAW_LOCAL) Q itself is
+// kept in P's place and need not be definite.
 ACOPF_HD bool prep_line(const Workspace& w, int l) {
   const int L = w.n_line;
   const double* d = w.line;
@@ -327,11 +329,16 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) Q[i][i] += w.rho_l[lc8(l, 4 + i)];
-  double Lc[4][4], Pinv[4][4];
-  const bool ok = chol4(Q, Lc);
-  chol4_inverse(Lc, Pinv);
   double Pp[10];
-  sym_pack(Pinv, Pp);
+  bool ok = true;
+  if (w.sync->hessian_mode == ACOPF_HESSIAN_RAW_LOCAL) {
+    sym_pack(Q, Pp);
+  } else {
+    double Lc[4][4], Pinv[4][4];
+    ok = chol4(Q, Lc);
+    chol4_inverse(Lc, Pinv);
+    sym_pack(Pinv, Pp);
+  }
 #pragma unroll
   for (int k = 0; k < 10; ++k) w.line_P[k * L + l] = Pp[k];
 #pragma unroll
@@ -399,6 +406,28 @@ ACOPF_HD void line_sweep_store(const Workspace& w, int l, const LineQPResult& re
   }
   w.mu[l] = res.mu[0];
   w.mu[L + l] = res.mu[1];
+}
+
+// Line update with the local solver (hessian mode RAW_LOCAL; line_P holds Q
+// itself): ALM + TRON from the previous sweep's solution and limit-row
+// multipliers.  Not converged counts like an infeasible line (status 2).
+// The sweep kernels that call it are separate instantiations, so that its
+// registers do not weigh on the exact solver's kernels.
+ACOPF_HD int update_line_local(const Workspace& w, int l) {
+  double Qp[10], c[4], lo[4], hi[4], G[2][4], h[2];
+  line_sweep_data(w, l, Qp, c, lo, hi, G, h);
+  const double z0[4] = {w.xl[lc8(l, 4)], w.xl[lc8(l, 5)], w.xl[lc8(l, 6)], w.xl[lc8(l, 7)]};
+  const double u0[2] = {w.mu[l], w.mu[w.n_line + l]};
+  const LineAlmResult a = solve_line_alm(Qp, c, lo, hi, G, h, z0, u0);
+  LineQPResult res;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) res.z[i] = a.z[i];
+  res.mu[0] = a.u[0];
+  res.mu[1] = a.u[1];
+  res.status = a.converged ? 0 : 2;
+  res.mask = 0;
+  line_sweep_store(w, l, res);
+  return res.status;
 }
 
 // Line update of one ADMM sweep (eq. line_kernel): exact minimiser of the

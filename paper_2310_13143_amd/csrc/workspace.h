@@ -49,6 +49,7 @@ struct SyncState {
   int numeric_error;       // non-finite data / vanishing pivot in the QP build
   int nonconvex;           // raw mode: a line matrix failed its Cholesky
   int blocks;              // grid size of the last solve
+  int hessian_mode;        // acopf_hessian_mode of the last QP build
 };
 
 // Per-scenario ADMM and SQP state.

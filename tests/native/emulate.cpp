@@ -115,6 +115,7 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   }
   for (int k = 0; k < ng; ++k) w.bus_gen[fg[g->gen_bus[k]]++] = k;
   int bad = 0;
+  w.sync->hessian_mode = mode;
   for (int l = 0; l < nl; ++l) bad += build_line(*g, *x, delta, mode, w, l) ? 0 : 1;
   for (int k = 0; k < ng; ++k) build_gen(*g, *x, delta, w, k);
   for (int i = 0; i < nb; ++i) build_bus(*g, *x, w, i);
@@ -144,7 +145,8 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   int infeasible = 0;
   for (int k = 0; k < sweeps; ++k) {
     infeasible = 0;
-    for (int l = 0; l < nl; ++l) infeasible += update_line(*g, w, l) != 0;
+    for (int l = 0; l < nl; ++l)
+      infeasible += (mode == ACOPF_HESSIAN_RAW_LOCAL ? update_line_local(w, l) : update_line(*g, w, l)) != 0;
     double r2 = 0.0, s2 = 0.0;
     for (int i = 0; i < nb; ++i) {
       if (g_bus_items == 2)

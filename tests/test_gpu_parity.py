@@ -746,3 +746,105 @@ def test_captured_sqp_loop_with_device_stops_replays_like_eager():
         out_c = dg_c.sqp_outcomes()
         for a, b in zip(out_c, out_e):
             assert (a["done"], a["reason"], a["iterations"]) == (b["done"], b["reason"], b["iterations"]), rep
+
+
+LOCAL_CASES = {"convex": (300.0, 2e4), "nonconvex": (3000.0, 30.0)}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["persistent", "launches", "graph"])
+@pytest.mark.parametrize("case", sorted(LOCAL_CASES))
+def test_local_line_solver_matches_oracle(case, mode):
+    """Sweeps with the paper's local line solver (ALM + TRON on the
+    unmodified line Hessians, hessian mode RAW_LOCAL) against the oracle's
+    ADMM with the same solver.  In the nonconvex case (line multipliers of
+    scale 3000, penalties 30) most line matrices are indefinite: the exact
+    solver's RAW mode refuses them, the local solver proceeds."""
+    from paper_2310_13143_amd import AcopfError
+    print(f"[gpu] local line solver {case} mode={mode}", flush=True)
+    pi_scale, rho_v = LOCAL_CASES[case]
+    g = grid_14()
+    x, pi = start_point(g, pi_scale=pi_scale, seed=5)
+    delta = 0.05
+    rho = admm.Rho.scalar(g, rho_v)
+    Q = qpm.build_qp(g, x, pi, delta, "raw")
+    lam_min = np.linalg.eigvalsh(admm.line_matrices(Q, rho)).min(axis=1)
+    assert ((lam_min < 0).sum() >= 5) == (case == "nonconvex")
+    nsw = 20
+    ref = admm.solve(g, Q, rho, nsw, 0.0, 0.0, record=True, line_solver="alm")
+    dg, xi, res, st = _run_gpu(g, x, pi, delta, rho, None, None, nsw, mode=mode, hessian=2)
+    assert res["sweeps"] == nsw
+    assert res["infeasible_lines"] == ref.infeasible_lines
+    _compare_state(st, ref.state, tol=1e-7)
+    assert abs(res["r"] - ref.r) <= 1e-6 * ref.r and abs(res["s"] - ref.s) <= 1e-6 * ref.s
+    if case == "nonconvex":
+        # the same QP with the exact solver's mode stops at the first line
+        dg.qp_build(xi, delta, 1)
+        with pytest.raises(AcopfError) as e:
+            dg.admm_init(*dg.rho_scalar(rho_v))
+            dg.admm_solve(2)
+        assert e.value.code == -3
+        # and a fresh setup goes back to the exact solver's kernels
+        dg2, _, _, st2 = _run_gpu(g, x, pi, delta, admm.Rho.scalar(g, 2e4), None, None, 10, mode=mode, hessian=0)
+        ref2 = admm.solve(g, qpm.build_qp(g, x, pi, delta, "psd"), admm.Rho.scalar(g, 2e4), 10, 0.0, 0.0)
+        _compare_state(st2, ref2.state)
+
+
+def test_local_line_solver_batch_matches_solo_runs():
+    """The local line solver in a batch (per-scenario block tables) gives
+    each scenario's solo run bit for bit."""
+    print("[gpu] local line solver batch", flush=True)
+    grids = _batch_cases()[:2]
+    DeviceGrid = _dev()
+    pts = [start_point(g, pi_scale=3000.0, seed=20 + k) for k, g in enumerate(grids)]
+    nsw = 30
+    dg = DeviceGrid(grids)
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    pi = np.concatenate([p[1] for p in pts])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), pi)
+    dg.qp_build(xb, 0.05, 2)
+    dg.admm_init(*dg.rho_scalar(30.0))
+    dg.admm_solve(nsw, 0.0, 0.0, sweep_mode=1, block_size=64)
+    res = dg.admm_results()
+    st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    for k, g in enumerate(grids):
+        x, pik = pts[k]
+        solo = DeviceGrid(g)
+        xs = solo.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pik)
+        solo.qp_build(xs, 0.05, 2)
+        solo.admm_init(*solo.rho_scalar(30.0))
+        rs = solo.admm_solve(nsw, 0.0, 0.0, sweep_mode=1, block_size=64)
+        ss = {k2: v.cpu().numpy() for k2, v in solo.admm_state().items()}
+        part = _slice_state(st, dg, k, dg.n_gen, dg.n_line, dg.n_bus)
+        for name, a in part.items():
+            b = ss[name].reshape(a.shape) if a.ndim == 2 else ss[name]
+            assert np.array_equal(a, b), (k, name)
+        assert res[k]["sweeps"] == rs["sweeps"] and res[k]["r"] == rs["r"] and res[k]["s"] == rs["s"]
+
+
+def test_sqp_with_local_line_solver_matches_oracle():
+    """Algorithm 1 with the unmodified Hessians and the local line solver on
+    the device against the oracle's SQP with the same settings, iteration by
+    iteration (fixed sweep budget, no early stop)."""
+    from paper_2310_13143_amd import _abi
+    print("[gpu] sqp ring14 local line solver", flush=True)
+    g = grid_14()
+    x0, _ = start_point(g)
+    params = sqp.SqpParams(max_iter=4, max_sweeps=150, eps_pri=0.0, eps_dual=0.0, delta0=0.05, tol_step=0.0,
+                           tol_primal=0.0, tol_dual=0.0, hessian_mode="raw", line_solver="alm")
+    ref = sqp.solve(g, params, x0=x0)
+    dg = _dev()(g)
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, None)
+    rho_g, rho_l = dg.rho_scalar(params.rho)
+    delta = params.delta0
+    for k, rec in enumerate(ref.records):
+        out = dg.sqp_step(x, delta, rho_g, rho_l, mu=params.mu_merit, delta_max=params.delta_max,
+                          hessian_mode=_abi.HESSIAN_RAW_LOCAL, warm_start=k > 0, max_sweeps=params.max_sweeps,
+                          eps=0.0, sweep_mode=_abi.SWEEP_LAUNCHES)
+        assert bool(out["accepted"]) == rec.accepted, k
+        assert abs(out["ared"] - rec.ared) <= 1e-6 * (1.0 + abs(rec.ared)), (k, out["ared"], rec.ared)
+        assert abs(out["pred"] - rec.pred) <= 1e-6 * (1.0 + abs(rec.pred)), (k, out["pred"], rec.pred)
+        assert abs(out["delta"] - rec.delta) <= 1e-12 * rec.delta, k
+        delta = out["delta"]
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    for name in ("pg", "qg", "w", "th", "wR", "wI"):
+        assert rel_err(xf[name], getattr(ref.x, name)) <= 1e-7, name

@@ -362,3 +362,43 @@ def test_line_qp_vertex_with_a_fifth_violated_constraint(emu, feasible):
     else:
         assert not feas.any()
         assert (st == 1).all()
+
+
+@pytest.mark.parametrize("pi_scale,rho", [(300.0, 2e4), (3000.0, 30.0)])
+def test_local_line_solver_sweeps_match_oracle(emu, pi_scale, rho):
+    """Sweeps with the unmodified line Hessians solved by the paper's local
+    method (ALM + TRON, hessian mode RAW_LOCAL) against the oracle's ADMM
+    with the same line solver.  At rho = 30 and with line multipliers pi of
+    scale 3000, most line subproblems are nonconvex (the exact solver would
+    fail on them)."""
+    g = grid_14()
+    delta = 0.05
+    x, pi = _setup(g, delta, pi_scale, 5)
+    Q = qpm.build_qp(g, x, pi, delta, "raw")
+    R = admm.Rho.scalar(g, rho)
+    lam_min = np.linalg.eigvalsh(admm.line_matrices(Q, R)).min(axis=1)
+    if rho < 1e3:
+        assert (lam_min < 0).sum() >= 5
+    nsw = 20
+    ref = admm.solve(g, Q, R, nsw, 0.0, 0.0, record=True, line_solver="alm")
+    hg = HostGrid(g)
+    cx, _ = hg.iterate(x, pi)
+    ws = np.zeros(emu.emu_workspace_bytes(g.n_bus, g.n_line, g.n_gen) // 8 + 64)
+    rho_g = np.full(2 * g.n_gen, rho); rho_l = np.full(8 * g.n_line, rho)
+    rs = np.zeros(2 * nsw)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    rc = emu.emu_run(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.c_double(delta), 2, ptr(rho_g), ptr(rho_l),
+                     None, None, nsw, ctypes.c_void_p(base), None, ptr(rs))
+    assert rc % 10000 == ref.infeasible_lines  # lines whose local solve did not converge in the last sweep
+    lay = _layout(emu, g, base)
+    slots = [emu.emu_slot8(k) for k in range(8)]
+    st = ref.state
+
+    def close(a, b, tol):
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= tol * scale, (np.abs(a - b).max(), scale)
+
+    close(lay("xl", 8 * g.n_line).reshape(-1, 8)[:, slots], st.xl, 1e-7)
+    close(lay("lam_l", 8 * g.n_line).reshape(-1, 8)[:, slots], st.lam_l, 1e-7)
+    close(lay("dw", g.n_bus), st.dw, 1e-7)
+    close(lay("nu", 2 * g.n_bus).reshape(2, -1).T, st.nu, 1e-7)

@@ -1,0 +1,103 @@
+"""Pins of the local line solver (ALM + TRON, Section IV-B2): on convex line
+subproblems it reaches the exact minimiser of the enumeration; on
+nonconvex ones it ends at a point that satisfies the first- and
+second-order conditions of a local minimiser; a hand case with negative
+curvature ends at the local minimiser its descent path leads to."""
+import numpy as np
+import pytest
+
+from oracle import alm, lineqp
+
+
+def _random_lines(rng, n, convex=True):
+    A = rng.standard_normal((n, 4, 4))
+    Q = A @ np.swapaxes(A, 1, 2) + 0.3 * np.eye(4)
+    if not convex:
+        Q = Q - rng.uniform(1.0, 4.0, (n, 1, 1)) * np.eye(4)
+    Q[: n // 2] *= rng.uniform(1e2, 1e6, (n // 2, 1, 1))
+    c = rng.standard_normal((n, 4)) * np.abs(Q).max(axis=(1, 2))[:, None] * rng.uniform(0.01, 2, (n, 1))
+    lo = -rng.uniform(0.01, 0.3, (n, 4))
+    hi = rng.uniform(0.01, 0.3, (n, 4))
+    G = rng.standard_normal((n, 2, 4))
+    h = rng.uniform(0.01, 0.2, (n, 2))
+    return Q, c, lo, hi, G, h
+
+
+def test_alm_reaches_the_exact_minimiser_of_convex_lines():
+    rng = np.random.default_rng(11)
+    Q, c, lo, hi, G, h = _random_lines(rng, 200)
+    zr, mur, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h)
+    assert feas.all()
+    for k in range(Q.shape[0]):
+        r = alm.solve_line(Q[k], c[k], lo[k], hi[k], G[k], h[k])
+        assert r.converged, k
+        assert np.abs(r.z - zr[k]).max() <= 1e-7 * (1 + np.abs(zr[k]).max()), k
+        assert np.abs(r.u - mur[k]).max() <= 1e-5 * (1 + np.abs(mur[k]).max()), k
+
+
+def _kkt(Q, c, lo, hi, G, h, z, u, tol=1e-7):
+    """First- and second-order conditions of a local minimiser of
+    0.5 z^T Q z + c^T z on the box with G z <= h, multipliers u of the rows."""
+    zs = 1 + np.abs(lo).max() + np.abs(hi).max()
+    gs = 1 + np.abs(Q).max() * zs + np.abs(c).max()
+    g = G @ z - h
+    assert (z >= lo - tol * zs).all() and (z <= hi + tol * zs).all()
+    assert (g <= tol * (1 + np.abs(G).sum(1) * zs + np.abs(h))).all()
+    assert (u >= 0).all()
+    assert np.all(np.abs(u * g) <= tol * gs * zs)
+    grad = Q @ z + c + G.T @ u           # = bound multipliers' share: lower bounds push up, upper down
+    atlo = z <= lo + tol * zs
+    athi = z >= hi - tol * zs
+    free = ~atlo & ~athi
+    assert np.all(np.abs(grad[free]) <= tol * gs)
+    assert np.all(grad[atlo & ~athi] >= -tol * gs) and np.all(grad[athi & ~atlo] <= tol * gs)
+    # second order: Q on the free variables, restricted to directions that keep the active rows
+    act = (u > tol * gs) | (np.abs(g) <= tol * (1 + np.abs(h)))
+    Nf = G[act][:, free]
+    if free.sum() > 0:
+        if Nf.shape[0] > 0:
+            _, sv, vt = np.linalg.svd(Nf)
+            rank = int((sv > 1e-12 * max(1.0, sv.max(initial=0))).sum())
+            Z = vt[rank:].T
+        else:
+            Z = np.eye(int(free.sum()))
+        if Z.shape[1] > 0:
+            Hr = Z.T @ Q[np.ix_(free, free)] @ Z
+            assert np.linalg.eigvalsh(Hr).min() >= -tol * np.abs(Q).max()
+
+
+def test_alm_ends_at_local_minimisers_of_nonconvex_lines():
+    rng = np.random.default_rng(12)
+    Q, c, lo, hi, G, h = _random_lines(rng, 200, convex=False)
+    assert (np.linalg.eigvalsh(Q).min(axis=1) < 0).sum() > 150
+    n_conv = 0
+    for k in range(Q.shape[0]):
+        r = alm.solve_line(Q[k], c[k], lo[k], hi[k], G[k], h[k])
+        if not r.converged:
+            continue
+        n_conv += 1
+        _kkt(Q[k], c[k], lo[k], hi[k], G[k], h[k], r.z, r.u)
+        # no better feasible point nearby (random small moves inside the box and rows)
+        phi = lambda z: 0.5 * z @ Q[k] @ z + c[k] @ z
+        for _ in range(20):
+            d = rng.standard_normal(4) * 1e-4 * (hi[k] - lo[k])
+            zn = np.clip(r.z + d, lo[k], hi[k])
+            if np.all(G[k] @ zn <= h[k]):
+                assert phi(zn) >= phi(r.z) - 1e-9 * (1 + abs(phi(r.z)))
+    assert n_conv >= 190
+
+
+def test_negative_curvature_hand_case():
+    """phi(z) = -0.5 z0^2 + 0.1 z0 + 0.5 (z1^2 + z2^2 + z3^2) on [-1, 2]^4
+    with rows that never bind: from z = 0 the descent direction is -z0, so
+    the solver ends at the local minimiser z0 = -1 (phi = -0.6; the other
+    local minimiser z0 = 2 has phi = -1.8), the others at 0."""
+    Q = np.diag([-1.0, 1.0, 1.0, 1.0])
+    c = np.array([0.1, 0.0, 0.0, 0.0])
+    lo, hi = np.full(4, -1.0), np.full(4, 2.0)
+    G = np.array([[1.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 1.0]])
+    h = np.array([10.0, 10.0])
+    r = alm.solve_line(Q, c, lo, hi, G, h)
+    assert r.converged
+    np.testing.assert_allclose(r.z, [-1.0, 0.0, 0.0, 0.0], atol=1e-9)
+    np.testing.assert_allclose(r.u, [0.0, 0.0], atol=1e-12)
