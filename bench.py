@@ -40,7 +40,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("e893c3b305633f9a", 118143528)}
+MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("ef6d6795fb366dfa", 119054501)}
 
 
 def sweep_sources_sha() -> str:
