@@ -23,7 +23,9 @@ multipliers of the bounds; lines without a feasible point are flagged.
 ``limit_relaxation`` gives the shift of the limit rows that the QP build
 applies to a line whose box and rows have no common point (the paper's
 ADMM keeps progressing on such QPs, Section V, because its augmented
-Lagrangian line solver relaxes the limits instead of failing).
+Lagrangian line solver does not fail on them: it ends at the point of
+least squared violation, ``min_violation``, and the shift reproduces that
+limit for the exact solver).
 
 Test infrastructure only (see the package docstring).
 """
@@ -65,8 +67,7 @@ def _feasible(z, lo, hi, G, h, tol):
     return ok & np.all(g <= h + tol * rs, axis=-1)
 
 
-RELAX_REL = 0.1    # margin of the relaxation, relative to the violation
-RELAX_ABS = 1e-9   # and absolute, per unit of 1 + |h_0| + |h_1|
+RELAX_ABS = 1e-9   # rounding guard of the relaxation, per unit of the rows' scale
 
 
 def min_max_violation(lo, hi, G, h):
@@ -103,13 +104,77 @@ def min_max_violation(lo, hi, G, h):
     return best
 
 
+def _segment_min(a, e, h):
+    """min over t in [0, 1] of f(t) = 0.5 sum_r max(0, a_r + t e_r - h_r)^2
+    (a, e, h of shape (..., 2)); returns (f_min, t_min).  f is convex and
+    piecewise quadratic: its minimiser is an end point, a breakpoint
+    a_r + t e_r = h_r, or the stationary point of one of its pieces (rows
+    {0}, {1} or {0, 1} positive)."""
+    b = a - h
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cand = [np.zeros(b.shape[:-1]), np.ones(b.shape[:-1])]
+        for r in range(2):
+            cand.append(np.where(e[..., r] != 0.0, -b[..., r] / e[..., r], 0.0))      # breakpoint / piece {r}
+        ee = (e * e).sum(-1)
+        cand.append(np.where(ee > 0.0, -(b * e).sum(-1) / ee, 0.0))               # piece {0, 1}
+    best_f = np.full(b.shape[:-1], np.inf)
+    best_t = np.zeros(b.shape[:-1])
+    for t in cand:
+        t = np.clip(t, 0.0, 1.0)
+        f = 0.5 * (np.maximum(b + t[..., None] * e, 0.0) ** 2).sum(-1)
+        better = f < best_f
+        best_f = np.where(better, f, best_f)
+        best_t = np.where(better, t, best_t)
+    return best_f, best_t
+
+
+def min_violation(lo, hi, G, h):
+    """v* = (G z* - h)^+ for z* minimising 0.5 ||(G z - h)^+||^2 over the box,
+    per line (the violation the paper's augmented Lagrangian line solver
+    drives its iterates to when the box and the rows have no common point:
+    its subproblems' penalty terms weigh this sum of squares with a penalty
+    parameter that goes to zero).  v* is unique, z* need not be.
+
+    The objective depends on z only through y = G z, which ranges over the
+    polygon Z = G [lo, hi] (the convex hull of the 16 images of the box
+    vertices).  When the minimum is positive it lies on the boundary of Z
+    (in the interior a move against the gradient (y - h)^+ would still
+    decrease it); every edge of Z is a segment between two of the 16
+    images, all of which lie in Z, so the minimum over the 120 segments is
+    the minimum over Z.  Lines whose box and rows intersect (min_max_violation
+    <= 0) get v* = 0."""
+    n = lo.shape[0]
+    corners = np.array(list(itertools.product((0, 1), repeat=4)), dtype=bool)   # (16, 4)
+    pts = np.stack([np.einsum("nrj,nj->nr", G, np.where(cb[None], hi, lo)) for cb in corners], 1)  # (n, 16, 2)
+    best_f = np.full(n, np.inf)
+    best_y = np.zeros((n, 2))
+    for i, j in itertools.combinations(range(16), 2):
+        a, e = pts[:, i], pts[:, j] - pts[:, i]
+        f, t = _segment_min(a, e, h)
+        better = f < best_f
+        best_f = np.where(better, f, best_f)
+        best_y = np.where(better[:, None], a + t[:, None] * e, best_y)
+    v = np.maximum(best_y - h, 0.0)
+    return np.where((min_max_violation(lo, hi, G, h) > 0.0)[:, None], v, 0.0)
+
+
+def relax_guard(lo, hi, G, h):
+    """RELAX_ABS times the scale of the rows' terms, 1 + |h_0| + |h_1| +
+    sum_j (|G_0j| + |G_1j|) max(|lo_j|, |hi_j|): a bound on the rounding
+    error of v* many times over."""
+    zmax = np.maximum(np.abs(lo), np.abs(hi))
+    return RELAX_ABS * (1.0 + np.abs(h).sum(1) + np.einsum("nrj,nj->n", np.abs(G), zmax))
+
+
 def limit_relaxation(lo, hi, G, h):
-    """Shift added to both limit rows of each line: 0 when the box and the
-    rows G z <= h have a common point (t* <= 0), else t* enlarged by a
-    margin, (1 + RELAX_REL) t* + RELAX_ABS (1 + |h_0| + |h_1|), so that the
-    relaxed set has an interior."""
-    t = min_max_violation(lo, hi, G, h)
-    return np.where(t > 0.0, (1.0 + RELAX_REL) * t + RELAX_ABS * (1.0 + np.abs(h).sum(1)), 0.0)
+    """Shift (n, 2) added to the limit rows of each line: 0 when the box and
+    the rows G z <= h have a common point, else v* (``min_violation``) plus
+    the rounding guard on both rows.  The QP on the relaxed rows then has as
+    its minimiser the limit of the paper's augmented Lagrangian line solver
+    (the minimiser over the points of least violation), up to the guard."""
+    v = min_violation(lo, hi, G, h)
+    infeasible = (v > 0.0).any(1)
+    return np.where(infeasible[:, None], v + relax_guard(lo, hi, G, h)[:, None], 0.0)
 
 
 def solve_line_qps(Q, c, lo, hi, G, h, tol: float = FEAS_TOL):

@@ -45,7 +45,7 @@ class LineQP:
     h: np.ndarray    # (L, 2)
     pk: np.ndarray   # (L, 4) flows at the iterate
     c0: np.ndarray   # (L,) 0.5 b^T H b
-    relax: np.ndarray  # (L,) shift already added to both entries of h (lineqp.limit_relaxation)
+    relax: np.ndarray  # (L, 2) shift already added to h (lineqp.limit_relaxation)
 
 
 @dataclass
@@ -198,10 +198,11 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
     if c_shift is not None:
         # c13 + e13 - 2 p_ij dp_ij - 2 q_ij dq_ij >= 0  <=>  G z <= h + e13
         h = h + np.asarray(c_shift, dtype=np.float64)[:, 2:4]
-    # a line whose box and limit rows do not intersect gets both rows relaxed
-    # by the smallest common amount (plus a margin) that makes them intersect
+    # a line whose box and limit rows do not intersect gets its rows relaxed
+    # by its least-squares violation (plus a rounding guard): the QP's line
+    # minimiser is then the limit of the paper's line solver on that line
     relax = limit_relaxation(lo, hi, G, h)
-    h = h + relax[:, None]
+    h = h + relax
 
     # generators (eq. gen_kernel bounds)
     fp = 2 * grid.cost2 * x.pg + grid.cost1

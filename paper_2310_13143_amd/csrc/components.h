@@ -27,17 +27,44 @@ ACOPF_HD size_t lc4(int l, int k) { return 4 * (size_t)l + k; }
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
+// phi(n) = sum_d min(g_d lo_d, g_d hi_d) - n . h with g = n_0 G_0 + n_1 G_1:
+// the smallest value of n . (G z - h) over the box.
+ACOPF_HD double box_support(const double lo[4], const double hi[4], const double G[2][4], const double h[2],
+                            double n0, double n1) {
+  double phi = -n0 * h[0] - n1 * h[1];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const double gd = n0 * G[0][d] + n1 * G[1][d];
+    phi += fmin(gd * lo[d], gd * hi[d]);
+  }
+  return phi;
+}
+
 // Relaxation of the limit rows of a line whose box lo <= z <= hi and rows
-// G z <= h have no common point.  t* = min over the box of max_r (G_r z -
-// h_r) is an LP; by LP duality it equals the maximum over a in [0, 1] of the
-// concave piecewise-linear phi(a) = sum_d min(g_d lo_d, g_d hi_d) - a h_0 -
-// (1 - a) h_1 with g = a G_0 + (1 - a) G_1, whose maximum lies at a = 0, a =
-// 1 or a breakpoint where some g_d vanishes.  Returns the shift added to
-// both rows: 0 if t* <= 0, else 1.1 t* + 1e-9 (1 + |h_0| + |h_1|), a
-// margin that leaves the relaxed set an interior.  (The paper's ADMM keeps
-// progressing on QPs without a feasible point, Section V; this is the
-// relaxation its augmented Lagrangian line solver is read to perform.)
-ACOPF_HD double limit_relaxation(const double lo[4], const double hi[4], const double G[2][4], const double h[2]) {
+// G z <= h have no common point (the paper's ADMM keeps progressing on QPs
+// without a feasible point, Section V: its augmented Lagrangian line solver
+// ends at the point of least squared violation).  Writes shift[r] = v_r +
+// guard to both rows, 0 for lines with a common point; returns true if
+// relaxed.
+//  * Common point: t* = min over the box of max_r (G_r z - h_r) <= 0.  By LP
+//    duality t* is the maximum of phi over n = (a, 1 - a), a in [0, 1]; phi
+//    is concave and piecewise linear, so the maximum lies at a = 0, a = 1
+//    or a breakpoint where some g_d vanishes.
+//  * v = (G z* - h)^+ for z* minimising ||(G z - h)^+||^2 over the box is
+//    the vector from the quadrant {y <= h} to its nearest point of the
+//    polygon G [lo, hi]; its length is the largest phi(n) over unit n >= 0
+//    and its direction the maximising n (distance between convex sets).
+//    On the quarter circle n = (cos th, sin th) phi is linear, n . c, within
+//    each sector between breakpoint angles (sign pattern of g fixed), so its
+//    maximum lies at th = 0, th = pi/2, a breakpoint, or a sector's
+//    stationary direction c / |c|.  Each breakpoint and end angle gives the
+//    sign patterns on both of its sides; phi itself is evaluated at every
+//    candidate.
+//  * guard = 1e-9 (1 + |h_0| + |h_1| + sum_d (|G_0d| + |G_1d|) max(|lo_d|,
+//    |hi_d|)) on both rows, many times the rounding error of v.
+ACOPF_HD bool limit_relaxation(const double lo[4], const double hi[4], const double G[2][4], const double h[2],
+                               double shift[2]) {
+  shift[0] = shift[1] = 0.0;
   double alpha[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
@@ -47,17 +74,58 @@ ACOPF_HD double limit_relaxation(const double lo[4], const double hi[4], const d
   }
   double t = -1e300;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const double a = alpha[k];
-    double phi = -a * h[0] - (1.0 - a) * h[1];
+  for (int k = 0; k < 6; ++k) t = fmax(t, box_support(lo, hi, G, h, alpha[k], 1.0 - alpha[k]));
+  if (!(t > 0.0)) return false;
+  // candidate angles: the ends of the quarter circle and the breakpoints in it
+  constexpr double kHalfPi = 1.5707963267948966192313216916398;
+  constexpr double kPi = 3.1415926535897932384626433832795;
+  double th[6] = {0.0, kHalfPi, -1.0, -1.0, -1.0, -1.0};
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const double gd = a * G[0][d] + (1.0 - a) * G[1][d];
-      phi += fmin(gd * lo[d], gd * hi[d]);
-    }
-    t = fmax(t, phi);
+  for (int d = 0; d < 4; ++d) {
+    if (G[0][d] == 0.0 && G[1][d] == 0.0) continue;
+    double a = atan2(-G[0][d], G[1][d]);
+    if (a < 0.0) a += kPi;
+    if (a <= kHalfPi) th[2 + d] = a;
   }
-  return (t > 0.0) ? 1.1 * t + 1e-9 * (1.0 + fabs(h[0]) + fabs(h[1])) : 0.0;
+  double best = -1e300, bn0 = 1.0, bn1 = 0.0;
+  auto consider = [&](double n0, double n1) {
+    const double phi = box_support(lo, hi, G, h, n0, n1);
+    if (phi > best) {
+      best = phi;
+      bn0 = n0;
+      bn1 = n1;
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (th[k] < 0.0) continue;
+    const double n0 = cos(th[k]), n1 = sin(th[k]);
+    consider(n0, n1);
+    // the sectors on both sides: the sign of g_d there, from g_d at th or,
+    // where g_d vanishes at th, from its derivative along the circle
+#pragma unroll
+    for (int side = -1; side <= 1; side += 2) {
+      double c0 = -h[0], c1 = -h[1];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        double gd = n0 * G[0][d] + n1 * G[1][d];
+        if (th[2 + d] == th[k]) gd = side * (-n1 * G[0][d] + n0 * G[1][d]);
+        const double sel = (gd >= 0.0) ? lo[d] : hi[d];
+        c0 += G[0][d] * sel;
+        c1 += G[1][d] * sel;
+      }
+      const double nc = sqrt(c0 * c0 + c1 * c1);
+      if (c0 >= 0.0 && c1 >= 0.0 && nc > 0.0) consider(c0 / nc, c1 / nc);
+    }
+  }
+  double scale = 1.0 + fabs(h[0]) + fabs(h[1]);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) scale += (fabs(G[0][d]) + fabs(G[1][d])) * fmax(fabs(lo[d]), fabs(hi[d]));
+  const double guard = 1e-9 * scale;
+  const double dist = fmax(best, 0.0);
+  shift[0] = dist * bn0 + guard;
+  shift[1] = dist * bn1 + guard;
+  return true;
 }
 
 // QP data of line l at the iterate (Sections III-B, III-C and IV-B2).
@@ -216,9 +284,10 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
     hr[0] += cshift[2];
     hr[1] += cshift[3];
   }
-  const double shift = limit_relaxation(lo, hi, Gr, hr);
-  const double hr0 = hr[0] + shift, hr1 = hr[1] + shift;
-  if (relaxed) *relaxed = shift > 0.0;
+  double shift[2];
+  const bool rel = limit_relaxation(lo, hi, Gr, hr, shift);
+  const double hr0 = hr[0] + shift[0], hr1 = hr[1] + shift[1];
+  if (relaxed) *relaxed = rel;
   ok = ok && isfinite(hr0) && isfinite(hr1) && isfinite(c0);
 
   double* d = w.line;

@@ -36,7 +36,7 @@ void emu_limit_relaxation(int n, const double* lo, const double* hi, const doubl
   for (int k = 0; k < n; ++k) {
     const double Gk[2][4] = {{G[8 * k + 0], G[8 * k + 1], G[8 * k + 2], G[8 * k + 3]},
                              {G[8 * k + 4], G[8 * k + 5], G[8 * k + 6], G[8 * k + 7]}};
-    out[k] = limit_relaxation(lo + 4 * k, hi + 4 * k, Gk, h + 2 * k);
+    limit_relaxation(lo + 4 * k, hi + 4 * k, Gk, h + 2 * k, out + 2 * k);
   }
 }
 

@@ -280,21 +280,29 @@ def test_rgg2000_sweeps_match_oracle():
 
 def test_relaxed_lines_match_oracle():
     """At a trust radius too small for some lines to reach their linearised
-    limits, the build relaxes those lines' rows like the oracle and every
-    line subproblem has a solution."""
+    limits, the build relaxes those lines' rows like the oracle (to their
+    least-squares violation) and every line subproblem has a solution.  The
+    relaxed lines' subproblems are ill-conditioned (their rows bind along
+    directions in which their coefficients are tiny, with multipliers up to
+    about 1e8), so FP64 solvers with KKT tolerances of 1e-12 to 1e-10 give
+    points up to 1e-4 of the box width apart whose objectives agree to a few
+    parts in 1e8; the state is compared per column to 1e-4, the bus values
+    to 1e-6."""
     print("[gpu] rgg2000 relaxed lines", flush=True)
     g = grid_2000()
     x, pi = start_point(g, pi_scale=20.0, seed=2)
     rho = admm.Rho.scalar(g, 2e4)
     delta = 0.00625
     Q = qpm.build_qp(g, x, pi, delta, "psd")
-    n_relaxed = int((Q.line.relax > 0).sum())
+    n_relaxed = int((Q.line.relax > 0).any(1).sum())
     assert n_relaxed > 10
     ref = admm.solve(g, Q, rho, 6, 0.0, 0.0)
     assert ref.infeasible_lines == 0
     _, _, res, st = _run_gpu(g, x, pi, delta, rho, None, None, 6, mode=1)
     assert res["relaxed_lines"] == n_relaxed and res["infeasible_lines"] == 0
-    _compare_state(st, ref.state)
+    _compare_state(st, ref.state, tol=1e-4)
+    assert rel_err_cols(st["dw"], ref.state.dw) <= 1e-6
+    assert rel_err_cols(st["nu"].reshape(2, -1).T, ref.state.nu) <= 1e-6
 
 
 def test_rgg70000_sampled_line_and_bus_updates():

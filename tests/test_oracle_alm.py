@@ -101,3 +101,51 @@ def test_negative_curvature_hand_case():
     assert r.converged
     np.testing.assert_allclose(r.z, [-1.0, 0.0, 0.0, 0.0], atol=1e-9)
     np.testing.assert_allclose(r.u, [0.0, 0.0], atol=1e-12)
+
+
+def test_relaxed_rows_give_the_local_solvers_point_on_lines_without_a_feasible_point():
+    """The QP build relaxes the limit rows of lines whose box and rows have
+    no common point (Section V: the paper's ADMM keeps progressing on such
+    QPs).  Pin of that reading: on the lines of the 2,000-bus grid without a
+    feasible point at trust radius 0.00625, the exact minimiser on the
+    relaxed rows is the point the paper's local method (ALM + TRON on the
+    original rows) runs to; the penalty parameter then falls to zero and the
+    iterates approach the minimiser over the points of least violation."""
+    from oracle import admm, qp as qpm
+    from synth.grids import grid_2000
+    from tests._util import start_point
+    g = grid_2000()
+    x, pi = start_point(g, pi_scale=20.0, seed=2)
+    Q = qpm.build_qp(g, x, pi, 0.00625, "psd")
+    L = Q.line
+    idx = np.nonzero((L.relax > 0).any(1))[0]
+    assert idx.size > 50
+    rho = admm.Rho.scalar(g, 2e4)
+    QL = admm.line_matrices(Q, rho)[idx]
+    # the line data of a first sweep from zero multipliers and bus values
+    c = (L.q + np.einsum("lf,lfi->li", rho.l[:, :4] * L.f0, L.F))[idx]
+    h0 = (L.h - L.relax)[idx]
+    lo, hi, G = L.lo[idx], L.hi[idx], L.G[idx]
+    assert (lineqp.min_max_violation(lo, hi, G, h0) > 0).all()
+    z, _, _, feas = lineqp.solve_line_qps(QL, c, lo, hi, G, L.h[idx])
+    assert feas.all()
+    # the other candidate reading: both rows shifted by the smallest common
+    # violation t* (plus 10%), the minimiser over the box's points whose
+    # larger violation is least
+    t = lineqp.min_max_violation(lo, hi, G, h0)
+    z_mm, _, _, feas_mm = lineqp.solve_line_qps(QL, c, lo, hi, G, h0 + 1.1 * t[:, None])
+    assert feas_mm.all()
+    err, err_mm = [], []
+    for k in range(idx.size):
+        r = alm.solve_line(QL[k], c[k], lo[k], hi[k], G[k], h0[k])
+        assert not r.converged          # no feasible point: the penalty runs down
+        width = np.abs(hi[k] - lo[k]).max()
+        err.append(np.abs(r.z - z[k]).max() / width)
+        err_mm.append(np.abs(r.z - z_mm[k]).max() / width)
+    err, err_mm = np.array(err), np.array(err_mm)
+    # the local method stalls near the limit once its penalty parameter is
+    # tiny (the subproblems are then ill-conditioned), a few parts in 1e7 of
+    # the box width at the median; the min-max reading is tens of percent away
+    assert np.median(err) < 1e-6 and np.percentile(err, 90) < 1e-4 and err.max() < 1e-3, \
+        (np.median(err), np.percentile(err, 90), err.max())
+    assert np.median(err_mm) > 1e-2

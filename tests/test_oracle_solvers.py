@@ -65,36 +65,115 @@ def test_line_qp_unconstrained_and_infeasible():
     assert not feas.any()
 
 
-def test_limit_relaxation_against_linprog_and_hand_case():
-    """t* = min over the box of the larger row violation: the oracle's vertex
-    and edge enumeration against SciPy's LP solver; the shift is zero for
-    lines with a feasible point and makes the others feasible."""
-    from scipy.optimize import linprog
-    rng = np.random.default_rng(0)
-    n = 200
+def _relax_cases(n, seed):
+    rng = np.random.default_rng(seed)
     lo = -rng.uniform(0, 0.1, (n, 4)); hi = rng.uniform(0, 0.1, (n, 4))
     lo[::7, 1] = 0.0; hi[::7, 1] = 0.0
     G = rng.standard_normal((n, 2, 4)); h = rng.uniform(-0.3, 0.1, (n, 2))
     G[::11, 1] = 0.0
+    return lo, hi, G, h
+
+
+def test_min_max_violation_against_linprog():
+    """t* = min over the box of the larger row violation (the test for a
+    common point of box and rows): the oracle's vertex and edge enumeration
+    against SciPy's LP solver."""
+    from scipy.optimize import linprog
+    lo, hi, G, h = _relax_cases(200, 0)
     t = lineqp.min_max_violation(lo, hi, G, h)
-    for k in range(n):
+    for k in range(lo.shape[0]):
         r = linprog(np.r_[np.zeros(4), 1.0], A_ub=np.hstack([G[k], -np.ones((2, 1))]), b_ub=h[k],
                     bounds=[(lo[k, i], hi[k, i]) for i in range(4)] + [(None, None)], method="highs")
         assert r.status == 0 and abs(t[k] - r.fun) < 1e-12
     assert 0.2 < (t > 0).mean() < 0.9
-    shift = lineqp.limit_relaxation(lo, hi, G, h)
-    assert np.all(shift[t <= 0] == 0.0)
-    assert np.all(shift[t > 0] > t[t > 0])
-    Q = np.broadcast_to(np.eye(4), (n, 4, 4)).copy()
-    c = rng.standard_normal((n, 4))
-    _, _, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h + shift[:, None])
-    assert feas.all()
-    # box [0, 1]^4, rows sum(z) <= -1 and 0 <= 1: t* = 1 at z = 0
+
+
+def test_min_violation_against_a_qp_solver():
+    """v* = (G z* - h)^+ at the least-squares violation over the box: the
+    oracle's minimum over the segments of the polygon G [lo, hi] against
+    SciPy's SLSQP on the equivalent QP min 0.5 |s|^2 s.t. s >= G z - h,
+    s >= 0, lo <= z <= hi (s is unique)."""
+    from scipy.optimize import minimize
+    lo, hi, G, h = _relax_cases(120, 5)
+    v = lineqp.min_violation(lo, hi, G, h)
+    t = lineqp.min_max_violation(lo, hi, G, h)
+    assert np.all(v[t <= 0] == 0.0) and np.all(v[t > 0].max(1) > 0)
+    n_both = 0
+    for k in np.nonzero(t > 0)[0]:
+        cons = [{"type": "ineq", "fun": lambda u, k=k: u[4:] - (G[k] @ u[:4] - h[k]), "jac":
+                 lambda u, k=k: np.hstack([-G[k], np.eye(2)])}]
+        best = None
+        for s0 in range(3):
+            z0 = lo[k] + np.random.default_rng(s0).uniform(0, 1, 4) * (hi[k] - lo[k])
+            u0 = np.r_[z0, np.maximum(G[k] @ z0 - h[k], 0) + 0.1]
+            r = minimize(lambda u: 0.5 * u[4:] @ u[4:], u0, jac=lambda u: np.r_[np.zeros(4), u[4:]],
+                         bounds=[(lo[k, i], hi[k, i]) for i in range(4)] + [(0, None)] * 2,
+                         constraints=cons, method="SLSQP", options={"ftol": 1e-15, "maxiter": 500})
+            if best is None or r.fun < best.fun:
+                best = r
+        s = np.maximum(best.x[4:], 0)
+        assert np.abs(v[k] - s).max() <= 1e-6 * (1 + np.abs(s).max()), (k, v[k], s)
+        n_both += int((v[k] > 0).all())
+    assert n_both >= 10
+
+
+def test_limit_relaxation_hand_cases():
+    """Hand cases of the relaxation.  (1) Box [0, 1]^4, rows sum(z) <= -1
+    and 0 <= 1: z = 0 violates the first row by 1, v* = (1, 0).  (2) One
+    variable on [-2, 2] (the others fixed at 0), rows 2 z <= -2 and -z <=
+    -0.5: for z in [-1, 0.5] both rows are violated, 0.5 ((2z + 2)^2 +
+    (0.5 - z)^2) has derivative 5 z + 3.5 and is least at z = -0.7,
+    v* = (0.6, 1.2), while the smallest common violation is t* = 1 at
+    z = -0.5.  The shifted rows then admit the
+    box's points of least violation only."""
     lo1, hi1 = np.zeros((1, 4)), np.ones((1, 4))
     G1 = np.zeros((1, 2, 4)); G1[0, 0] = 1.0
     h1 = np.array([[-1.0, 1.0]])
     assert lineqp.min_max_violation(lo1, hi1, G1, h1)[0] == 1.0
-    assert lineqp.limit_relaxation(lo1, hi1, G1, h1)[0] == pytest.approx(1.1 + 3e-9, rel=1e-15)
+    np.testing.assert_allclose(lineqp.min_violation(lo1, hi1, G1, h1)[0], [1.0, 0.0], atol=1e-15)
+    guard = 1e-9 * (1 + 2 + 4)
+    np.testing.assert_allclose(lineqp.limit_relaxation(lo1, hi1, G1, h1)[0], [1.0 + guard, guard], rtol=1e-14)
+    lo2, hi2 = np.array([[-2.0, 0, 0, 0]]), np.array([[2.0, 0, 0, 0]])
+    G2 = np.zeros((1, 2, 4)); G2[0, 0, 0] = 2.0; G2[0, 1, 0] = -1.0
+    h2 = np.array([[-2.0, -0.5]])
+    assert lineqp.min_max_violation(lo2, hi2, G2, h2)[0] == pytest.approx(1.0, abs=1e-15)
+    np.testing.assert_allclose(lineqp.min_violation(lo2, hi2, G2, h2)[0], [0.6, 1.2], atol=1e-14)
+    shift = lineqp.limit_relaxation(lo2, hi2, G2, h2)
+    # on the relaxed rows only z = -0.7 (up to the guard) is left
+    Q = np.eye(4)[None]
+    for c0 in (-5.0, 5.0):
+        z, _, _, feas = lineqp.solve_line_qps(Q, np.array([[c0, 0, 0, 0]]), lo2, hi2, G2, h2 + shift)
+        assert feas[0] and abs(z[0, 0] + 0.7) < 1e-7
+
+
+def test_relaxed_rows_admit_only_points_of_least_violation():
+    """On random infeasible lines the QP on the relaxed rows is feasible,
+    and its minimisers (of random objectives) have the least squared
+    violation psi* = 0.5 |v*|^2 of the original rows up to the guard: each
+    row is violated by at most v*_r + guard, so psi <= 0.5 |v* + guard|^2,
+    and no point of the box has psi < psi*."""
+    lo, hi, G, h = _relax_cases(200, 0)
+    shift = lineqp.limit_relaxation(lo, hi, G, h)
+    t = lineqp.min_max_violation(lo, hi, G, h)
+    assert np.all(shift[t <= 0] == 0.0) and np.all(shift[t > 0] > 0.0)
+    v = lineqp.min_violation(lo, hi, G, h)
+    guard = lineqp.relax_guard(lo, hi, G, h)
+    bad = t > 0
+    psi_star = 0.5 * (v ** 2).sum(1)
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        Q = np.broadcast_to(np.eye(4), (lo.shape[0], 4, 4)).copy()
+        c = rng.standard_normal((lo.shape[0], 4))
+        z, _, _, feas = lineqp.solve_line_qps(Q, c, lo, hi, G, h + shift)
+        assert feas.all()
+        viol = np.maximum(np.einsum("nrj,nj->nr", G, z) - h, 0.0)
+        psi = 0.5 * (viol ** 2).sum(1)
+        # the enumeration accepts rows met to FEAS_TOL times their scale
+        tol = lineqp.FEAS_TOL * (1 + np.abs(h) + np.einsum("nrj,nj->nr", np.abs(G), np.abs(z)))
+        slack = guard[:, None] + tol
+        assert np.all(viol[bad] <= v[bad] + slack[bad])
+        assert np.all(psi[bad] <= 0.5 * ((v[bad] + slack[bad]) ** 2).sum(1))
+        assert np.all(psi[bad] >= psi_star[bad] * (1 - 1e-12))
 
 
 def test_gen_update_matches_scalar_minimisation():
