@@ -181,9 +181,15 @@ acopf_status acopf_set_delta(const acopf_grid* grid, const double* delta, void* 
  * by A_ij (Section IV-B2; PSD-projected in ACOPF_HESSIAN_PSD mode), flow
  * map, linearised limits (opfqpc13, opfqpc14), boxes (opfqpc1-4 with the
  * trust region; the reference angle fixed), generator gradients and the
- * bus constants p^{d,(k)}, q^{d,(k)}.  Returns ACOPF_ERR_NUMERIC if a line
- * has |wR cos + wI sin| < 1e-8 at x (after the stream syncs this is
- * reported by the next solve). */
+ * bus constants p^{d,(k)}, q^{d,(k)}.  A line whose box and linearised
+ * limits have no common point gets its limit rows relaxed by the least-
+ * squares violation over the box, plus a rounding guard of 1e-9 of the
+ * rows' scale (the point the paper's augmented Lagrangian line solver runs
+ * to on such a line, Section V; counted in relaxed_lines).  The Hessian
+ * mode also picks the line solver of the solves that follow on this
+ * workspace (exact, or the local ALM + TRON for ACOPF_HESSIAN_RAW_LOCAL).
+ * Returns ACOPF_ERR_NUMERIC if a line has |wR cos + wI sin| < 1e-8 at x
+ * (after the stream syncs this is reported by the next solve). */
 acopf_status acopf_qp_build(const acopf_grid* grid, const acopf_iterate* x, double delta,
                             int32_t hessian_mode, void* workspace, void* stream);
 
@@ -198,8 +204,9 @@ acopf_status acopf_admm_init(const acopf_grid* grid, const double* rho_g, const 
 
 /* Run ADMM sweeps (Algorithm 2) from the workspace state until the stop
  * test of Section IV-B5 holds or max_sweeps: generator closed form (eq.
- * gen_kernel), exact line subproblem (eq. line_kernel, dual active-set
- * method on the 4-variable strictly convex QP), bus closed form (eq.
+ * gen_kernel), line subproblem (eq. line_kernel: the dual active-set
+ * method on the 4-variable strictly convex QP, or ALM + TRON in the
+ * RAW_LOCAL mode), bus closed form (eq.
  * bus_kernel_simp), multiplier update (eq. multiplier), residuals.  If
  * result is non-NULL (host) the stream is synchronised and the result
  * copied; otherwise the result is kept in the workspace
