@@ -352,6 +352,26 @@ typedef struct {
  * synchronises the stream). */
 acopf_status acopf_sqp_outcome_batch(const acopf_grid* grid, void* workspace, void* stream, acopf_sqp_outcome* out);
 
+/* Linear feasibility projection (Section II-A, eq. linfeas; Algorithm 1,
+ * the step before its loop): replaces the start x (device arrays, updated
+ * in place; x.pi is not touched) by the nearest point, in the Euclidean
+ * norm over (pg, qg, w, theta, wR, wI), that meets the ACOPF's linear
+ * constraints: power balance (opfc5, opfc6), bounds (opfc1-4), theta_ref
+ * unchanged; wR, wI free (boxed at +-10 around x for the line solver).  A
+ * positive distance certifies that x violated them.  Runs the identity-
+ * Hessian QP through the ADMM sweeps of acopf_admm_solve (params:
+ * max_sweeps, eps_pri, eps_dual, the launch or graph sweep mode, block
+ * size; no trace or balancing): every penalty is rho (> 0), and each line
+ * solves a 4-variable QP in (d_w_i, d_wR, d_w_j, d_wI) exactly.  The
+ * workspace then holds the projection, not a QP subproblem: call
+ * acopf_qp_build before the next acopf_admm_solve.  result (host, optional)
+ * as acopf_admm_solve's, read after the iterate is updated.  Errors:
+ * ACOPF_ERR_INVALID_ARG (null argument, rho <= 0), ACOPF_ERR_UNSUPPORTED
+ * (persistent sweep mode, trace, balancing). */
+acopf_status acopf_linfeas(const acopf_grid* grid, const acopf_iterate* x, double rho,
+                           const acopf_admm_params* params, void* workspace, void* stream,
+                           acopf_admm_result* result);
+
 /* Infeasibility report of the ACOPF (eq. acopf) at x (synchronises; host
  * result): infinity norms of the power-balance residuals, of (opfc11),
  * (opfc12), of the line-limit violations and of the bound violations;

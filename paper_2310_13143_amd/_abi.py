@@ -85,7 +85,8 @@ class ResidualsReport(ctypes.Structure):
 EXPORTS = ("acopf_last_error", "acopf_workspace_bytes", "acopf_setup", "acopf_setup_batch", "acopf_set_delta",
            "acopf_qp_build", "acopf_admm_init", "acopf_admm_solve", "acopf_admm_result_batch",
            "acopf_admm_result_get", "acopf_admm_state_get", "acopf_step", "acopf_sqp_step",
-           "acopf_sqp_step_batch", "acopf_sqp_outcome_batch", "acopf_residuals", "acopf_residuals_batch", "acopf_features",
+           "acopf_sqp_step_batch", "acopf_sqp_outcome_batch", "acopf_linfeas", "acopf_residuals",
+           "acopf_residuals_batch", "acopf_features",
            "acopf_warm_targets", "acopf_warm_decode", "acopf_mlp_param_count", "acopf_mlp_scratch_bytes",
            "acopf_mlp_forward", "acopf_mlp_gradient", "acopf_mlp_gradient_noalloc", "acopf_mlp_adam", "acopf_mlp_feature_stats",
            "acopf_mlp_standardize", "acopf_mlp_fold")
@@ -132,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.acopf_sqp_step.argtypes = [P(Grid), P(Iterate), P(Iterate), c_void_p, c_void_p, P(SqpParams), c_void_p,
                                    c_void_p, P(SqpState)]
     lib.acopf_residuals.argtypes = [P(Grid), P(Iterate), c_void_p, c_void_p, P(ResidualsReport)]
+    lib.acopf_linfeas.argtypes = [P(Grid), P(Iterate), c_double, P(AdmmParams), c_void_p, c_void_p, c_void_p]
     lib.acopf_features.argtypes = [P(Grid), P(Iterate), c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                                    c_void_p]
     lib.acopf_warm_targets.argtypes = [P(Grid), c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "components.h"
+#include "linfeas.h"
 #include "errors.h"
 
 using namespace acopf;
@@ -155,6 +156,36 @@ __global__ void k_build_gens(acopf_grid g, acopf_iterate x, Workspace w) {
 
 __global__ void k_build_buses(acopf_grid g, acopf_iterate x, Workspace w) {
   for (int i = gtid(); i < g.n_bus; i += gstride()) build_bus(g, x, w, i);
+}
+
+// QP of the linear feasibility projection at the start x (lines, generators;
+// the buses take k_build_buses).
+__global__ void k_build_lines_linfeas(acopf_grid g, acopf_iterate x, Workspace w) {
+  for (int l = gtid(); l < g.n_line; l += gstride()) build_line_linfeas(g, x, w, l);
+}
+
+__global__ void k_build_gens_linfeas(acopf_grid g, acopf_iterate x, Workspace w) {
+  for (int k = gtid(); k < g.n_gen; k += gstride()) build_gen_linfeas(g, x, w, k);
+}
+
+// x <- x + d of the projection: generators and buses from their ADMM values,
+// wR, wI from the lines' own values.
+__global__ void k_apply_linfeas(acopf_grid g, acopf_iterate x, Workspace w) {
+  const int G = g.n_gen, L = g.n_line, B = g.n_bus;
+  for (int t = gtid(); t < G + B + L; t += gstride()) {
+    if (t < G) {
+      x.pg[t] += w.xg[t];
+      x.qg[t] += w.xg[G + t];
+    } else if (t < G + B) {
+      const int i = t - G;
+      x.w[i] += w.dw[i];
+      x.th[i] += w.dth[i];
+    } else {
+      const int l = t - G - B;
+      x.wR[l] += w.mu[l];
+      x.wI[l] += w.mu[L + l];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- ADMM init
@@ -443,6 +474,18 @@ k_line_phase_local(Workspace w, int single, int test, double eps_pri, double eps
   const int l = line_of_thread(w, single, s);
   if (l < 0) return;
   if (update_line_local(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
+}
+
+// Line phase of the linear feasibility projection: one exact solve per
+// thread from the line's previous working set.
+__global__ void __launch_bounds__(256)
+k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double eps_dual) {
+  __shared__ int s_stop;
+  int s;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
+  const int l = line_of_thread(w, single, s);
+  if (l < 0) return;
+  if (update_line_linfeas(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
 
 // Bus phase by coupling items (launch modes): one thread per line end or
@@ -1150,11 +1193,13 @@ void set_hessian_mode(const void* workspace, int mode) {
     t.mode[workspace] = mode;
 }
 
-bool local_line_solver(const void* workspace) {
+// 0 exact line solver, 1 local line solver, 2 the projection's line kernel.
+int line_solver_of(const void* workspace) {
   ModeTable& t = mode_table();
   std::lock_guard<std::mutex> lock(t.mu);
   auto it = t.mode.find(workspace);
-  return it != t.mode.end() && it->second == ACOPF_HESSIAN_RAW_LOCAL;
+  if (it == t.mode.end()) return 0;
+  return it->second == ACOPF_HESSIAN_RAW_LOCAL ? 1 : (it->second == kModeLinfeas ? 2 : 0);
 }
 
 acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int32_t* line_off_h,
@@ -1293,9 +1338,11 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
   return ACOPF_OK;
 }
 
+// rho_fill > 0: every penalty is rho_fill (rho_g, rho_l unused).
 acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const double* rho_l, const double* lam_g,
-                            const double* lam_l, bool keep_lam, void* workspace, void* stream) {
-  if (!grid_ok(g) || !workspace || !rho_l || (g->n_gen > 0 && !rho_g))
+                            const double* lam_l, bool keep_lam, void* workspace, void* stream,
+                            double rho_fill = 0.0) {
+  if (!grid_ok(g) || !workspace || (rho_fill <= 0.0 && (!rho_l || (g->n_gen > 0 && !rho_g))))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_init: null argument");
   if ((lam_l == nullptr && lam_g != nullptr) || (lam_l != nullptr && lam_g == nullptr && g->n_gen > 0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_init: give both warm-start multiplier arrays or neither");
@@ -1312,8 +1359,13 @@ acopf_status admm_init_impl(const acopf_grid* g, const double* rho_g, const doub
   auto to_lines = [&](double* d, const double* src, int n) {
     hipLaunchKernelGGL(k_fields_to_lines, dim3(blocks_for(8LL * n, bs)), dim3(bs), 0, s, d, src, n);
   };
-  copy(w.rho_g, rho_g, G2);
-  to_lines(w.rho_l, rho_l, g->n_line);
+  if (rho_fill > 0.0) {
+    fill(w.rho_g, G2, rho_fill);
+    fill(w.rho_l, L8, rho_fill);
+  } else {
+    copy(w.rho_g, rho_g, G2);
+    to_lines(w.rho_l, rho_l, g->n_line);
+  }
   if (keep_lam) {
     // multipliers of the previous solve stay in place (previous-iterate warm start)
   } else if (lam_l) {
@@ -1347,7 +1399,7 @@ struct SweepLaunch {
   acopf_grid g;
   Workspace w;
   int nbl, nbb, bs, single, ns, trace, max_sweeps;
-  int local;  // the local line solver's kernel
+  int solver;  // line kernel: 0 exact, 1 local (ALM + TRON), 2 linear feasibility projection
   double eps_pri, eps_dual;
 };
 
@@ -1358,8 +1410,11 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
   const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
-    if (a.local)
+    if (a.solver == 1)
       hipLaunchKernelGGL(k_line_phase_local, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
+                         (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
+    else if (a.solver == 2)
+      hipLaunchKernelGGL(k_line_phase_linfeas, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
                          (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
     else
       hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
@@ -1407,7 +1462,7 @@ std::string graph_key(const SweepLaunch& a, int n, int dev) {
                         g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
                         g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
   put(ptrs, sizeof ptrs);
-  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps, a.local};
+  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps, a.solver};
   put(shape, sizeof shape);
   put(&a.eps_pri, sizeof a.eps_pri);
   put(&a.eps_dual, sizeof a.eps_dual);
@@ -1540,7 +1595,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: residual balancing needs balance_mu >= 1 and balance_tau > 1");
   if (balance && p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
     return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: residual balancing runs in the launch-per-phase modes");
-  const bool local = local_line_solver(workspace);
+  const int solver = line_solver_of(workspace);
+  const bool local = solver == 1;
   if (p->trace) {
     const int bz = kDefaultBlock;
     const long long G2 = 2LL * g->n_gen, L8 = 8LL * g->n_line;
@@ -1570,7 +1626,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.ns = ns;
     a.trace = p->trace;
     a.max_sweeps = p->max_sweeps;
-    a.local = local ? 1 : 0;
+    a.solver = solver;
     a.eps_pri = p->eps_pri;
     a.eps_dual = p->eps_dual;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1608,6 +1664,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     }
   } else if (p->sweep_mode == ACOPF_SWEEP_PERSISTENT) {
     if (ns != 1) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: the persistent mode serves one scenario");
+    if (solver == 2)
+      return fail(ACOPF_ERR_UNSUPPORTED, "acopf_linfeas: the projection runs in the launch-per-phase modes");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     int cus = 0, coop = 0;
@@ -1909,6 +1967,36 @@ acopf_status acopf_residuals_batch(const acopf_grid* g, const acopf_iterate* x, 
     out[k].primal = std::max(std::max(std::max(r[k].balance, r[k].c11), std::max(r[k].c12, r[k].limit)), r[k].bounds);
     out[k].dual = r[k].dual / std::max(1.0, r[k].gradf);
   }
+  return ACOPF_OK;
+}
+
+acopf_status acopf_linfeas(const acopf_grid* g, const acopf_iterate* x, double rho, const acopf_admm_params* p,
+                           void* workspace, void* stream, acopf_admm_result* result) {
+  if (!grid_ok(g) || !iterate_ok(x) || !p || !workspace)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_linfeas: null argument");
+  if (!(rho > 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_linfeas: rho must be > 0");
+  if (p->sweep_mode == ACOPF_SWEEP_PERSISTENT)
+    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_linfeas: the projection runs in the launch-per-phase modes");
+  if (p->trace || p->balance_every != 0)
+    return fail(ACOPF_ERR_UNSUPPORTED, "acopf_linfeas: no trace sums or residual balancing for the projection");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int bs = kDefaultBlock;
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w, kModeLinfeas);
+  set_hessian_mode(workspace, kModeLinfeas);
+  hipLaunchKernelGGL(k_build_lines_linfeas, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, w);
+  if (g->n_gen > 0)
+    hipLaunchKernelGGL(k_build_gens_linfeas, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w);
+  hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
+  HIP_TRY(hipGetLastError());
+  acopf_status rc = admm_init_impl(g, nullptr, nullptr, nullptr, nullptr, false, workspace, stream, rho);
+  if (rc != ACOPF_OK) return rc;
+  rc = acopf_admm_solve(g, p, workspace, stream, nullptr);
+  if (rc != ACOPF_OK) return rc;
+  const int n = g->n_gen + g->n_bus + g->n_line;
+  hipLaunchKernelGGL(k_apply_linfeas, dim3(blocks_for(n, bs)), dim3(bs), 0, s, *g, *x, w);
+  HIP_TRY(hipGetLastError());
+  if (result) return acopf_admm_result_get(g, workspace, stream, result);
   return ACOPF_OK;
 }
 

@@ -339,6 +339,8 @@ ACOPF_HD void build_gen(const acopf_grid& g, const acopf_iterate& x, double delt
   d[GF_PHI * G + k] = phi;
   d[GF_QLO * G + k] = fmin(fmax(-delta, g.qmin[k] - qv), qhi);
   d[GF_QHI * G + k] = qhi;
+  d[GF_FQ * G + k] = 0.0;
+  d[GF_FQQ * G + k] = 0.0;
 }
 
 // p^{d,(k)}, q^{d,(k)} of bus i (constants after eq. acopf_qppf).
@@ -396,8 +398,12 @@ ACOPF_HD bool prep_line(const Workspace& w, int l) {
       for (int j = 0; j < 4; ++j) Q[i][j] += rho * Fr[i] * Fr[j];
     }
   }
+  // in the linear feasibility projection z = (w_i, wR, w_j, wI): only the
+  // w copies are coupled to bus values (the angle copies are held at zero)
+  const bool lf = w.sync->hessian_mode == kModeLinfeas;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Q[i][i] += w.rho_l[lc8(l, 4 + i)];
+  for (int i = 0; i < 4; ++i)
+    if (!lf || (i & 1) == 0) Q[i][i] += w.rho_l[lc8(l, 4 + i)];
   double Pp[10];
   bool ok = true;
   if (w.sync->hessian_mode == ACOPF_HESSIAN_RAW_LOCAL) {
@@ -542,7 +548,7 @@ ACOPF_HD void update_gen(const Workspace& w, int k) {
   const double* d = w.gen;
   const double rp = w.rho_g[k], rq = w.rho_g[G + k];
   double xp = (rp * w.xbar_g[k] - w.lam_g[k] - d[GF_FP * G + k]) / (d[GF_FPP * G + k] + rp);
-  double xq = (rq * w.xbar_g[G + k] - w.lam_g[G + k]) / rq;
+  double xq = (rq * w.xbar_g[G + k] - w.lam_g[G + k] - d[GF_FQ * G + k]) / (d[GF_FQQ * G + k] + rq);
   xp = fmin(fmax(xp, d[GF_PLO * G + k]), d[GF_PHI * G + k]);
   xq = fmin(fmax(xq, d[GF_QLO * G + k]), d[GF_QHI * G + k]);
   w.xg[k] = xp;

@@ -36,7 +36,14 @@ enum LineField {
   LF_COUNT = 79
 };
 
-enum GenField { GF_FP = 0, GF_FPP, GF_PLO, GF_PHI, GF_QLO, GF_QHI, GF_COUNT };
+// f', f'' of the active power's objective, its box, the reactive power's
+// box, and the reactive power's f', f'' (zero in the SQP's QP, whose cost
+// has no reactive term; one in the linear feasibility projection).
+enum GenField { GF_FP = 0, GF_FPP, GF_PLO, GF_PHI, GF_QLO, GF_QHI, GF_FQ, GF_FQQ, GF_COUNT };
+
+// hessian_mode value of a workspace holding the linear feasibility
+// projection's QP (Section II-A, eq. linfeas) instead of an SQP subproblem.
+constexpr int kModeLinfeas = 3;
 
 enum BusFlag { BUS_REF = 1 };
 
@@ -49,7 +56,7 @@ struct SyncState {
   int numeric_error;       // non-finite data / vanishing pivot in the QP build
   int nonconvex;           // raw mode: a line matrix failed its Cholesky
   int blocks;              // grid size of the last solve
-  int hessian_mode;        // acopf_hessian_mode of the last QP build
+  int hessian_mode;        // acopf_hessian_mode of the last QP build, or kModeLinfeas
 };
 
 // Per-scenario ADMM and SQP state.

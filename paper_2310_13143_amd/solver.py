@@ -309,6 +309,17 @@ class DeviceGrid:
                                          rho_l.data_ptr(), rho_g.data_ptr(), self.stream))
         return lam_g[:2 * G], lam_l, rho_g[:2 * G], rho_l
 
+    def linfeas(self, x: dict, rho: float = 1.0, max_sweeps: int = 20000, eps: float = 1e-8,
+                sweep_mode: int = _abi.SWEEP_GRAPH, block_size: int = 0) -> dict:
+        """Linear feasibility projection of the iterate x, in place
+        (acopf_linfeas); returns the ADMM result of the projection."""
+        p = _admm_params(max_sweeps, eps, eps, sweep_mode, block_size, 0, False, None)
+        res = AdmmResult()
+        cx = self.c_iterate(x)
+        check(self.lib.acopf_linfeas(ctypes.byref(self.cgrid), ctypes.byref(cx), float(rho), ctypes.byref(p),
+                                     self.ws, self.stream, ctypes.byref(res)))
+        return self._result_dict(res)
+
     def residuals_batch(self, x: dict) -> list:
         r = (ResidualsReport * self.n_scen)()
         cx = self.c_iterate(x)

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../paper_2310_13143_amd/csrc/components.h"
+#include "../../paper_2310_13143_amd/csrc/linfeas.h"
 
 using namespace acopf;
 
@@ -86,9 +87,10 @@ static void bus_by_items(const acopf_grid& g, const Workspace& w, int i, double&
 // The workspace is a host buffer of acopf_workspace_bytes-equivalent size.
 size_t emu_workspace_bytes(int nb, int nl, int ng) { return layout_workspace(nullptr, nb, nl, ng, 1, nullptr); }
 
-int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode, const double* rho_g,
-            const double* rho_l, const double* lam_g, const double* lam_l, int sweeps, void* ws_base,
-            const acopf_iterate* d, double* rs_out) {
+}  // extern "C"
+
+// Workspace of one scenario with the tables of acopf_setup.
+static Workspace emu_setup(const acopf_grid* g, void* ws_base) {
   const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
   Workspace w;
   layout_workspace(ws_base, nb, nl, ng, 1, &w);
@@ -97,7 +99,6 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   w.scen_line_off[0] = 0; w.scen_line_off[1] = nl;
   w.scen_gen_off[0] = 0; w.scen_gen_off[1] = ng;
   for (int i = 0; i < nb; ++i) { w.bus_scen[i] = 0; w.bus_flags[i] = (i == g->ref_bus) ? BUS_REF : 0; }
-  w.scen[0].delta = delta;
   // incidence tables (same construction as acopf_setup)
   std::vector<int> deg(nb, 0), gdeg(nb, 0);
   for (int l = 0; l < nl; ++l) { deg[g->line_from[l]]++; deg[g->line_to[l]]++; }
@@ -114,6 +115,17 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
     w.bus_end[fe[g->line_to[l]]++] = 2 * l + 1;
   }
   for (int k = 0; k < ng; ++k) w.bus_gen[fg[g->gen_bus[k]]++] = k;
+  return w;
+}
+
+extern "C" {
+
+int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode, const double* rho_g,
+            const double* rho_l, const double* lam_g, const double* lam_l, int sweeps, void* ws_base,
+            const acopf_iterate* d, double* rs_out) {
+  const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
+  Workspace w = emu_setup(g, ws_base);
+  w.scen[0].delta = delta;
   int bad = 0;
   w.sync->hessian_mode = mode;
   for (int l = 0; l < nl; ++l) bad += build_line(*g, *x, delta, mode, w, l) ? 0 : 1;
@@ -165,6 +177,48 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
     for (int k = 0; k < ng; ++k) { d->pg[k] = w.xg[k]; d->qg[k] = w.xg[ng + k]; }
   }
   return bad * 10000 + infeasible;
+}
+
+// Linear feasibility projection (acopf_linfeas) on the host: build, cold
+// start with every penalty rho, `sweeps` sweeps, x <- x + d (x modified).
+// rs_out: ||r||^2, ||s||^2 per sweep.  Returns the number of line solves
+// that did not succeed in the last sweep.
+int emu_linfeas_run(const acopf_grid* g, const acopf_iterate* x, double rho, int sweeps, void* ws_base,
+                    double* rs_out) {
+  const int nb = g->n_bus, nl = g->n_line, ng = g->n_gen;
+  Workspace w = emu_setup(g, ws_base);
+  w.sync->hessian_mode = kModeLinfeas;
+  for (int l = 0; l < nl; ++l) build_line_linfeas(*g, *x, w, l);
+  for (int k = 0; k < ng; ++k) build_gen_linfeas(*g, *x, w, k);
+  for (int i = 0; i < nb; ++i) build_bus(*g, *x, w, i);
+  for (int k = 0; k < 2 * ng; ++k) w.rho_g[k] = rho;
+  for (int k = 0; k < 8 * nl; ++k) w.rho_l[k] = rho;
+  std::memset(w.lam_g, 0, sizeof(double) * 2 * ng);
+  std::memset(w.lam_l, 0, sizeof(double) * 8 * nl);
+  std::memset(w.xg, 0, sizeof(double) * 2 * ng);
+  std::memset(w.xbar_g, 0, sizeof(double) * 2 * ng);
+  std::memset(w.xl, 0, sizeof(double) * 8 * nl);
+  std::memset(w.xbar_f, 0, sizeof(double) * 4 * nl);
+  std::memset(w.xbar_v, 0, sizeof(double) * 4 * nl);
+  std::memset(w.dw, 0, sizeof(double) * nb);
+  std::memset(w.dth, 0, sizeof(double) * nb);
+  std::memset(w.nu, 0, sizeof(double) * 2 * nb);
+  std::memset(w.mu, 0, sizeof(double) * 2 * nl);
+  std::memset(w.line_mask, 0, sizeof(int32_t) * nl);
+  for (int l = 0; l < nl; ++l) prep_line(w, l);
+  int bad = 0;
+  for (int k = 0; k < sweeps; ++k) {
+    bad = 0;
+    for (int l = 0; l < nl; ++l) bad += update_line_linfeas(w, l) != 0;
+    double r2 = 0.0, s2 = 0.0;
+    for (int i = 0; i < nb; ++i) update_bus(*g, w, i, r2, s2);
+    rs_out[2 * k] = r2;
+    rs_out[2 * k + 1] = s2;
+  }
+  for (int k = 0; k < ng; ++k) { x->pg[k] += w.xg[k]; x->qg[k] += w.xg[ng + k]; }
+  for (int i = 0; i < nb; ++i) { x->w[i] += w.dw[i]; x->th[i] += w.dth[i]; }
+  for (int l = 0; l < nl; ++l) { x->wR[l] += w.mu[l]; x->wI[l] += w.mu[nl + l]; }
+  return bad;
 }
 
 // Addresses of the ADMM state arrays inside a host workspace, in the order

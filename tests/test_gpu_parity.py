@@ -856,3 +856,68 @@ def test_sqp_with_local_line_solver_matches_oracle():
     xf = {k: v.cpu().numpy() for k, v in x.items()}
     for name in ("pg", "qg", "w", "th", "wR", "wI"):
         assert rel_err(xf[name], getattr(ref.x, name)) <= 1e-7, name
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["launches", "graph"])
+@pytest.mark.parametrize("case", ["ring14", "tiny_shunt"])
+def test_linfeas_matches_oracle(case, mode):
+    """Linear feasibility projection (Section II-A, eq. linfeas) on the
+    device: a fixed sweep count against the oracle's decomposed projection
+    (1e-8), and a converged run against the oracle's interior-point
+    projection (1e-6), with the linear constraints met and the multipliers
+    pi untouched."""
+    from oracle import linfeas
+    print(f"[gpu] linfeas {case} mode={mode}", flush=True)
+    g = CASES[case]()
+    x0 = acopf.flat_start(g)
+    nsw = 150
+    ref = linfeas.admm_project(g, x0, 1.0, nsw)
+    dg = _dev()(g)
+    pi0 = np.random.default_rng(3).standard_normal((g.n_line, 4))
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, pi0)
+    res = dg.linfeas(x, rho=1.0, max_sweeps=nsw, eps=0.0, sweep_mode=mode)
+    assert res["sweeps"] == nsw and res["infeasible_lines"] == 0
+    assert abs(res["r"] - ref.r) <= 1e-7 * ref.r and abs(res["s"] - ref.s) <= 1e-7 * ref.s
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    for name in ("pg", "qg", "w", "th", "wR", "wI"):
+        assert rel_err(xf[name], getattr(ref.x, name)) <= TOL, name
+    assert np.array_equal(xf["pi"].reshape(4, -1).T, pi0)
+    # converged
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, pi0)
+    res = dg.linfeas(x, rho=1.0, max_sweeps=20000, eps=1e-10, sweep_mode=mode)
+    assert res["converged"]
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    xp = acopf.Iterate(*(xf[n] for n in ("pg", "qg", "w", "th", "wR", "wI")))
+    p = linfeas.project(g, x0)
+    assert linfeas.violation(g, xp) < 1e-8
+    np.testing.assert_allclose(linfeas._vec(xp), linfeas._vec(p.x), atol=1e-6)
+    # the workspace serves a QP subproblem again after a build
+    dg.qp_build(x, 0.05)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    assert dg.admm_solve(10, sweep_mode=mode)["sweeps"] == 10
+
+
+def test_linfeas_batch_matches_solo_runs_and_rejects_the_persistent_mode():
+    """Two scenarios projected in one batch give their solo runs bit for
+    bit; the persistent sweep mode is refused."""
+    from paper_2310_13143_amd import AcopfError
+    print("[gpu] linfeas batch", flush=True)
+    grids = _batch_cases()[:2]
+    DeviceGrid = _dev()
+    x0s = [acopf.flat_start(g) for g in grids]
+    dg = DeviceGrid(grids)
+    cat = lambda name: np.concatenate([getattr(x, name) for x in x0s])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
+    dg.linfeas(xb, rho=1.0, max_sweeps=100, eps=0.0, sweep_mode=1)
+    xbf = {k: v.cpu().numpy() for k, v in xb.items()}
+    offs = {"pg": dg.offsets["gen"], "qg": dg.offsets["gen"], "w": dg.offsets["bus"], "th": dg.offsets["bus"],
+            "wR": dg.offsets["line"], "wI": dg.offsets["line"]}
+    for k, g in enumerate(grids):
+        solo = DeviceGrid(g)
+        xs = solo.iterate(x0s[k].pg, x0s[k].qg, x0s[k].w, x0s[k].th, x0s[k].wR, x0s[k].wI, None)
+        solo.linfeas(xs, rho=1.0, max_sweeps=100, eps=0.0, sweep_mode=1)
+        for name, o in offs.items():
+            assert np.array_equal(xbf[name][o[k]:o[k + 1]], xs[name].cpu().numpy()), (k, name)
+    with pytest.raises(AcopfError) as e:
+        dg.linfeas(xb, sweep_mode=0)
+    assert e.value.code == -5

@@ -473,3 +473,28 @@ def test_relaxed_line_objectives_match_oracle(emu):
     rs = 1 + np.abs(h) + np.einsum("nrj,nj->nr", np.abs(G), np.abs(z))
     assert (np.einsum("nrj,nj->nr", G, z) - h <= 1e-11 * rs).all()   # far inside the 1e-9 guard
     assert (z >= lo).all() and (z <= hi).all()
+
+
+@pytest.mark.parametrize("case", ["ring14", "tiny_shunt"])
+def test_linfeas_sweeps_match_oracle(emu, case):
+    """The linear feasibility projection's sweeps (line kernel with free wR,
+    wI, generators with a reactive term, the unchanged bus closed form) on
+    the host against the oracle's decomposed projection, sweep by sweep in
+    the residual norms and in the projected iterate after a fixed count."""
+    from oracle import linfeas
+    g = grid_14() if case == "ring14" else tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04)
+    x0 = acopf.flat_start(g)
+    nsw = 60
+    ref = linfeas.admm_project(g, x0, 1.0, nsw)
+    hg = HostGrid(g)
+    cx, arrays = hg.iterate(x0, np.zeros((g.n_line, 4)))
+    ws = np.zeros(emu.emu_workspace_bytes(g.n_bus, g.n_line, g.n_gen) // 8 + 64)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    rs = np.zeros(2 * nsw)
+    bad = emu.emu_linfeas_run(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.c_double(1.0), nsw,
+                              ctypes.c_void_p(base), ptr(rs))
+    assert bad == 0
+    assert abs(np.sqrt(rs[-2]) - ref.r) <= 1e-8 * ref.r and abs(np.sqrt(rs[-1]) - ref.s) <= 1e-8 * ref.s
+    for name, a in zip(("pg", "qg", "w", "th", "wR", "wI"), arrays[:6]):
+        b = getattr(ref.x, name)
+        assert np.abs(a - b).max() <= 1e-10 * (1 + np.abs(b).max()), name

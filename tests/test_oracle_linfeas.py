@@ -65,3 +65,23 @@ def test_projection_kkt_and_nearest_feasible_point():
         y = linfeas._vec(linfeas.project(g, xs).x)
         assert linfeas.violation(g, linfeas._unvec(g, y)) < 1e-8
         assert np.sum((y - v0) ** 2) >= p.objective - 1e-9
+
+
+@pytest.mark.parametrize("case", ["ring14", "tiny_shunt"])
+def test_decomposed_projection_reaches_the_projection(case):
+    """The projection run through the ADMM decomposition of the QP
+    subproblems (identity Hessian: generators, lines with free wR, wI and a
+    1/degree share of each bus's w term, buses with their balance rows)
+    converges to the interior-point projection: the same point to 1e-7, the
+    linear constraints met."""
+    g = grid_14() if case == "ring14" else tiny_grid(seed=21, n_bus=7, n_line=10, n_gen=3, shunt_scale=0.04)
+    x0 = acopf.flat_start(g)
+    assert linfeas.violation(g, x0) > 1e-3
+    p = linfeas.project(g, x0)
+    a = linfeas.admm_project(g, x0, 1.0, 20000, 1e-10, 1e-10)
+    assert a.converged
+    assert linfeas.violation(g, a.x) < 1e-8
+    np.testing.assert_allclose(linfeas._vec(a.x), linfeas._vec(p.x), atol=1e-7)
+    # the angles are not moved (theta_ref of the start is 0 and no other
+    # linear constraint involves them)
+    assert np.array_equal(a.x.th, x0.th)
