@@ -119,7 +119,7 @@ def main():
         if getattr(args, k) is None:
             setattr(args, k, v)
     if args.block is None:
-        args.block = 0 if args.workload == "batch64" else 64
+        args.block = 0 if args.workload == "batch64" else 128
 
     import torch
     from synth.grids import WORKLOADS, power_flow_start

@@ -65,6 +65,30 @@ __device__ double block_sum(double v, double* lds) {
   return t;
 }
 
+// block_sum of two values at once, the result valid in thread 0 only (the
+// same order and arithmetic as block_sum; two barriers instead of six).
+__device__ void block_sum2_to_first(double& a, double& b, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    lds[wave] = a;
+    lds[8 + wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int k = 0; k < nw; ++k) ta += lds[k];
+    for (int k = 0; k < nw; ++k) tb += lds[8 + k];
+    a = ta;
+    b = tb;
+  }
+}
+
 __device__ double block_max(double v, double* lds) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -545,8 +569,7 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
     for (int m = 0; m < 6; ++m) res[m] = bres[m][head];
     bus_item_update<kTrace>(w, code, v, res, rr, ss);
   }
-  rr = block_sum(rr, lds);
-  ss = block_sum(ss, lds);
+  block_sum2_to_first(rr, ss, lds);
   if (t == 0) {
     w.partials[blockIdx.x] = rr;
     w.partials[w.max_partials + blockIdx.x] = ss;
