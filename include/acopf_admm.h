@@ -297,7 +297,18 @@ typedef struct {
    * frozen: later calls leave it out until acopf_set_delta starts a new
    * run.  See acopf_sqp_outcome_batch. */
   int32_t stop;
-  int32_t reserved;
+  /* restore = 1: this call takes a feasibility restoration step instead (a
+   * remedy the paper names as missing, Section V): the QP with the same
+   * linearised constraints (opfqpc5, opfqpc6, opfqpc11-14; lines without a
+   * feasible point relaxed as in acopf_qp_build) and the objective
+   * 0.5 ||d||^2 over (pg, qg, w, theta, wR, wI) (each bus variable's term
+   * shared among its lines by 1/degree; pi and the costs unused; exact line
+   * solver), within the radius held for the scenario.  The step is accepted
+   * iff it lowers the constraint violation h of the merit function
+   * (state->ared = h(x) - h(x + d), pred = 0); the radius and x.pi are left
+   * as they are, and soc is ignored.  The caller calls it when a run's
+   * radius has collapsed and restarts the radius after an accepted step. */
+  int32_t restore;
   double tol_primal, tol_dual, tol_step, delta_min;
 } acopf_sqp_params;
 

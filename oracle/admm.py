@@ -92,7 +92,9 @@ def gen_update(qp, st: AdmmState, rho: Rho):
     g = qp.gen
     rp, rq = rho.g[:, 0], rho.g[:, 1]
     xp = (rp * st.xbar_g[:, 0] - st.lam_g[:, 0] - g.fp) / (g.fpp + rp)
-    xq = (rq * st.xbar_g[:, 1] - st.lam_g[:, 1]) / rq
+    fq = 0.0 if g.fq is None else g.fq
+    fqq = 0.0 if g.fqq is None else g.fqq
+    xq = (rq * st.xbar_g[:, 1] - st.lam_g[:, 1] - fq) / (fqq + rq)
     xp = np.minimum(np.maximum(xp, g.lo[:, 0]), g.hi[:, 0])
     xq = np.minimum(np.maximum(xq, g.lo[:, 1]), g.hi[:, 1])
     return np.stack([xp, xq], 1)

@@ -61,15 +61,17 @@ def assemble(grid, qp) -> QPMatrices:
     zi = np.stack([ix["w"][f], ix["th"][f], ix["w"][t], ix["th"][t]], 1)  # (L, 4)
     Lq = qp.line
     # objective
-    rows = [ix["pg"]]
-    cols = [ix["pg"]]
-    vals = [qp.gen.fpp]
+    rows = [ix["pg"], ix["qg"]]
+    cols = [ix["pg"], ix["qg"]]
+    vals = [qp.gen.fpp, np.zeros(G) if qp.gen.fqq is None else qp.gen.fqq]
     for a in range(4):
         for b_ in range(4):
             rows.append(zi[:, a]); cols.append(zi[:, b_]); vals.append(Lq.M[:, a, b_])
     P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
     q = np.zeros(n)
     q[ix["pg"]] += qp.gen.fp
+    if qp.gen.fq is not None:
+        q[ix["qg"]] += qp.gen.fq
     np.add.at(q, zi.ravel(), Lq.q.ravel())
     const = float(Lq.c0.sum())
     # balance rows: P rows 0..B-1, Q rows B..2B-1

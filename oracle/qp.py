@@ -54,6 +54,8 @@ class GenQP:
     fpp: np.ndarray  # f''(p^k)
     lo: np.ndarray   # (G, 2)
     hi: np.ndarray   # (G, 2)
+    fq: np.ndarray = None   # reactive power's f', f'' (None: zero, the cost has no reactive term)
+    fqq: np.ndarray = None
 
 
 @dataclass
@@ -132,9 +134,25 @@ def psd_project(M):
     return 0.5 * (P + np.swapaxes(P, 1, 2))
 
 
+def restoration_hessian(grid):
+    """Per-line Hessian of the restoration QP's objective 0.5 ||d||^2 in
+    u = (w_i, th_i, wR, wI, w_j, th_j): each bus variable's term shared
+    among its incident lines (1 / degree), so that the shares add up to
+    0.5 (d_w^2 + d_th^2) per bus."""
+    deg = np.bincount(grid.f, minlength=grid.n_bus) + np.bincount(grid.t, minlength=grid.n_bus)
+    wf, wt = 1.0 / deg[grid.f], 1.0 / deg[grid.t]
+    one = np.ones(grid.n_line)
+    diag = np.stack([wf, wf, one, one, wt, wt], 1)
+    return np.einsum("li,ij->lij", diag, np.eye(6))
+
+
 def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str = "psd",
              rhs_shift=None, c_shift=None) -> QP:
     """Data of (QPsub) at iterate x with line multipliers pi and trust radius delta.
+
+    ``hessian_mode`` "restore": the QP of a feasibility restoration step, the
+    same linearised constraints with the objective 0.5 ||d||^2 (lines:
+    ``restoration_hessian``; generators 0.5 (d_p^2 + d_q^2); pi unused).
 
     ``c_shift`` (n_line, 4), if given, is added to the constraint values
     c11..c14 of (opfc11-14) at x in their linearisations (opfqpc11-14): the
@@ -147,14 +165,17 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
         cs = -np.asarray(c_shift, dtype=np.float64)[:, :2]
         rhs_shift = cs if rhs_shift is None else rhs_shift + cs
     aR, bR, aI, bI = elimination(grid, x, rhs_shift)
-    H = line_hessian(grid, x, pi)
+    if hessian_mode == "restore":
+        H = restoration_hessian(grid)
+    else:
+        H = line_hessian(grid, x, pi)
     A, b = lift_matrix(aR, bR, aI, bI)
     At = np.swapaxes(A, 1, 2)
     M = At @ H @ A
     M = 0.5 * (M + np.swapaxes(M, 1, 2))
     if hessian_mode == "psd":
         M = psd_project(M)
-    elif hessian_mode != "raw":
+    elif hessian_mode not in ("raw", "restore"):
         raise ValueError(hessian_mode)
     q = (At @ (H @ b[:, :, None]))[:, :, 0]
     c0 = 0.5 * np.einsum("li,lij,lj->l", b, H, b)
@@ -222,7 +243,9 @@ def build_qp(grid, x: Iterate, pi: np.ndarray, delta: float, hessian_mode: str =
 
     return QP(
         line=LineQP(aR, bR, aI, bI, H, M, q, F, f0, lo, hi, G, h, pk, c0, relax),
-        gen=GenQP(fp, fpp, np.stack([plo, qlo], 1), np.stack([phi, qhi], 1)),
+        gen=(GenQP(np.zeros(grid.n_gen), np.ones(grid.n_gen), np.stack([plo, qlo], 1), np.stack([phi, qhi], 1),
+                   np.zeros(grid.n_gen), np.ones(grid.n_gen)) if hessian_mode == "restore"
+             else GenQP(fp, fpp, np.stack([plo, qlo], 1), np.stack([phi, qhi], 1))),
         bus=BusQP(pdk, qdk, blo, bhi),
         delta=float(delta), ref=int(grid.ref),
     )

@@ -88,6 +88,18 @@ class SqpParams:
     # (Algorithm 1).  True: only when the ADMM solve met its stop test (a
     # safeguard for QPs without a feasible point; see the module docstring).
     pi_if_converged: bool = False
+    # feasibility restoration (named by the paper as missing, Section V):
+    # when the radius falls below delta_min, up to max_restore times a
+    # restoration step is taken instead of stopping: the QP with the same
+    # linearised constraints and the objective 0.5 ||d||^2 (hessian mode
+    # "restore") within radius restore_delta (0: delta0), solved cold; it is
+    # accepted iff it lowers the constraint violation h of the merit
+    # function, and then the radius restarts at delta0 and the next QP solve
+    # starts cold; pi is kept.  A rejected restoration step ends the run
+    # (TR_COLLAPSED).
+    restore: bool = False
+    max_restore: int = 3
+    restore_delta: float = 0.0
 
 
 @dataclass
@@ -105,6 +117,7 @@ class SqpRecord:
     primal: float
     dual: float
     soc: bool = False
+    restore: bool = False
 
 
 @dataclass
@@ -243,6 +256,8 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
     lam_g = lam_l = None
     recs = []
     outcome = "MAX_ITER"
+    restores = 0
+    restoring = False
 
     def qp_solve(qp, lam_g, lam_l):
         if params.qp_solver == "direct":
@@ -258,6 +273,28 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
                 st.lam_g, st.lam_l)
 
     for k in range(params.max_iter):
+        if restoring:
+            # feasibility restoration step (see SqpParams.restore)
+            restoring = False
+            restores += 1
+            dr = params.restore_delta if params.restore_delta > 0 else params.delta0
+            qp = qpmod.build_qp(grid, x, pi, dr, "restore")
+            d, _, nup, nuq, res, _, _ = qp_solve(qp, None, None)
+            xt = x.plus(d)
+            h0, h1 = acopf.infeas_h(grid, x), acopf.infeas_h(grid, xt)
+            accepted = h1 < h0
+            if accepted:
+                x = xt
+                delta = params.delta0
+            lam_g = lam_l = None
+            pr = acopf.primal_infeasibility(grid, x)["primal"]
+            du = acopf.dual_infeasibility(grid, x, nup, nuq, pi)
+            recs.append(SqpRecord(k, accepted, h0 - h1, 0.0, dr, step_norm(d), res.sweeps, res.r, res.s,
+                                  acopf.objective(grid, x.pg), pr, du, False, True))
+            if not accepted:
+                outcome = "TR_COLLAPSED"
+                break
+            continue
         qp = qpmod.build_qp(grid, x, pi, delta, params.hessian_mode)
         d, pi_new, nup, nuq, res, lam_g, lam_l = qp_solve(qp, lam_g, lam_l)
         xt = x.plus(d)
@@ -304,6 +341,9 @@ def solve(grid, params: SqpParams = SqpParams(), x0: Iterate | None = None, time
             outcome = "SMALL_STEP"
             break
         if delta < params.delta_min:
+            if params.restore and restores < params.max_restore:
+                restoring = True
+                continue
             outcome = "TR_COLLAPSED"
             break
     return SqpResult(x, pi, outcome, len(recs), recs)

@@ -62,7 +62,7 @@ class SqpParams(ctypes.Structure):
     _fields_ = [("mu", c_double), ("delta_max", c_double), ("grow_ratio", c_double),
                 ("hessian_mode", c_int32), ("warm_start", c_int32), ("admm", AdmmParams),
                 ("lam_g0", c_void_p), ("lam_l0", c_void_p), ("pi_update", c_int32), ("soc", c_int32),
-                ("stop", c_int32), ("reserved", c_int32), ("tol_primal", c_double), ("tol_dual", c_double),
+                ("stop", c_int32), ("restore", c_int32), ("tol_primal", c_double), ("tol_dual", c_double),
                 ("tol_step", c_double), ("delta_min", c_double)]
 
 

@@ -173,9 +173,9 @@ __global__ void k_build_lines(acopf_grid g, acopf_iterate x, int mode, Workspace
   }
 }
 
-__global__ void k_build_gens(acopf_grid g, acopf_iterate x, Workspace w) {
+__global__ void k_build_gens(acopf_grid g, acopf_iterate x, Workspace w, int restore) {
   for (int k = gtid(); k < g.n_gen; k += gstride())
-    build_gen(g, x, w.scen[w.bus_scen[g.gen_bus[k]]].delta, w, k);
+    build_gen(g, x, w.scen[w.bus_scen[g.gen_bus[k]]].delta, w, k, restore != 0);
 }
 
 __global__ void k_build_buses(acopf_grid g, acopf_iterate x, Workspace w) {
@@ -793,7 +793,8 @@ __device__ void merit_sums(const Workspace& w, int s, double a[7], double& smax,
 // scenario (fixed-order sums over the scenario's components).  soc = 1: a
 // rejected step with pred > 0 of a scenario whose QP was solved is marked
 // for a second-order correction (decided by k_soc_decide).
-__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule, int soc) {
+// restore: a restoration step, accepted iff it lowers h; radius and pi kept.
+__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule, int soc, int restore) {
   __shared__ double lds[16];
   const int s = blockIdx.x;
   double a[7], smax;
@@ -826,6 +827,17 @@ __global__ void k_decide(Workspace w, double mu, double delta_max, double grow, 
     dc->step_inf = smax;
     dc->delta_in = delta;
     const bool failed = w.scen[s].status != 0;
+    if (restore) {
+      const bool acc = !failed && a[4] < a[3];
+      dc->ared = a[3] - a[4];
+      dc->pred = 0.0;
+      dc->delta_out = delta;
+      dc->accepted = acc ? 1 : 0;
+      dc->update_pi = 0;
+      dc->soc = 0;
+      dc->soc_sweeps = 0;
+      return;
+    }
     const bool ok = !failed && ared > 0.0 && pred > 0.0;
     double dn = delta;
     if (ok) {
@@ -1565,6 +1577,31 @@ acopf_status acopf_set_delta(const acopf_grid* g, const double* delta, void* wor
   return ACOPF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// QP build; mode may also be kModeRestore (a restoration step's QP: exact
+// line solver, generators with 0.5 (d_p^2 + d_q^2)).
+acopf_status qp_build_impl(const acopf_grid* g, const acopf_iterate* x, double delta, int mode, void* workspace,
+                           void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace w = ws_of(g, workspace);
+  const int bs = kDefaultBlock;
+  const bool restore = mode == kModeRestore;
+  if (delta > 0.0) hipLaunchKernelGGL(k_set_delta, dim3(blocks_for(w.n_scen, bs)), dim3(bs), 0, s, w, delta);
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w, mode);
+  set_hessian_mode(workspace, restore ? ACOPF_HESSIAN_PSD : mode);
+  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, mode, w, 0);
+  if (g->n_gen > 0)
+    hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w, restore ? 1 : 0);
+  hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+}  // namespace
+
+extern "C" {
+
 acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double delta, int32_t mode,
                             void* workspace, void* stream) {
   if (!grid_ok(g) || !iterate_ok(x) || !workspace)
@@ -1572,17 +1609,7 @@ acopf_status acopf_qp_build(const acopf_grid* g, const acopf_iterate* x, double 
   if (!(delta >= 0.0)) return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: trust radius must be >= 0");
   if (mode != ACOPF_HESSIAN_PSD && mode != ACOPF_HESSIAN_RAW && mode != ACOPF_HESSIAN_RAW_LOCAL)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_qp_build: unknown Hessian mode");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = ws_of(g, workspace);
-  const int bs = kDefaultBlock;
-  if (delta > 0.0) hipLaunchKernelGGL(k_set_delta, dim3(blocks_for(w.n_scen, bs)), dim3(bs), 0, s, w, delta);
-  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w, (int)mode);
-  set_hessian_mode(workspace, mode);
-  hipLaunchKernelGGL(k_build_lines, dim3(blocks_for(g->n_line, bs)), dim3(bs), 0, s, *g, *x, (int)mode, w, 0);
-  if (g->n_gen > 0) hipLaunchKernelGGL(k_build_gens, dim3(blocks_for(g->n_gen, bs)), dim3(bs), 0, s, *g, *x, w);
-  hipLaunchKernelGGL(k_build_buses, dim3(blocks_for(g->n_bus, bs)), dim3(bs), 0, s, *g, *x, w);
-  HIP_TRY(hipGetLastError());
-  return ACOPF_OK;
+  return qp_build_impl(g, x, delta, mode, workspace, stream);
 }
 
 acopf_status acopf_admm_init(const acopf_grid* g, const double* rho_g, const double* rho_l,
@@ -1825,8 +1852,13 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
                                        "while the stream is being captured");
   if (p->stop && !(p->tol_primal >= 0.0 && p->tol_dual >= 0.0 && p->tol_step >= 0.0 && p->delta_min >= 0.0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: stop tolerances must be >= 0");
-  acopf_status rc = acopf_qp_build(g, x, 0.0, p->hessian_mode, workspace, stream);
+  if (p->restore != 0 && p->restore != 1) return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: restore must be 0 or 1");
+  if (p->hessian_mode != ACOPF_HESSIAN_PSD && p->hessian_mode != ACOPF_HESSIAN_RAW &&
+      p->hessian_mode != ACOPF_HESSIAN_RAW_LOCAL)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown Hessian mode");
+  acopf_status rc = qp_build_impl(g, x, 0.0, p->restore ? kModeRestore : p->hessian_mode, workspace, stream);
   if (rc != ACOPF_OK) return rc;
+  const bool soc = p->soc && !p->restore;
   if (p->stop) hipLaunchKernelGGL(k_sqp_begin, dim3(blocks_for(w.n_scen, 64)), dim3(64), 0, s, w);
   if (p->pi_update != ACOPF_PI_ALWAYS && p->pi_update != ACOPF_PI_IF_CONVERGED)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_sqp_step: unknown multiplier update rule");
@@ -1856,12 +1888,12 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
   hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
   hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
-                     (int)p->pi_update, p->soc ? 1 : 0);
+                     (int)p->pi_update, soc ? 1 : 0, p->restore);
   hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w, 0);
   HIP_TRY(hipGetLastError());
   std::vector<acopf_admm_result> ar(w.n_scen);
   bool have_ar = false;
-  if (p->soc) {
+  if (soc) {
     // second-order correction of the rejected steps (end of Section II-D):
     // under capture the pass is always recorded (scenarios without a
     // rejected step are left out of it); otherwise it runs only when a

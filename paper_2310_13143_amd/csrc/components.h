@@ -159,36 +159,49 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
   const double bR = (c * r1 + 2.0 * wI * r2) / K2;
   const double bI = (s * r1 - 2.0 * wR * r2) / K2;
 
-  // Hessian of L_ij (eq. lag) in u = (w_i, th_i, wR, wI, w_j, th_j)
+  // Hessian of L_ij (eq. lag) in u = (w_i, th_i, wR, wI, w_j, th_j); for a
+  // restoration step (kModeRestore) the Hessian of 0.5 ||d||^2 instead,
+  // each bus variable's term shared among its lines by 1 / degree
   double H[6][6];
 #pragma unroll
   for (int a = 0; a < 6; ++a)
 #pragma unroll
     for (int b = 0; b < 6; ++b) H[a][b] = 0.0;
-  H[2][2] += 2.0 * p11;
-  H[3][3] += 2.0 * p11;
-  H[0][4] -= p11;
-  H[4][0] -= p11;
-  const double T = -wR * s + wI * c;
-  H[1][1] += p12 * T;
-  H[5][5] += p12 * T;
-  H[1][5] -= p12 * T;
-  H[5][1] -= p12 * T;
-  H[2][1] += p12 * c; H[1][2] += p12 * c;
-  H[2][5] -= p12 * c; H[5][2] -= p12 * c;
-  H[3][1] += p12 * s; H[1][3] += p12 * s;
-  H[3][5] -= p12 * s; H[5][3] -= p12 * s;
-  {
-    const double gp_ij[6] = {gii, 0.0, gij, bij, 0.0, 0.0};
-    const double gq_ij[6] = {-bii, 0.0, -bij, gij, 0.0, 0.0};
-    const double gp_ji[6] = {0.0, 0.0, gji, -bji, gjj, 0.0};
-    const double gq_ji[6] = {0.0, 0.0, -bji, -gji, -bjj, 0.0};
+  if (mode == kModeRestore) {
+    const double sf = 1.0 / (double)(w.bus_end_ptr[f + 1] - w.bus_end_ptr[f]);
+    const double st = 1.0 / (double)(w.bus_end_ptr[t + 1] - w.bus_end_ptr[t]);
+    H[0][0] = sf;
+    H[1][1] = sf;
+    H[2][2] = 1.0;
+    H[3][3] = 1.0;
+    H[4][4] = st;
+    H[5][5] = st;
+  } else {
+    H[2][2] += 2.0 * p11;
+    H[3][3] += 2.0 * p11;
+    H[0][4] -= p11;
+    H[4][0] -= p11;
+    const double T = -wR * s + wI * c;
+    H[1][1] += p12 * T;
+    H[5][5] += p12 * T;
+    H[1][5] -= p12 * T;
+    H[5][1] -= p12 * T;
+    H[2][1] += p12 * c; H[1][2] += p12 * c;
+    H[2][5] -= p12 * c; H[5][2] -= p12 * c;
+    H[3][1] += p12 * s; H[1][3] += p12 * s;
+    H[3][5] -= p12 * s; H[5][3] -= p12 * s;
+    {
+      const double gp_ij[6] = {gii, 0.0, gij, bij, 0.0, 0.0};
+      const double gq_ij[6] = {-bii, 0.0, -bij, gij, 0.0, 0.0};
+      const double gp_ji[6] = {0.0, 0.0, gji, -bji, gjj, 0.0};
+      const double gq_ji[6] = {0.0, 0.0, -bji, -gji, -bjj, 0.0};
 #pragma unroll
-    for (int a = 0; a < 6; ++a)
+      for (int a = 0; a < 6; ++a)
 #pragma unroll
-      for (int b = 0; b < 6; ++b)
-        H[a][b] -= 2.0 * p13 * (gp_ij[a] * gp_ij[b] + gq_ij[a] * gq_ij[b]) +
-                   2.0 * p14 * (gp_ji[a] * gp_ji[b] + gq_ji[a] * gq_ji[b]);
+        for (int b = 0; b < 6; ++b)
+          H[a][b] -= 2.0 * p13 * (gp_ij[a] * gp_ij[b] + gq_ij[a] * gq_ij[b]) +
+                     2.0 * p14 * (gp_ji[a] * gp_ji[b] + gq_ji[a] * gq_ji[b]);
+    }
   }
   // A (6x4): rows e0, e1, aR, aI, e2, e3; M = A^T H A, q = A^T H b
   double A[6][4];
@@ -327,20 +340,21 @@ ACOPF_HD bool build_line(const acopf_grid& g, const acopf_iterate& x, double del
   return ok;
 }
 
+// restore: the objective 0.5 (d_p^2 + d_q^2) of a restoration step.
 ACOPF_HD void build_gen(const acopf_grid& g, const acopf_iterate& x, double delta, const Workspace& w,
-                        int k) {
+                        int k, bool restore = false) {
   const int G = g.n_gen;
   const double p = x.pg[k], qv = x.qg[k];
   double* d = w.gen;
-  d[GF_FP * G + k] = 2.0 * g.cost2[k] * p + g.cost1[k];
-  d[GF_FPP * G + k] = 2.0 * g.cost2[k];
+  d[GF_FP * G + k] = restore ? 0.0 : 2.0 * g.cost2[k] * p + g.cost1[k];
+  d[GF_FPP * G + k] = restore ? 1.0 : 2.0 * g.cost2[k];
   const double phi = fmin(delta, g.pmax[k] - p), qhi = fmin(delta, g.qmax[k] - qv);
   d[GF_PLO * G + k] = fmin(fmax(-delta, g.pmin[k] - p), phi);
   d[GF_PHI * G + k] = phi;
   d[GF_QLO * G + k] = fmin(fmax(-delta, g.qmin[k] - qv), qhi);
   d[GF_QHI * G + k] = qhi;
   d[GF_FQ * G + k] = 0.0;
-  d[GF_FQQ * G + k] = 0.0;
+  d[GF_FQQ * G + k] = restore ? 1.0 : 0.0;
 }
 
 // p^{d,(k)}, q^{d,(k)} of bus i (constants after eq. acopf_qppf).

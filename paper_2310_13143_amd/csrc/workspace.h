@@ -45,6 +45,10 @@ enum GenField { GF_FP = 0, GF_FPP, GF_PLO, GF_PHI, GF_QLO, GF_QHI, GF_FQ, GF_FQQ
 // projection's QP (Section II-A, eq. linfeas) instead of an SQP subproblem.
 constexpr int kModeLinfeas = 3;
 
+// Line Hessian mode of a feasibility restoration step's QP: the objective
+// 0.5 ||d||^2 in place of the Lagrangian's Hessian (build_line).
+constexpr int kModeRestore = 4;
+
 enum BusFlag { BUS_REF = 1 };
 
 // Whole-batch synchronisation and error state.

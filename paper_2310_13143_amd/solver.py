@@ -190,11 +190,12 @@ class DeviceGrid:
         return d
 
     def _sqp_params(self, mu, delta_max, grow_ratio, hessian_mode, warm_start, admm: AdmmParams, lam, pi_update,
-                    soc=False, stop=None):
+                    soc=False, stop=None, restore=False):
         start = int(warm_start) if not isinstance(warm_start, bool) else int(warm_start)
         p = SqpParams(float(mu), float(delta_max), float(grow_ratio), int(hessian_mode), start, admm)
         p.pi_update = int(pi_update)
         p.soc = int(bool(soc))
+        p.restore = int(bool(restore))
         if stop is not None:
             p.stop = 1
             p.tol_primal, p.tol_dual, p.tol_step, p.delta_min = (float(v) for v in stop)
@@ -211,11 +212,13 @@ class DeviceGrid:
                  max_sweeps: int = 20000, eps: float = 1e-4, sweep_mode: int = _abi.SWEEP_PERSISTENT,
                  block_size: int = 0, max_blocks: int = 0, d: dict | None = None, lam=None,
                  trace: bool = False, pi_update: int = _abi.PI_ALWAYS, soc: bool = False,
-                 balance=None) -> dict:
+                 balance=None, restore: bool = False) -> dict:
         """One trust-region SQP iteration on the device; x is updated in place
         when the step is accepted.  warm_start: False/True (zero / previous
         multipliers) or one of _abi.START_*; lam = (lam_g, lam_l) for
-        START_GIVEN; soc: second-order correction of a rejected step.
+        START_GIVEN; soc: second-order correction of a rejected step;
+        restore: a feasibility restoration step instead (accepted iff it
+        lowers the constraint violation h; radius and pi unchanged).
         Returns the host-side decision record."""
         if d is None:
             d = self.empty_iterate()
@@ -224,7 +227,7 @@ class DeviceGrid:
         self._rho_g, self._rho_l = f64(rho_g), f64(rho_l)
         p = self._sqp_params(mu, delta_max, grow_ratio, hessian_mode, warm_start,
                              _admm_params(max_sweeps, eps, eps, sweep_mode, block_size, max_blocks, trace, balance),
-                             lam, pi_update, soc)
+                             lam, pi_update, soc, restore=restore)
         st = SqpState()
         st.delta = float(delta)
         cx, cd = self.c_iterate(x), self.c_iterate(d)

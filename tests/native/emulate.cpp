@@ -129,7 +129,7 @@ int emu_run(const acopf_grid* g, const acopf_iterate* x, double delta, int mode,
   int bad = 0;
   w.sync->hessian_mode = mode;
   for (int l = 0; l < nl; ++l) bad += build_line(*g, *x, delta, mode, w, l) ? 0 : 1;
-  for (int k = 0; k < ng; ++k) build_gen(*g, *x, delta, w, k);
+  for (int k = 0; k < ng; ++k) build_gen(*g, *x, delta, w, k, mode == kModeRestore);
   for (int i = 0; i < nb; ++i) build_bus(*g, *x, w, i);
   std::memcpy(w.rho_g, rho_g, sizeof(double) * 2 * ng);
   // caller layout [field][line] -> the workspace's line-by-line state

@@ -921,3 +921,46 @@ def test_linfeas_batch_matches_solo_runs_and_rejects_the_persistent_mode():
     with pytest.raises(AcopfError) as e:
         dg.linfeas(xb, sweep_mode=0)
     assert e.value.code == -5
+
+
+def test_sqp_with_restoration_matches_oracle():
+    """Feasibility restoration (hessian mode kModeRestore through
+    acopf_sqp_step's restore flag) on the 14-bus grid with its line limits
+    halved, where the radius collapses: the device iterations, restoration
+    steps included, follow the oracle's SQP with restoration (fixed sweep
+    budget): acceptance, the reduction of h of a restoration step, radii and
+    the final iterate."""
+    import dataclasses
+    print("[gpu] sqp ring14 restoration", flush=True)
+    g = grid_14()
+    g = dataclasses.replace(g, smax_ij=0.5 * g.smax_ij, smax_ji=0.5 * g.smax_ji)
+    x0, _ = start_point(g)
+    params = sqp.SqpParams(max_iter=8, max_sweeps=60, eps_pri=0.0, eps_dual=0.0, delta0=0.05, tol_step=0.0,
+                           tol_primal=0.0, tol_dual=0.0, delta_min=0.02, restore=True)
+    ref = sqp.solve(g, params, x0=x0)
+    assert any(r.restore and r.accepted for r in ref.records)
+    dg = _dev()(g)
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, None)
+    rho_g, rho_l = dg.rho_scalar(params.rho)
+    delta = params.delta0
+    warm = False
+    for k, rec in enumerate(ref.records):
+        if rec.restore:
+            out = dg.sqp_step(x, params.delta0, rho_g, rho_l, mu=params.mu_merit, warm_start=False,
+                              max_sweeps=params.max_sweeps, eps=0.0, sweep_mode=1, restore=True)
+            assert bool(out["accepted"]) == rec.accepted, k
+            assert abs(out["ared"] - rec.ared) <= 1e-6 * (1.0 + abs(rec.ared)), (k, out["ared"], rec.ared)
+            assert out["delta"] == params.delta0
+            delta, warm = params.delta0, False
+            continue
+        out = dg.sqp_step(x, delta, rho_g, rho_l, mu=params.mu_merit, delta_max=params.delta_max,
+                          warm_start=warm, max_sweeps=params.max_sweeps, eps=0.0, sweep_mode=1)
+        assert bool(out["accepted"]) == rec.accepted, k
+        assert abs(out["ared"] - rec.ared) <= 1e-6 * (1.0 + abs(rec.ared)), (k, out["ared"], rec.ared)
+        # a rejection sets the radius from the step's norm, which the ADMM
+        # iterates give to about 1e-8
+        assert abs(out["delta"] - rec.delta) <= 1e-8 * rec.delta, k
+        delta, warm = out["delta"], True
+    xf = {k: v.cpu().numpy() for k, v in x.items()}
+    for name in ("pg", "qg", "w", "th", "wR", "wI"):
+        assert rel_err(xf[name], getattr(ref.x, name)) <= 1e-7, name

@@ -498,3 +498,44 @@ def test_linfeas_sweeps_match_oracle(emu, case):
     for name, a in zip(("pg", "qg", "w", "th", "wR", "wI"), arrays[:6]):
         b = getattr(ref.x, name)
         assert np.abs(a - b).max() <= 1e-10 * (1 + np.abs(b).max()), name
+
+
+def test_restoration_qp_sweeps_and_merit_match_oracle(emu):
+    """A feasibility restoration step's QP (objective 0.5 ||d||^2, the same
+    constraints; line Hessian mode kModeRestore = 4, generators with unit
+    curvature on p and q) built and swept by the device code on the host
+    against the oracle's restore-mode QP and ADMM, and the constraint
+    violation h at x and x + d against the oracle."""
+    g = grid_14()
+    delta = 0.05
+    x, pi = _setup(g, delta, 50.0, 9)
+    Q = qpm.build_qp(g, x, pi, delta, "restore")
+    R = admm.Rho.scalar(g, 2e4)
+    nsw = 40
+    ref = admm.solve(g, Q, R, nsw, 0.0, 0.0)
+    hg = HostGrid(g)
+    cx, _ = hg.iterate(x, pi)
+    ws = np.zeros(emu.emu_workspace_bytes(g.n_bus, g.n_line, g.n_gen) // 8 + 64)
+    rho_g = np.full(2 * g.n_gen, 2e4); rho_l = np.full(8 * g.n_line, 2e4)
+    d_arrays = [np.zeros(n) for n in (g.n_gen, g.n_gen, g.n_bus, g.n_bus, g.n_line, g.n_line, 4 * g.n_line)]
+    cd = _abi.Iterate(*[a.ctypes.data for a in d_arrays])
+    rs = np.zeros(2 * nsw)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    rc = emu.emu_run(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.c_double(delta), 4, ptr(rho_g), ptr(rho_l),
+                     None, None, nsw, ctypes.c_void_p(base), ctypes.byref(cd), ptr(rs))
+    assert rc == 0
+    lay = _layout(emu, g, base)
+    slots = [emu.emu_slot8(k) for k in range(8)]
+    st = ref.state
+    from tests._util import rel_err_cols
+    assert rel_err_cols(lay("xl", 8 * g.n_line).reshape(-1, 8)[:, slots], st.xl) <= 1e-8
+    assert rel_err_cols(lay("xg", 2 * g.n_gen).reshape(2, -1).T, st.xg) <= 1e-8
+    assert rel_err_cols(lay("dw", g.n_bus), st.dw) <= 1e-8
+    dref = sqp.assemble_step(g, Q, st)
+    for a, name in zip(d_arrays[:6], ("pg", "qg", "w", "th", "wR", "wI")):
+        b = getattr(dref, name)
+        assert np.abs(a - b).max() <= 1e-8 * (1 + np.abs(b).max()), name
+    mer = np.zeros(8)
+    emu.emu_merit(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.byref(cd), ctypes.c_void_p(base), ptr(mer))
+    assert mer[3] == pytest.approx(acopf.infeas_h(g, x), rel=1e-10)
+    assert mer[4] == pytest.approx(acopf.infeas_h(g, x.plus(dref)), rel=1e-7)

@@ -256,3 +256,69 @@ def test_sqp_from_the_flat_start_with_the_linear_feasibility_projection():
     assert last.primal <= 1e-4 and last.dual <= 1e-4
     ref, viol = _full_acopf_slsqp(g, power_flow_start(g))
     assert viol < 1e-8 and abs(last.objective - ref) <= 1e-4 * abs(ref)
+
+
+def test_restoration_qp_objective_is_half_the_squared_step():
+    """The restoration QP (hessian mode "restore") has the same linearised
+    constraints and the objective 0.5 ||d||^2: for any bus-side (d_w, d_th),
+    the line terms 0.5 z^T M z + q^T z + c0 over all lines add up to
+    0.5 (sum_bus (d_w^2 + d_th^2) + sum_line (d_wR^2 + d_wI^2)) with d_wR,
+    d_wI from the elimination, and the generator terms are 0.5 (d_p^2 +
+    d_q^2); its constraints are those of the ordinary QP."""
+    g = grid_14()
+    rng = np.random.default_rng(31)
+    x = _random_iterate(g, rng)
+    pi = rng.standard_normal((g.n_line, 4))
+    Q = qpm.build_qp(g, x, pi, 0.05, "restore")
+    Q0 = qpm.build_qp(g, x, pi, 0.05, "psd")
+    for f in ("F", "f0", "G", "h", "lo", "hi", "aR", "bR", "aI", "bI"):
+        np.testing.assert_array_equal(getattr(Q.line, f), getattr(Q0.line, f))
+    np.testing.assert_array_equal(Q.bus.pdk, Q0.bus.pdk)
+    for _ in range(3):
+        dw, dth = rng.standard_normal(g.n_bus) * 0.01, rng.standard_normal(g.n_bus) * 0.01
+        z = np.stack([dw[g.f], dth[g.f], dw[g.t], dth[g.t]], 1)
+        L = Q.line
+        line = float(np.sum(0.5 * np.einsum("li,lij,lj->l", z, L.M, z) + (L.q * z).sum(1) + L.c0))
+        dwR = np.einsum("li,li->l", L.aR, z) + L.bR
+        dwI = np.einsum("li,li->l", L.aI, z) + L.bI
+        ref = 0.5 * (np.sum(dw ** 2) + np.sum(dth ** 2) + np.sum(dwR ** 2) + np.sum(dwI ** 2))
+        assert abs(line - ref) <= 1e-12 * (1 + ref)
+    np.testing.assert_array_equal(Q.gen.fp, 0.0)
+    np.testing.assert_array_equal(Q.gen.fpp, 1.0)
+    np.testing.assert_array_equal(Q.gen.fq, 0.0)
+    np.testing.assert_array_equal(Q.gen.fqq, 1.0)
+
+
+def _tight_ring14():
+    import dataclasses
+    g = grid_14()
+    return dataclasses.replace(g, smax_ij=0.5 * g.smax_ij, smax_ji=0.5 * g.smax_ji)
+
+
+def test_restoration_lowers_the_violation_after_a_collapse():
+    """With line limits halved the 14-bus SQP (exact QP solves, second-order
+    correction) collapses its radius after one step.  With restoration the
+    run takes restoration steps instead of stopping: the first is accepted,
+    lowers the constraint violation h (by the amount its step gives when
+    recomputed from the collapsed iterate) and restarts the radius; the run
+    ends with less than half the h of the run without restoration."""
+    g = _tight_ring14()
+    s = power_flow_start(g)
+    x0 = acopf.Iterate(s["pg"], s["qg"], s["w"], s["th"], s["wR"], s["wI"])
+    base = dict(max_iter=30, qp_solver="direct", soc=True, delta0=0.05, delta_min=1e-3)
+    r0 = sqp.solve(g, sqp.SqpParams(**base), x0=x0)
+    assert r0.outcome == "TR_COLLAPSED" and not any(q.restore for q in r0.records)
+    r1 = sqp.solve(g, sqp.SqpParams(restore=True, **base), x0=x0)
+    k = next(i for i, q in enumerate(r1.records) if q.restore)
+    assert [q.accepted for q in r1.records[:k]] == [q.accepted for q in r0.records[:k]]
+    rec = r1.records[k]
+    assert rec.accepted and rec.ared > 0 and rec.delta == base["delta0"]
+    h_final0 = acopf.infeas_h(g, r0.x)
+    h_final1 = acopf.infeas_h(g, r1.x)
+    assert h_final1 < 0.5 * h_final0
+    # replay up to the restoration to check its step
+    x = r0.x  # the collapsed iterate (no step was accepted after the first)
+    qp = qpm.build_qp(g, x, r0.pi, base["delta0"], "restore")
+    d = sqp.direct_qp_step(g, x, qp)[0]
+    xt = x.plus(d)
+    assert acopf.infeas_h(g, x) - acopf.infeas_h(g, xt) == pytest.approx(rec.ared, rel=1e-9)
