@@ -38,7 +38,9 @@ TRON for psi on the box (one trust-region step per iteration):
      inside the box, conjugate gradients on the model (stopping at the trust
      region boundary or at negative curvature), followed by a projected
      search along the resulting direction with the same decrease rule;
-  3. ratio test rho = (psi(z + s) - psi(z)) / q(s): the step is taken if
+  3. ratio test rho = (psi(z + s) - psi(z)) / q(s), the change of psi
+     formed from s without subtracting the two values (which cancel near a
+     minimiser whose psi is large): the step is taken if
      rho > 1e-4; Delta <- 0.25 ||s|| if rho < 0.25, Delta <- max(Delta,
      2 ||s||) if rho > 0.75; stop at a projected gradient <= omega.
 
@@ -80,6 +82,17 @@ def psi(z, Q, c, G, h, u, mu):
     g = G @ z - h
     t = np.maximum(0.0, g + mu * u)
     return 0.5 * z @ Q @ z + c @ z + float(np.sum(t * t - (mu * u) ** 2)) / (2.0 * mu)
+
+
+def psi_change(z, s, Q, c, G, h, u, mu):
+    """psi(z + s) - psi(z), in the algebraically equal form s^T (Q z + c) +
+    0.5 s^T Q s + sum_r (a1_r - a0_r)(a1_r + a0_r) / (2 mu) with a =
+    max(0, g + mu u): the difference of the two values themselves loses all
+    its digits near a minimiser whose psi is large."""
+    d_obj = float(s @ (Q @ z + c) + 0.5 * s @ Q @ s)
+    a0 = np.maximum(0.0, G @ z - h + mu * u)
+    a1 = np.maximum(0.0, G @ (z + s) - h + mu * u)
+    return d_obj + float(np.sum((a1 - a0) * (a1 + a0))) / (2.0 * mu)
 
 
 def psi_grad_hess(z, Q, c, G, h, u, mu):
@@ -192,7 +205,6 @@ def tron_step(z, grad, B, lo, hi, delta):
 def tron(z0, Q, c, G, h, u, mu, lo, hi, omega, delta, max_iter):
     """Box-constrained minimisation of psi from z0 to projected gradient <= omega."""
     z = _proj(z0, lo, hi)
-    f = psi(z, Q, c, G, h, u, mu)
     dmin = 1e-15 * (1.0 + float(np.abs(lo).max() + np.abs(hi).max()))
     it = 0
     for it in range(1, max_iter + 1):
@@ -201,11 +213,9 @@ def tron(z0, Q, c, G, h, u, mu, lo, hi, omega, delta, max_iter):
             return z, it - 1, max(delta, dmin)
         s = tron_step(z, grad, B, lo, hi, delta)
         q = _model(s, grad, B)
-        fn = psi(z + s, Q, c, G, h, u, mu)
-        rho = (fn - f) / q if q < 0 else -1.0
+        rho = psi_change(z, s, Q, c, G, h, u, mu) / q if q < 0 else -1.0
         if rho > 1e-4:
             z = _proj(z + s, lo, hi)
-            f = fn
         sn = float(np.linalg.norm(s))
         if rho < 0.25:
             delta = 0.25 * sn if sn > 0 else 0.25 * delta

@@ -64,16 +64,24 @@ struct Problem {
   double Q[4][4], c[4], lo[4], hi[4], G[2][4], h[2];
 };
 
-ACOPF_HD double psi(const Problem& P, const double z[4], const double u[2], double mu) {
-  double Qz[4];
+// psi(z + s) - psi(z) without subtracting the two values: s^T (Q z + c) +
+// 0.5 s^T Q s + sum_r (a1 - a0)(a1 + a0) / (2 mu), a = max(0, g + mu u).
+ACOPF_HD double psi_change(const Problem& P, const double z[4], const double s[4], const double u[2], double mu) {
+  double Qz[4], Qs[4];
   matvec(P.Q, z, Qz);
-  double v = 0.5 * dot(z, Qz) + dot(P.c, z);
+  matvec(P.Q, s, Qs);
+  double v = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v += s[i] * (Qz[i] + P.c[i]);
+  v += 0.5 * dot(s, Qs);
   double pen = 0.0;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    const double g = dot(P.G[r], z) - P.h[r];
-    const double t = fmax(0.0, g + mu * u[r]);
-    pen += t * t - (mu * u[r]) * (mu * u[r]);
+    const double g0 = dot(P.G[r], z) - P.h[r];
+    const double gs = dot(P.G[r], s);
+    const double a0 = fmax(0.0, g0 + mu * u[r]);
+    const double a1 = fmax(0.0, g0 + gs + mu * u[r]);
+    pen += (a1 - a0) * (a1 + a0);
   }
   return v + pen / (2.0 * mu);
 }
@@ -234,7 +242,6 @@ ACOPF_HD int tron(const Problem& P, double z[4], const double u[2], double mu, d
                   int max_iter) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) z[i] = proj1(z[i], P.lo[i], P.hi[i]);
-  double f = psi(P, z, u, mu);
   double amax = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) amax = fmax(amax, fabs(P.lo[i]));
@@ -249,15 +256,10 @@ ACOPF_HD int tron(const Problem& P, double z[4], const double u[2], double mu, d
     double s[4];
     tron_step(P, z, grad, B, delta, s);
     const double q = model(s, grad, B);
-    double zs[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) zs[i] = z[i] + s[i];
-    const double fn = psi(P, zs, u, mu);
-    const double rho = (q < 0.0) ? (fn - f) / q : -1.0;
+    const double rho = (q < 0.0) ? psi_change(P, z, s, u, mu) / q : -1.0;
     if (rho > 1e-4) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) z[i] = proj1(zs[i], P.lo[i], P.hi[i]);
-      f = fn;
+      for (int i = 0; i < 4; ++i) z[i] = proj1(z[i] + s[i], P.lo[i], P.hi[i]);
     }
     const double sn = norm(s);
     if (rho < 0.25)

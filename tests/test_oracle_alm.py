@@ -149,3 +149,42 @@ def test_relaxed_rows_give_the_local_solvers_point_on_lines_without_a_feasible_p
     assert np.median(err) < 1e-6 and np.percentile(err, 90) < 1e-4 and err.max() < 1e-3, \
         (np.median(err), np.percentile(err, 90), err.max())
     assert np.median(err_mm) > 1e-2
+
+
+def test_psi_change_equals_the_difference_of_values():
+    rng = np.random.default_rng(13)
+    Q, c, lo, hi, G, h = _random_lines(rng, 50, convex=False)
+    for k in range(50):
+        z = rng.uniform(lo[k], hi[k])
+        s = rng.standard_normal(4) * 0.05
+        u = np.abs(rng.standard_normal(2))
+        mu = 10.0 ** rng.uniform(-3, 1)
+        ref = alm.psi(z + s, Q[k], c[k], G[k], h[k], u, mu) - alm.psi(z, Q[k], c[k], G[k], h[k], u, mu)
+        got = alm.psi_change(z, s, Q[k], c[k], G[k], h[k], u, mu)
+        scale = abs(alm.psi(z, Q[k], c[k], G[k], h[k], u, mu)) + abs(ref) + 1.0
+        assert abs(got - ref) <= 1e-12 * scale
+
+
+def test_alm_converges_from_a_start_at_the_minimiser_of_stiff_lines():
+    """Strictly convex, stiff lines (line matrices with eigenvalues from 2e4
+    to 7e6 on a box of half-width 0.05, as penalties of 2e4 give on large
+    grids), rows far from binding, started a hair away from their minimiser
+    (the previous sweep's solution): the ratio test must see the model's
+    decrease although psi itself is large, and the method converges to the
+    exact minimiser."""
+    rng = np.random.default_rng(14)
+    n = 60
+    ok = 0
+    for k in range(n):
+        qm, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+        Q = qm @ np.diag([2e4, 1e5, 1e6, 7e6]) @ qm.T
+        lo, hi = np.full(4, -0.05), np.full(4, 0.05)
+        c = rng.standard_normal(4) * 2e5
+        G = rng.standard_normal((2, 4))
+        h = np.full(2, 5.0)
+        zr, _, _, feas = lineqp.solve_line_qps(Q[None], c[None], lo[None], hi[None], G[None], h[None])
+        r = alm.solve_line(Q, c, lo, hi, G, h, z0=zr[0] + 1e-9 * rng.standard_normal(4), u0=np.zeros(2))
+        assert r.converged, k
+        assert np.abs(r.z - zr[0]).max() <= 1e-8, k
+        ok += 1
+    assert ok == n
