@@ -116,12 +116,15 @@ typedef struct {
                            final penalties are exported by acopf_admm_state_get */
   double balance_mu;    /* e.g. 10 */
   double balance_tau;   /* e.g. 2, > 1 */
+  int32_t norm_inf;     /* 1: the stop test, r_norm and s_norm use infinity norms
+                           (largest |r_c|, |s_c| over the couplings) instead of
+                           Euclidean ones; 0 (default): Euclidean */
 } acopf_admm_params;
 
 typedef struct {
   int32_t sweeps;            /* sweeps run                                           */
   int32_t outcome;           /* acopf_admm_outcome                                   */
-  double r_norm, s_norm;     /* ||r||_2, ||s||_2 of the last sweep                   */
+  double r_norm, s_norm;     /* ||r||, ||s|| of the last sweep (the solve's norm)    */
   int32_t infeasible_lines;  /* line subproblems without a feasible point, last sweep */
   int32_t blocks;            /* grid size the sweeps ran with                        */
   int32_t status;            /* 0, or ACOPF_ERR_NUMERIC / ACOPF_ERR_NONCONVEX_LINE when the

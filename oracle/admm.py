@@ -193,8 +193,10 @@ def bus_update(grid, qp, xg, xl, st: AdmmState, rho: Rho):
     return xbar_g, xbar_f, dw, dth, nu
 
 
-def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None, line_solver: str = "exact"):
-    """One ADMM iteration of Algorithm 2; returns (new state, r, s, feasible)."""
+def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None, line_solver: str = "exact", norm: str = "2"):
+    """One ADMM iteration of Algorithm 2; returns (new state, r, s, feasible)
+    with r, s the Euclidean norms of the primal and dual residuals over all
+    couplings, or their infinity norms (norm "inf")."""
     xg = gen_update(qp, st, rho)
     xl, mu, feas = line_update(grid, qp, st, rho, Q, line_solver)
     xbar_g, xbar_f, dw, dth, nu = bus_update(grid, qp, xg, xl, st, rho)
@@ -203,8 +205,15 @@ def sweep(grid, qp, st: AdmmState, rho: Rho, Q=None, line_solver: str = "exact")
     xbar_l_old = np.concatenate([st.xbar_f, np.stack([st.dw[f], st.dth[f], st.dw[t], st.dth[t]], 1)], 1)
     lam_g = st.lam_g + rho.g * (xg - xbar_g)
     lam_l = st.lam_l + rho.l * (xl - xbar_l)
-    r2 = np.sum((xg - xbar_g) ** 2) + np.sum((xl - xbar_l) ** 2)
-    s2 = np.sum((rho.g * (xbar_g - st.xbar_g)) ** 2) + np.sum((rho.l * (xbar_l - xbar_l_old)) ** 2)
+    if norm == "inf":
+        r2 = max(np.max((xg - xbar_g) ** 2, initial=0.0), np.max((xl - xbar_l) ** 2, initial=0.0))
+        s2 = max(np.max((rho.g * (xbar_g - st.xbar_g)) ** 2, initial=0.0),
+                 np.max((rho.l * (xbar_l - xbar_l_old)) ** 2, initial=0.0))
+    elif norm == "2":
+        r2 = np.sum((xg - xbar_g) ** 2) + np.sum((xl - xbar_l) ** 2)
+        s2 = np.sum((rho.g * (xbar_g - st.xbar_g)) ** 2) + np.sum((rho.l * (xbar_l - xbar_l_old)) ** 2)
+    else:
+        raise ValueError(norm)
     new = AdmmState(xg, xbar_g, lam_g, xl, xbar_f, lam_l, dw, dth, mu, nu)
     return new, float(np.sqrt(r2)), float(np.sqrt(s2)), feas
 
@@ -233,8 +242,9 @@ def balance_factor(r: float, s: float, b: Balance) -> float:
 
 def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
           state: AdmmState | None = None, record: bool = False, record_states: bool = False,
-          balance: Balance | None = None, line_solver: str = "exact"):
-    """Algorithm 2 until ||r|| <= eps_pri and ||s|| <= eps_dual or max_sweeps;
+          balance: Balance | None = None, line_solver: str = "exact", norm: str = "2"):
+    """Algorithm 2 until ||r|| <= eps_pri and ||s|| <= eps_dual (Euclidean
+    norms, or infinity norms with norm "inf") or max_sweeps;
     with ``balance``, residual balancing of the penalties between sweeps
     (the result's ``rho`` holds the final penalties)."""
     st = cold_state(grid) if state is None else state.copy()
@@ -245,7 +255,7 @@ def solve(grid, qp, rho: Rho, max_sweeps: int, eps_pri: float, eps_dual: float,
     bad = 0
     k = 0
     for k in range(1, max_sweeps + 1):
-        st, r, s, feas = sweep(grid, qp, st, rho, Q, line_solver)
+        st, r, s, feas = sweep(grid, qp, st, rho, Q, line_solver, norm)
         bad = int((~feas).sum())
         if record:
             hist.append((r, s))

@@ -45,7 +45,8 @@ class Iterate(ctypes.Structure):
 class AdmmParams(ctypes.Structure):
     _fields_ = [("max_sweeps", c_int32), ("eps_pri", c_double), ("eps_dual", c_double),
                 ("sweep_mode", c_int32), ("block_size", c_int32), ("max_blocks", c_int32), ("trace", c_int32),
-                ("balance_every", c_int32), ("balance_mu", c_double), ("balance_tau", c_double)]
+                ("balance_every", c_int32), ("balance_mu", c_double), ("balance_tau", c_double),
+                ("norm_inf", c_int32)]
 
 
 class AdmmResult(ctypes.Structure):

@@ -65,13 +65,15 @@ __device__ double block_sum(double v, double* lds) {
   return t;
 }
 
-// block_sum of two values at once, the result valid in thread 0 only (the
-// same order and arithmetic as block_sum; two barriers instead of six).
-__device__ void block_sum2_to_first(double& a, double& b, double* lds) {
+// block_sum of two values at once (inf: their maxima), the result valid in
+// thread 0 only (the same order and arithmetic as block_sum; two barriers
+// instead of six).
+__device__ void block_sum2_to_first(double& a, double& b, double* lds, bool inf = false) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
+    const double ta = __shfl_xor(a, off, 64), tb = __shfl_xor(b, off, 64);
+    a = inf ? fmax(a, ta) : a + ta;
+    b = inf ? fmax(b, tb) : b + tb;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
@@ -82,8 +84,8 @@ __device__ void block_sum2_to_first(double& a, double& b, double* lds) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double ta = 0.0, tb = 0.0;
-    for (int k = 0; k < nw; ++k) ta += lds[k];
-    for (int k = 0; k < nw; ++k) tb += lds[8 + k];
+    for (int k = 0; k < nw; ++k) ta = inf ? fmax(ta, lds[k]) : ta + lds[k];
+    for (int k = 0; k < nw; ++k) tb = inf ? fmax(tb, lds[8 + k]) : tb + lds[8 + k];
     a = ta;
     b = tb;
   }
@@ -272,7 +274,7 @@ __global__ void k_clear_flags(Workspace w, int mode) {
 
 // Start of a solve: per-scenario stop state, barrier flags, block tables of
 // both phases for block size bs.
-__global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
+__global__ void k_reset_solve(Workspace w, int blocks, int bs, int items, int norm_inf) {
   for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
     ScenState* sc = &w.scen[s];
@@ -297,6 +299,7 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
     sy->n_done = failed;
     sy->barrier_error = 0;
     sy->blocks = blocks;
+    sy->norm_inf = norm_inf;
     int lb = 0, bb = 0;
     for (int s = 0; s < w.n_scen; ++s) {
       w.line_blk_off[s] = lb;
@@ -315,13 +318,14 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items) {
 // Sum of scenario s's partials [p0, p1) (fixed order), stop decision.
 __device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int max_sweeps, double eps_pri,
                                 double eps_dual, double* lds) {
+  const bool inf = w.sync->norm_inf != 0;
   double r2 = 0.0, s2 = 0.0;
   for (int b = p0 + (int)threadIdx.x; b < p1; b += blockDim.x) {
-    r2 += w.partials[b];
-    s2 += w.partials[w.max_partials + b];
+    acc_norm(r2, w.partials[b], inf);
+    acc_norm(s2, w.partials[w.max_partials + b], inf);
   }
-  r2 = block_sum(r2, lds);
-  s2 = block_sum(s2, lds);
+  r2 = inf ? block_max(r2, lds) : block_sum(r2, lds);
+  s2 = inf ? block_max(s2, lds) : block_sum(s2, lds);
   if (threadIdx.x == 0) {
     ScenState* sc = &w.scen[s];
     const int k = sc->sweeps + 1;
@@ -351,6 +355,7 @@ __device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int m
 // shuffles (every lane ends with the same bits), so each kernel that
 // evaluates the stop test gets the same value.  Valid in the first wave.
 __device__ void sweep_sums(const Workspace& w, int p0, int p1, double& r2, double& s2) {
+  const bool inf = w.sync->norm_inf != 0;
   double a = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
     // up to 16 partials per lane are loaded before any is added (one round
@@ -365,15 +370,15 @@ __device__ void sweep_sums(const Workspace& w, int p0, int p1, double& r2, doubl
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        a += ra[j];
-        b += rb[j];
+        acc_norm(a, ra[j], inf);
+        acc_norm(b, rb[j], inf);
       }
     }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
+    acc_norm(a, __shfl_xor(a, off, 64), inf);
+    acc_norm(b, __shfl_xor(b, off, 64), inf);
   }
   r2 = a;
   s2 = b;
@@ -561,15 +566,16 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   }
   __syncthreads();
   double rr = 0.0, ss = 0.0;
+  const bool inf = w.sync->norm_inf != 0;
   if (whole) {
-    bus_whole_update<kTrace>(g, w, bus, rr, ss);
+    bus_whole_update<kTrace>(g, w, bus, rr, ss, inf);
   } else if (bus >= 0) {
     double res[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) res[m] = bres[m][head];
-    bus_item_update<kTrace>(w, code, v, res, rr, ss);
+    bus_item_update<kTrace>(w, code, v, res, rr, ss, inf);
   }
-  block_sum2_to_first(rr, ss, lds);
+  block_sum2_to_first(rr, ss, lds, inf);
   if (t == 0) {
     w.partials[blockIdx.x] = rr;
     w.partials[w.max_partials + blockIdx.x] = ss;
@@ -696,9 +702,10 @@ __global__ void __launch_bounds__(256) k_sweep_persistent(acopf_grid g, Workspac
       if ((LOCAL ? update_line_local(w, l) : update_line(g, w, l)) != 0) atomicAdd(&sc->infeasible[k & 1], 1);
     grid_barrier(w, 2u * k + 1u, [] {});
     double r2 = 0.0, s2 = 0.0;
-    for (int i = gtid(); i < g.n_bus; i += gstride()) update_bus(g, w, i, r2, s2);
-    r2 = block_sum(r2, lds);
-    s2 = block_sum(s2, lds);
+    const bool inf = sy->norm_inf != 0;
+    for (int i = gtid(); i < g.n_bus; i += gstride()) update_bus(g, w, i, r2, s2, inf);
+    r2 = inf ? block_max(r2, lds) : block_sum(r2, lds);
+    s2 = inf ? block_max(s2, lds) : block_sum(s2, lds);
     if (threadIdx.x == 0) {
       w.partials[blockIdx.x] = r2;
       w.partials[w.max_partials + blockIdx.x] = s2;
@@ -1622,6 +1629,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   if (!grid_ok(g) || !p || !workspace) return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: null argument");
   if (p->max_sweeps < 0 || !(p->eps_pri >= 0.0) || !(p->eps_dual >= 0.0))
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: bad parameters");
+  if (p->norm_inf != 0 && p->norm_inf != 1)
+    return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: norm_inf must be 0 or 1");
   const int bs = p->block_size > 0 ? p->block_size : kDefaultBlock;
   if (bs % 64 != 0 || bs > 256)
     return fail(ACOPF_ERR_INVALID_ARG, "acopf_admm_solve: block_size must be a multiple of 64, <= 256");
@@ -1630,7 +1639,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
   const int ns = w.n_scen;
   const int reset_blocks = blocks_for(std::max(w.max_partials, ns), 256);
   if (p->max_sweeps == 0) {
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, 0, bs, 0);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, 0, bs, 0, p->norm_inf);
     HIP_TRY(hipGetLastError());
     if (result) return acopf_admm_result_get(g, workspace, stream, result);
     return ACOPF_OK;
@@ -1685,7 +1694,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     // a stream under capture records plain launches, and every chunk up to
     // the cap (the stop test then acts on the device only)
     const bool use_graph = p->sweep_mode == ACOPF_SWEEP_GRAPH && !capturing;
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs, 1);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs, 1, p->norm_inf);
     for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
       const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
       hipGraphExec_t ge = nullptr;
@@ -1731,7 +1740,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     if (p->max_blocks > 0) nblk = std::min<long long>(nblk, p->max_blocks);
     nblk = std::min<long long>(nblk, w.max_partials);
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nblk, bs, 0);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nblk, bs, 0, p->norm_inf);
     acopf_grid gg = *g;
     int ms = p->max_sweeps;
     double ep = p->eps_pri, ed = p->eps_dual;

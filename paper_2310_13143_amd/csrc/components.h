@@ -556,6 +556,11 @@ ACOPF_HD bool line_neighbour_check(const Workspace& w, int l, int base, int idx,
   return check_working_set(Pp, c, lo, hi, G, h, m, res);
 }
 
+// A residual term added to a running norm of the stop test: the sum of
+// squares (Euclidean norms) or the largest square (infinity norms; the
+// square root of either is the norm).
+ACOPF_HD void acc_norm(double& acc, double v2, bool inf) { acc = inf ? fmax(acc, v2) : acc + v2; }
+
 // Generator update (eq. gen_kernel, closed form clamp) of generator k.
 ACOPF_HD void update_gen(const Workspace& w, int k) {
   const int G = w.n_gen;
@@ -582,7 +587,8 @@ ACOPF_HD void update_gen(const Workspace& w, int k) {
 // kTrace: also add |r_c| and |s_c| of every coupling at the bus to the
 // workspace's trace sums.
 template <bool kTrace = false>
-ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2) {
+ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double& r2, double& s2,
+                         bool inf = false) {
   // Line ends are visited in chunks of kChunk: the chunk's CSR entries are
   // loaded together, then all of its coupling values, so a bus of degree d
   // waits on 2 ceil(d / kChunk) memory round trips per pass instead of 2 d.
@@ -670,8 +676,8 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
       const double ds = rho * (xb - w.xbar_g[idx]);
       w.lam_g[idx] = lam_new;
       w.xbar_g[idx] = xb;
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+      acc_norm(rr, (xv - xb) * (xv - xb), inf);
+      acc_norm(ss, ds * ds, inf);
       if (kTrace) {
         w.tr_r_g[idx] += fabs(xv - xb);
         w.tr_s_g[idx] += fabs(ds);
@@ -724,8 +730,8 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
         const double ds = rho * (xb - v[j][12 + m]);
         w.lam_l[lc8(l[j], kp + m)] = lam_new;
         w.xbar_f[lc4(l[j], kp + m)] = xb;
-        rr += (xv - xb) * (xv - xb);
-        ss += ds * ds;
+        acc_norm(rr, (xv - xb) * (xv - xb), inf);
+        acc_norm(ss, ds * ds, inf);
         if (kTrace) {
           w.tr_r_l[(kp + m) * L + l[j]] += fabs(xv - xb);
           w.tr_s_l[(kp + m) * L + l[j]] += fabs(ds);
@@ -739,8 +745,8 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
         const double ds = rho * (xb - ((m == 0) ? dw_old : dth_old));
         w.lam_l[lc8(l[j], kw + m)] = lam + rho * (xv - xb);
         w.xbar_v[lc4(l[j], 2 * sd[j] + m)] = xb;
-        rr += (xv - xb) * (xv - xb);
-        ss += ds * ds;
+        acc_norm(rr, (xv - xb) * (xv - xb), inf);
+        acc_norm(ss, ds * ds, inf);
         if (kTrace) {
           w.tr_r_l[(kw + m) * L + l[j]] += fabs(xv - xb);
           w.tr_s_l[(kw + m) * L + l[j]] += fabs(ds);
@@ -752,8 +758,8 @@ ACOPF_HD void update_bus(const acopf_grid& g, const Workspace& w, int i, double&
   w.dth[i] = dth_new;
   w.nu[i] = nup;
   w.nu[w.n_bus + i] = nuq;
-  r2 += rr;
-  s2 += ss;
+  acc_norm(r2, rr, inf);
+  acc_norm(s2, ss, inf);
 }
 
 // The bus update of update_bus split by coupling item (one line end or one
@@ -856,7 +862,7 @@ ACOPF_HD void bus_item_solve(const double sum[8], const double bc[7], double out
 // ||s||^2 (kTrace: also the trace sums).
 template <bool kTrace = false>
 ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], const double res[6], double& rr,
-                              double& ss) {
+                              double& ss, bool inf = false) {
   if (code >= 0) {
     const int L = w.n_line;
     const int l = code >> 1, sd = code & 1;
@@ -869,8 +875,8 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
       const double ds = rho * (xb - v[12 + m]);
       w.lam_l[lc8(l, kp + m)] = lam_new;
       w.xbar_f[lc4(l, kp + m)] = xb;
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+      acc_norm(rr, (xv - xb) * (xv - xb), inf);
+      acc_norm(ss, ds * ds, inf);
       if (kTrace) {
         w.tr_r_l[(kp + m) * L + l] += fabs(xv - xb);
         w.tr_s_l[(kp + m) * L + l] += fabs(ds);
@@ -883,8 +889,8 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
       const double ds = rho * (xb - res[4 + m]);
       w.lam_l[lc8(l, kw + m)] = lam + rho * (xv - xb);
       w.xbar_v[lc4(l, 2 * sd + m)] = xb;
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+      acc_norm(rr, (xv - xb) * (xv - xb), inf);
+      acc_norm(ss, ds * ds, inf);
       if (kTrace) {
         w.tr_r_l[(kw + m) * L + l] += fabs(xv - xb);
         w.tr_s_l[(kw + m) * L + l] += fabs(ds);
@@ -901,8 +907,8 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
       const double ds = rho * (xb - v[6 + j]);
       w.lam_g[idx] = lam_new;
       w.xbar_g[idx] = xb;
-      rr += (xv - xb) * (xv - xb);
-      ss += ds * ds;
+      acc_norm(rr, (xv - xb) * (xv - xb), inf);
+      acc_norm(ss, ds * ds, inf);
       if (kTrace) {
         w.tr_r_g[idx] += fabs(xv - xb);
         w.tr_s_g[idx] += fabs(ds);
@@ -917,7 +923,8 @@ ACOPF_HD void bus_item_update(const Workspace& w, int code, const double v[14], 
 // item's values are loaded again for its update; nothing has changed them
 // in between (a generator's own update is recomputed with the same result).
 template <bool kTrace = false>
-ACOPF_HD void bus_whole_update(const acopf_grid& g, const Workspace& w, int i, double& rr, double& ss) {
+ACOPF_HD void bus_whole_update(const acopf_grid& g, const Workspace& w, int i, double& rr, double& ss,
+                               bool inf = false) {
   const int g0 = w.bus_gen_ptr[i], g1 = w.bus_gen_ptr[i + 1];
   const int e0 = w.bus_end_ptr[i], e1 = w.bus_end_ptr[i + 1];
   const int n = (g1 - g0) + (e1 - e0);
@@ -940,7 +947,7 @@ ACOPF_HD void bus_whole_update(const acopf_grid& g, const Workspace& w, int i, d
     const int code = (j < g1 - g0) ? -(w.bus_gen[g0 + j] + 1) : w.bus_end[e0 + j - (g1 - g0)];
     double v[14], a[8];
     bus_item_terms(w, code, v, a);
-    bus_item_update<kTrace>(w, code, v, out, rr, ss);
+    bus_item_update<kTrace>(w, code, v, out, rr, ss, inf);
   }
 }
 

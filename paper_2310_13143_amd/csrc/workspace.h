@@ -61,6 +61,7 @@ struct SyncState {
   int nonconvex;           // raw mode: a line matrix failed its Cholesky
   int blocks;              // grid size of the last solve
   int hessian_mode;        // acopf_hessian_mode of the last QP build, or kModeLinfeas
+  int norm_inf;            // the running solve's stop test uses infinity norms
 };
 
 // Per-scenario ADMM and SQP state.

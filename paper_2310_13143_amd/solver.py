@@ -41,11 +41,13 @@ def _pack(grids):
     return arrays, (nb.astype(np.int32), nl.astype(np.int32), ng.astype(np.int32), refs)
 
 
-def _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance) -> AdmmParams:
+def _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance,
+                 norm_inf=False) -> AdmmParams:
     p = AdmmParams(int(max_sweeps), float(eps_pri), float(eps_dual), int(sweep_mode), int(block_size),
                    int(max_blocks), int(bool(trace)))
     if balance is not None:
         p.balance_every, p.balance_mu, p.balance_tau = int(balance[0]), float(balance[1]), float(balance[2])
+    p.norm_inf = int(bool(norm_inf))
     return p
 
 
@@ -137,9 +139,11 @@ class DeviceGrid:
 
     def admm_solve(self, max_sweeps: int, eps_pri: float = 0.0, eps_dual: float = 0.0,
                    sweep_mode: int = _abi.SWEEP_PERSISTENT, block_size: int = 0, max_blocks: int = 0,
-                   sync: bool = True, trace: bool = False, balance=None):
-        """balance = (every, mu, tau): residual balancing of the penalties."""
-        p = _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance)
+                   sync: bool = True, trace: bool = False, balance=None, norm_inf: bool = False):
+        """balance = (every, mu, tau): residual balancing of the penalties;
+        norm_inf: stop test and reported norms on infinity norms."""
+        p = _admm_params(max_sweeps, eps_pri, eps_dual, sweep_mode, block_size, max_blocks, trace, balance,
+                         norm_inf)
         res = AdmmResult()
         check(self.lib.acopf_admm_solve(ctypes.byref(self.cgrid), ctypes.byref(p), self.ws, self.stream,
                                         ctypes.byref(res) if sync else None))

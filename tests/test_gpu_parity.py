@@ -1010,3 +1010,29 @@ def test_rgg70000_local_line_solver_sampled():
     # an iteration whose branches (ratio test, active set) sit on a rounding
     # boundary may part ways on a line now and then; all but 1% must match
     assert bad <= len(sample) // 100, bad
+
+
+@pytest.mark.parametrize("mode", [0, 2], ids=["persistent", "graph"])
+def test_infinity_norm_stop_test_matches_oracle(mode):
+    """The stop test on infinity norms (acopf_admm_params.norm_inf): the
+    reported norms after a fixed sweep count, and the stop sweep of a
+    stopped solve, against the oracle's ADMM with infinity norms."""
+    print(f"[gpu] infinity norm mode={mode}", flush=True)
+    g = grid_14()
+    x, pi = start_point(g, pi_scale=20.0, seed=3)
+    rho = _rho(g, 4)
+    Q = qpm.build_qp(g, x, pi, 0.05, "psd")
+    ref = admm.solve(g, Q, rho, 60, 0.0, 0.0, norm="inf")
+    dg, xi, res, st = _run_gpu(g, x, pi, 0.05, rho, None, None, 60, mode=mode, norm_inf=True)
+    assert res["sweeps"] == 60
+    assert abs(res["r"] - ref.r) <= 1e-7 * ref.r and abs(res["s"] - ref.s) <= 1e-7 * ref.s
+    _compare_state(st, ref.state)
+    # stop at ||r||_inf <= 3e-3 and ||s||_inf <= 20 (the dual residuals carry
+    # the penalties of about 2e4)
+    ref2 = admm.solve(g, Q, rho, 400, 3e-3, 20.0, norm="inf")
+    assert ref2.converged and ref2.sweeps < 400
+    dg.qp_build(xi, 0.05, 0)
+    dg.admm_init(rho.g.T.reshape(-1), rho.l.T.reshape(-1))
+    res2 = dg.admm_solve(400, 3e-3, 20.0, sweep_mode=mode, norm_inf=True)
+    assert res2["converged"] and abs(res2["sweeps"] - ref2.sweeps) <= 1
+    assert res2["r"] <= 3e-3 and res2["s"] <= 20.0

@@ -325,3 +325,31 @@ def test_pi_recovery_equals_sensitivity_of_optimal_value():
             slope = (vp - vm) / (2 * eps)
             assert abs(pir[line, k] + slope) < 1e-4 * (1 + abs(slope)), (line, k, pir[line, k], slope)
     np.testing.assert_allclose(pir[:, 2:], -st.mu)
+
+
+def test_infinity_norm_stop_test_bounds_the_euclidean_one():
+    """One sweep from the same state with both residual norms: the infinity
+    norms are the largest coupling residuals, so ||.||_inf <= ||.||_2 <=
+    sqrt(couplings) ||.||_inf, and the state is the same."""
+    from oracle import admm, qp as qpm
+    from synth.grids import grid_14, power_flow_start
+    from oracle import acopf
+    g = grid_14()
+    s = power_flow_start(g)
+    x = acopf.Iterate(s["pg"], s["qg"], s["w"], s["th"], s["wR"], s["wI"])
+    rng = np.random.default_rng(2)
+    pi = rng.standard_normal((g.n_line, 4)) * 20
+    Q = qpm.build_qp(g, x, pi, 0.05)
+    rho = admm.Rho.scalar(g, 2e4)
+    st = admm.warm_state(g, rng.standard_normal((g.n_gen, 2)) * 100, rng.standard_normal((g.n_line, 8)) * 100)
+    n = 2 * g.n_gen + 8 * g.n_line
+    for _ in range(3):
+        s2, r2, q2, _ = admm.sweep(g, Q, st, rho)
+        si, ri, qi, _ = admm.sweep(g, Q, st, rho, norm="inf")
+        np.testing.assert_array_equal(s2.xl, si.xl)
+        assert ri <= r2 * (1 + 1e-15) and r2 <= np.sqrt(n) * ri * (1 + 1e-15)
+        assert qi <= q2 * (1 + 1e-15) and q2 <= np.sqrt(n) * qi * (1 + 1e-15)
+        st = s2
+    res = admm.solve(g, Q, rho, 400, 1e-3, 1e-3, norm="inf")
+    res2 = admm.solve(g, Q, rho, 400, 1e-3, 1e-3)
+    assert res.sweeps <= res2.sweeps
