@@ -354,8 +354,11 @@ __device__ void finish_scenario(const Workspace& w, int s, int p0, int p1, int m
 // [p0, p1): the first wave adds them lane-strided, then by a butterfly of
 // shuffles (every lane ends with the same bits), so each kernel that
 // evaluates the stop test gets the same value.  Valid in the first wave.
+// kInf: the partials are maxima of squares (infinity norms); a template
+// parameter, so that the Euclidean sum is a plain chain of adds.
+template <bool kInf>
 __device__ void sweep_sums(const Workspace& w, int p0, int p1, double& r2, double& s2) {
-  const bool inf = w.sync->norm_inf != 0;
+  constexpr bool inf = kInf;
   double a = 0.0, b = 0.0;
   if (threadIdx.x < 64) {
     // up to 16 partials per lane are loaded before any is added (one round
@@ -410,8 +413,9 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // most 256 registers per lane: two waves per SIMD (measured faster than one
 // wave with more registers; a cap of three waves spills hundreds of bytes).
 // Start of a line-phase block: its scenario s and, with `test`, the stop
-// test of the previous sweep (launch modes).  False when the block has
-// nothing to do (scenario done or stopped now).
+// test of the previous sweep (launch modes; 1 on Euclidean norms, 2 on
+// infinity norms, an argument so that no flag load precedes the test).
+// False when the block has nothing to do (scenario done or stopped now).
 __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single, int test, double eps_pri,
                                                  double eps_dual, int& s, int* s_stop) {
   s = 0;
@@ -424,7 +428,8 @@ __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single,
   }
   if (test) {
     double r2, s2;
-    sweep_sums(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+    if (test == 2) sweep_sums<true>(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+    else sweep_sums<false>(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
     if (threadIdx.x == 0) {
       const bool stop = stop_met(r2, s2, eps_pri, eps_dual);
       // the scenario's first block records the stop; every block obeys it
@@ -444,7 +449,8 @@ __device__ __forceinline__ int line_of_thread(const Workspace& w, int single, in
   return l < (single ? w.n_line : w.scen_line_off[s + 1]) ? l : -1;
 }
 
-// `test`: first evaluate the stop test of the previous sweep (launch modes).
+// `test`: first evaluate the stop test of the previous sweep (launch modes;
+// 1 Euclidean, 2 infinity norms).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
@@ -524,8 +530,10 @@ k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double e
 // closed form; then every thread updates its couplings.  A bus of degree d
 // costs one round of independent loads on d threads instead of a
 // dependent walk over its CSR on one.  Blocks past a scenario's last item
-// block exit at once.  The scenario's first block counts the sweep.
-template <bool kTrace, int kBlock>
+// block exit at once.  The scenario's first block counts the sweep.  kInf:
+// the residual partials are maxima of squares (infinity norms), a template
+// parameter so that the Euclidean kernel carries no selects.
+template <bool kTrace, int kBlock, bool kInf>
 __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w, int single) {
   __shared__ double terms[8][kBlock];
   __shared__ double bres[6][kBlock];
@@ -541,6 +549,7 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   const int t = threadIdx.x;
   const size_t slot = (size_t)blockIdx.x * kBlock + t;
   const int code = w.item_code[slot], bus = w.item_bus[slot], head = w.item_head[slot], len = w.item_len[slot];
+  constexpr bool inf = kInf;
   const bool whole = code == kItemBus;  // a bus wider than a block: its thread walks all its items
   const bool lead = bus >= 0 && t == head && !whole;
   double bc[7];
@@ -566,7 +575,6 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   }
   __syncthreads();
   double rr = 0.0, ss = 0.0;
-  const bool inf = w.sync->norm_inf != 0;
   if (whole) {
     bus_whole_update<kTrace>(g, w, bus, rr, ss, inf);
   } else if (bus >= 0) {
@@ -595,7 +603,8 @@ __global__ void k_finish_phase(Workspace w, int max_sweeps, double eps_pri, doub
   const int s = blockIdx.x;
   if (w.sync->done || w.scen[s].done) return;
   double r2, s2;
-  sweep_sums(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+  if (w.sync->norm_inf) sweep_sums<true>(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
+  else sweep_sums<false>(w, w.bus_blk_off[s], w.bus_blk_off[s + 1], r2, s2);
   if (threadIdx.x == 0) {
     const bool stop = stop_met(r2, s2, eps_pri, eps_dual) || w.scen[s].sweeps >= max_sweeps;
     record_sweep(w, s, r2, s2, stop, eps_pri, eps_dual);
@@ -1442,15 +1451,31 @@ struct SweepLaunch {
   Workspace w;
   int nbl, nbb, bs, single, ns, trace, max_sweeps;
   int solver;  // line kernel: 0 exact, 1 local (ALM + TRON), 2 linear feasibility projection
+  int norm_inf;  // infinity norms (bus partials, stop test)
   double eps_pri, eps_dual;
 };
+
+template <bool kTrace, int kBlock>
+void launch_bus_items_norm(const SweepLaunch& a, dim3 grid, dim3 block, hipStream_t s) {
+  if (a.norm_inf)
+    hipLaunchKernelGGL((k_bus_items<kTrace, kBlock, true>), grid, block, 0, s, a.g, a.w, a.single);
+  else
+    hipLaunchKernelGGL((k_bus_items<kTrace, kBlock, false>), grid, block, 0, s, a.g, a.w, a.single);
+}
+
+void launch_bus_items(const SweepLaunch& a, bool small, dim3 grid, dim3 block, hipStream_t s) {
+  if (a.trace && small) launch_bus_items_norm<true, 64>(a, grid, block, s);
+  else if (a.trace) launch_bus_items_norm<true, 256>(a, grid, block, s);
+  else if (small) launch_bus_items_norm<false, 64>(a, grid, block, s);
+  else launch_bus_items_norm<false, 256>(a, grid, block, s);
+}
 
 // n sweeps: each line phase but the first tests the sweep before it; the
 // chunk ends with k_finish_phase.
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   const bool small = item_block_for(a.g.n_line) == 64;
   const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
-  const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? 1 : 0;
+  const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? (a.norm_inf ? 2 : 1) : 0;
   for (int k = 0; k < n; ++k) {
     if (a.solver == 1)
       hipLaunchKernelGGL(k_line_phase_local, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
@@ -1461,14 +1486,7 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
     else
       hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
                          (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
-    if (a.trace && small)
-      hipLaunchKernelGGL((k_bus_items<true, 64>), grid, block, 0, s, a.g, a.w, a.single);
-    else if (a.trace)
-      hipLaunchKernelGGL((k_bus_items<true, 256>), grid, block, 0, s, a.g, a.w, a.single);
-    else if (small)
-      hipLaunchKernelGGL((k_bus_items<false, 64>), grid, block, 0, s, a.g, a.w, a.single);
-    else
-      hipLaunchKernelGGL((k_bus_items<false, 256>), grid, block, 0, s, a.g, a.w, a.single);
+    launch_bus_items(a, small, grid, block, s);
   }
   hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(64), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
 }
@@ -1504,7 +1522,7 @@ std::string graph_key(const SweepLaunch& a, int n, int dev) {
                         g.bij, g.gji, g.bji, g.gjj, g.bjj, g.smax_ij, g.smax_ji, g.gen_bus, g.pmin, g.pmax,
                         g.qmin, g.qmax, g.cost2, g.cost1, a.w.bus_end_ptr /* workspace base */};
   put(ptrs, sizeof ptrs);
-  const int shape[8] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps, a.solver};
+  const int shape[9] = {a.nbl, a.nbb, a.bs, a.single, a.ns, a.trace, a.max_sweeps, a.solver, a.norm_inf};
   put(shape, sizeof shape);
   put(&a.eps_pri, sizeof a.eps_pri);
   put(&a.eps_dual, sizeof a.eps_dual);
@@ -1686,6 +1704,7 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     a.trace = p->trace;
     a.max_sweeps = p->max_sweeps;
     a.solver = solver;
+    a.norm_inf = p->norm_inf;
     a.eps_pri = p->eps_pri;
     a.eps_dual = p->eps_dual;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
