@@ -41,7 +41,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("966838533346e52d", 119356610)}
+MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("f3c86475e9eb5581", 112040119)}
 
 
 def sweep_sources_sha() -> str:

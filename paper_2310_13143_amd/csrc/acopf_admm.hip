@@ -104,6 +104,26 @@ __device__ double block_max(double v, double* lds) {
   return m;
 }
 
+// Workgroups of a launch are dispatched to the chip's 8 XCDs in turn
+// (workgroup b to XCD b mod 8), and each XCD has its own L2.  Logical block
+// of workgroup b when n blocks are used and the launch has at least
+// 8 * ceil(n / 8) workgroups: XCD x runs the contiguous logical blocks
+// [x * per, (x + 1) * per), so that neighbouring blocks share an L2: item
+// blocks next to each other in bus order share the records of the lines
+// between them, and line blocks the values of nearby buses.  -1 past the n
+// used blocks.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int per = (n + kXcds - 1) / kXcds;
+  const int k = b / kXcds;
+  if (k >= per) return -1;
+  const int r = (b % kXcds) * per + k;
+  return r < n ? r : -1;
+}
+
+inline unsigned xcd_grid(long long n) { return (unsigned)((n + kXcds - 1) / kXcds * kXcds); }
+
 // Scenario owning block b of a phase whose per-scenario first blocks are
 // blk_off[0..ns]; -1 past the last block.
 __device__ __forceinline__ int scen_of_block(const int32_t* blk_off, int ns, int b) {
@@ -408,8 +428,9 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
   return __hip_atomic_load(&w.sync->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// `single`: one scenario, launched with exactly ceil(n / block) blocks, so a
-// block needs no table lookup (one flag read before the line work).  At
+// `single`: one scenario, ceil(n / block) blocks used (the launch rounded up
+// to the XCD order's multiple of 8), so a block needs no table lookup (one
+// flag read before the line work).  Blocks b are logical (xcd_block).  At
 // most 256 registers per lane: two waves per SIMD (measured faster than one
 // wave with more registers; a cap of three waves spills hundreds of bytes).
 // Start of a line-phase block: its scenario s and, with `test`, the stop
@@ -417,13 +438,16 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 // infinity norms, an argument so that no flag load precedes the test).
 // False when the block has nothing to do (scenario done or stopped now).
 __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single, int test, double eps_pri,
-                                                 double eps_dual, int& s, int* s_stop) {
+                                                 double eps_dual, int& s, int& b, int* s_stop) {
   s = 0;
   if (single) {
     if (w.scen[0].done) return false;
+    b = xcd_block(blockIdx.x, (w.n_line + (int)blockDim.x - 1) / (int)blockDim.x);
+    if (b < 0) return false;
   } else {
     if (batch_done(w)) return false;
-    s = scen_of_block(w.line_blk_off, w.n_scen, blockIdx.x);
+    b = xcd_block(blockIdx.x, w.line_blk_off[w.n_scen]);
+    s = b < 0 ? -1 : scen_of_block(w.line_blk_off, w.n_scen, b);
     if (s < 0 || w.scen[s].done) return false;
   }
   if (test) {
@@ -433,7 +457,7 @@ __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single,
     if (threadIdx.x == 0) {
       const bool stop = stop_met(r2, s2, eps_pri, eps_dual);
       // the scenario's first block records the stop; every block obeys it
-      if (stop && (int)blockIdx.x == (single ? 0 : w.line_blk_off[s])) record_sweep(w, s, r2, s2, true, eps_pri, eps_dual);
+      if (stop && b == (single ? 0 : w.line_blk_off[s])) record_sweep(w, s, r2, s2, true, eps_pri, eps_dual);
       *s_stop = stop ? 1 : 0;
     }
     __syncthreads();
@@ -443,9 +467,9 @@ __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single,
 }
 
 // Line of this thread in scenario s, -1 past the scenario's lines.
-__device__ __forceinline__ int line_of_thread(const Workspace& w, int single, int s) {
-  const int l = single ? (int)(blockIdx.x * blockDim.x + threadIdx.x)
-                       : w.scen_line_off[s] + (int)((blockIdx.x - w.line_blk_off[s]) * blockDim.x + threadIdx.x);
+__device__ __forceinline__ int line_of_thread(const Workspace& w, int single, int s, int b) {
+  const int l = single ? (int)(b * blockDim.x + threadIdx.x)
+                       : w.scen_line_off[s] + (int)((b - w.line_blk_off[s]) * blockDim.x + threadIdx.x);
   return l < (single ? w.n_line : w.scen_line_off[s + 1]) ? l : -1;
 }
 
@@ -454,9 +478,9 @@ __device__ __forceinline__ int line_of_thread(const Workspace& w, int single, in
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
-  int s;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
-  const int l = line_of_thread(w, single, s);
+  int s, b;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   // one full solve per thread (the exact solver's own warm start and guess)
   if (!search) {
@@ -504,9 +528,9 @@ k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double
 __global__ void __launch_bounds__(256)
 k_line_phase_local(Workspace w, int single, int test, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
-  int s;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
-  const int l = line_of_thread(w, single, s);
+  int s, b;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   if (update_line_local(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
@@ -516,9 +540,9 @@ k_line_phase_local(Workspace w, int single, int test, double eps_pri, double eps
 __global__ void __launch_bounds__(256)
 k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
-  int s;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, &s_stop)) return;
-  const int l = line_of_thread(w, single, s);
+  int s, b;
+  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   if (update_line_linfeas(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
 }
@@ -529,8 +553,9 @@ k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double e
 // LDS; the bus's first thread adds them (fixed order) and solves the bus's
 // closed form; then every thread updates its couplings.  A bus of degree d
 // costs one round of independent loads on d threads instead of a
-// dependent walk over its CSR on one.  Blocks past a scenario's last item
-// block exit at once.  The scenario's first block counts the sweep.  kInf:
+// dependent walk over its CSR on one.  Workgroups take item blocks in XCD
+// order (xcd_block); blocks past a scenario's last item block exit at once.
+// The scenario's first block counts the sweep.  kInf:
 // the residual partials are maxima of squares (infinity norms), a template
 // parameter so that the Euclidean kernel carries no selects.
 template <bool kTrace, int kBlock, bool kInf>
@@ -538,16 +563,19 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   __shared__ double terms[8][kBlock];
   __shared__ double bres[6][kBlock];
   __shared__ double lds[16];
-  int s = 0;
+  int s = 0, b;
   if (single) {
-    if (w.scen[0].done || (int)blockIdx.x >= w.item_blk_off[1]) return;
+    if (w.scen[0].done) return;
+    b = xcd_block(blockIdx.x, w.item_blk_off[1]);
+    if (b < 0) return;
   } else {
     if (batch_done(w)) return;
-    s = scen_of_block(w.item_blk_off, w.n_scen, blockIdx.x);
+    b = xcd_block(blockIdx.x, w.item_blk_off[w.n_scen]);
+    s = b < 0 ? -1 : scen_of_block(w.item_blk_off, w.n_scen, b);
     if (s < 0 || w.scen[s].done) return;
   }
   const int t = threadIdx.x;
-  const size_t slot = (size_t)blockIdx.x * kBlock + t;
+  const size_t slot = (size_t)b * kBlock + t;
   const int code = w.item_code[slot], bus = w.item_bus[slot], head = w.item_head[slot], len = w.item_len[slot];
   constexpr bool inf = kInf;
   const bool whole = code == kItemBus;  // a bus wider than a block: its thread walks all its items
@@ -585,9 +613,9 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
   }
   block_sum2_to_first(rr, ss, lds, inf);
   if (t == 0) {
-    w.partials[blockIdx.x] = rr;
-    w.partials[w.max_partials + blockIdx.x] = ss;
-    if ((int)blockIdx.x == w.item_blk_off[s]) {
+    w.partials[b] = rr;
+    w.partials[w.max_partials + b] = ss;
+    if (b == w.item_blk_off[s]) {
       ScenState* sc = &w.scen[s];
       const int k = sc->sweeps + 1;
       sc->sweeps = k;
@@ -1474,17 +1502,17 @@ void launch_bus_items(const SweepLaunch& a, bool small, dim3 grid, dim3 block, h
 // chunk ends with k_finish_phase.
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
   const bool small = item_block_for(a.g.n_line) == 64;
-  const dim3 grid((unsigned)a.nbb), block(small ? 64 : 256);
+  const dim3 grid(xcd_grid(a.nbb)), block(small ? 64 : 256);
   const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? (a.norm_inf ? 2 : 1) : 0;
   for (int k = 0; k < n; ++k) {
     if (a.solver == 1)
-      hipLaunchKernelGGL(k_line_phase_local, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
+      hipLaunchKernelGGL(k_line_phase_local, dim3(xcd_grid(a.nbl)), dim3(a.bs), 0, s, a.w, a.single,
                          (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
     else if (a.solver == 2)
-      hipLaunchKernelGGL(k_line_phase_linfeas, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.w, a.single,
+      hipLaunchKernelGGL(k_line_phase_linfeas, dim3(xcd_grid(a.nbl)), dim3(a.bs), 0, s, a.w, a.single,
                          (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
     else
-      hipLaunchKernelGGL(k_line_phase, dim3((unsigned)a.nbl), dim3(a.bs), 0, s, a.g, a.w, a.single,
+      hipLaunchKernelGGL(k_line_phase, dim3(xcd_grid(a.nbl)), dim3(a.bs), 0, s, a.g, a.w, a.single,
                          (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
     launch_bus_items(a, small, grid, block, s);
   }
