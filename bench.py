@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # reports null.
 SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_amd/csrc/components.h",
                  "paper_2310_13143_amd/csrc/line_qp.h", "paper_2310_13143_amd/csrc/line_alm.h",
-                 "paper_2310_13143_amd/csrc/linfeas.h",
+                 "paper_2310_13143_amd/csrc/linfeas.h", "paper_2310_13143_amd/csrc/launch_order.h",
                  "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")

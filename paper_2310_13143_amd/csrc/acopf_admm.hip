@@ -24,8 +24,9 @@
 #include <vector>
 
 #include "components.h"
-#include "linfeas.h"
 #include "errors.h"
+#include "launch_order.h"
+#include "linfeas.h"
 
 using namespace acopf;
 
@@ -37,6 +38,9 @@ std::string& acopf::last_error() {
 namespace {
 
 constexpr int kDefaultBlock = 256;
+// Most blocks of a sweep launch: its work items (blocks x up to 256
+// threads, rounded up for the XCD order) must count below 2^32.
+constexpr long long kMaxSweepBlocks = 1LL << 22;
 constexpr long long kSpinLimit = 1LL << 25;
 // Most lines per wave that the line phase's neighbour search serves.
 constexpr int kSearchLines = 2;
@@ -104,25 +108,14 @@ __device__ double block_max(double v, double* lds) {
   return m;
 }
 
-// Workgroups of a launch are dispatched to the chip's 8 XCDs in turn
-// (workgroup b to XCD b mod 8), and each XCD has its own L2.  Logical block
-// of workgroup b when n blocks are used and the launch has at least
-// 8 * ceil(n / 8) workgroups: XCD x runs the contiguous logical blocks
-// [x * per, (x + 1) * per), so that neighbouring blocks share an L2: item
-// blocks next to each other in bus order share the records of the lines
-// between them, and line blocks the values of nearby buses.  -1 past the n
-// used blocks.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int xcd_block(int b, int n) {
-  const int per = (n + kXcds - 1) / kXcds;
-  const int k = b / kXcds;
-  if (k >= per) return -1;
-  const int r = (b % kXcds) * per + k;
-  return r < n ? r : -1;
+// Orders a wave's LDS stores before the loads of its other lanes (the
+// fences of a workgroup barrier without the barrier: the exchange stays
+// within one wave).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
-
-inline unsigned xcd_grid(long long n) { return (unsigned)((n + kXcds - 1) / kXcds * kXcds); }
 
 // Scenario owning block b of a phase whose per-scenario first blocks are
 // blk_off[0..ns]; -1 past the last block.
@@ -293,7 +286,8 @@ __global__ void k_clear_flags(Workspace w, int mode) {
 }
 
 // Start of a solve: per-scenario stop state, barrier flags, block tables of
-// both phases for block size bs.
+// both phases for block size bs.  items: the bus phase runs by workgroups
+// of that many item blocks (0: by buses).
 __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items, int norm_inf) {
   for (int b = gtid(); b < w.max_partials; b += gstride()) w.arrive[b * kArriveStride] = 0u;
   for (int s = gtid(); s < w.n_scen; s += gstride()) {
@@ -330,7 +324,7 @@ __global__ void k_reset_solve(Workspace w, int blocks, int bs, int items, int no
     w.line_blk_off[w.n_scen] = lb;
     w.bus_blk_off[w.n_scen] = bb;
     if (items)  // the bus phase runs by item blocks: its partials follow them
-      for (int s = 0; s <= w.n_scen; ++s) w.bus_blk_off[s] = w.item_blk_off[s];
+      for (int s = 0; s <= w.n_scen; ++s) w.bus_blk_off[s] = w.item_blk_off[s] / items;
   }
 }
 
@@ -553,40 +547,44 @@ k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double e
 // LDS; the bus's first thread adds them (fixed order) and solves the bus's
 // closed form; then every thread updates its couplings.  A bus of degree d
 // costs one round of independent loads on d threads instead of a
-// dependent walk over its CSR on one.  Workgroups take item blocks in XCD
-// order (xcd_block); blocks past a scenario's last item block exit at once.
-// The scenario's first block counts the sweep.  kInf:
-// the residual partials are maxima of squares (infinity norms), a template
+// dependent walk over its CSR on one.  Each wave runs one item block on its
+// own (the item block is the wave: its lanes exchange terms through LDS
+// without a workgroup barrier); workgroup b runs item blocks
+// [kWaves b, kWaves (b + 1)), taken in XCD order (xcd_block), and writes
+// one partial.  Workgroups past a scenario's last item block exit at
+// once; the scenario's first workgroup counts the sweep.  kInf: the
+// residual partials are maxima of squares (infinity norms), a template
 // parameter so that the Euclidean kernel carries no selects.
-template <bool kTrace, int kBlock, bool kInf>
-__global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w, int single) {
-  __shared__ double terms[8][kBlock];
-  __shared__ double bres[6][kBlock];
+template <bool kTrace, bool kInf, int kWaves>
+__global__ void __launch_bounds__(kItemBlock * kWaves) k_bus_items(acopf_grid g, Workspace w, int single) {
+  constexpr int kThreads = kItemBlock * kWaves;
+  __shared__ double terms[8][kThreads];
+  __shared__ double bres[6][kThreads];
   __shared__ double lds[16];
   int s = 0, b;
   if (single) {
     if (w.scen[0].done) return;
-    b = xcd_block(blockIdx.x, w.item_blk_off[1]);
+    b = xcd_block(blockIdx.x, w.item_blk_off[1] / kWaves);
     if (b < 0) return;
   } else {
     if (batch_done(w)) return;
-    b = xcd_block(blockIdx.x, w.item_blk_off[w.n_scen]);
-    s = b < 0 ? -1 : scen_of_block(w.item_blk_off, w.n_scen, b);
+    b = xcd_block(blockIdx.x, w.item_blk_off[w.n_scen] / kWaves);
+    s = b < 0 ? -1 : scen_of_block(w.item_blk_off, w.n_scen, b * kWaves);
     if (s < 0 || w.scen[s].done) return;
   }
-  const int t = threadIdx.x;
-  const size_t slot = (size_t)b * kBlock + t;
+  const int t = threadIdx.x, seg = t & ~(kItemBlock - 1);  // seg: the wave's item block in LDS
+  const size_t slot = (size_t)b * kThreads + t;
   const int code = w.item_code[slot], bus = w.item_bus[slot], head = w.item_head[slot], len = w.item_len[slot];
   constexpr bool inf = kInf;
   const bool whole = code == kItemBus;  // a bus wider than a block: its thread walks all its items
-  const bool lead = bus >= 0 && t == head && !whole;
+  const bool lead = bus >= 0 && t - seg == head && !whole;
   double bc[7];
   if (lead) bus_item_consts(g, w, bus, bc);
   double v[14], a[8];
   bus_item_terms(w, code, v, a);
 #pragma unroll
   for (int m = 0; m < 8; ++m) terms[m][t] = a[m];
-  __syncthreads();
+  wave_lds_sync();
   if (lead) {
     double sum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < len; ++j)
@@ -601,21 +599,21 @@ __global__ void __launch_bounds__(kBlock) k_bus_items(acopf_grid g, Workspace w,
 #pragma unroll
     for (int m = 0; m < 6; ++m) bres[m][t] = out[m];
   }
-  __syncthreads();
+  wave_lds_sync();
   double rr = 0.0, ss = 0.0;
   if (whole) {
     bus_whole_update<kTrace>(g, w, bus, rr, ss, inf);
   } else if (bus >= 0) {
     double res[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) res[m] = bres[m][head];
+    for (int m = 0; m < 6; ++m) res[m] = bres[m][seg + head];
     bus_item_update<kTrace>(w, code, v, res, rr, ss, inf);
   }
   block_sum2_to_first(rr, ss, lds, inf);
   if (t == 0) {
     w.partials[b] = rr;
     w.partials[w.max_partials + b] = ss;
-    if (b == w.item_blk_off[s]) {
+    if (b * kWaves == w.item_blk_off[s]) {
       ScenState* sc = &w.scen[s];
       const int k = sc->sweeps + 1;
       sc->sweeps = k;
@@ -1343,13 +1341,14 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
   // generators then its line ends (CSR order) in consecutive slots of one
   // block; a bus that does not fit the current block starts the next one,
   // and a bus with more items than a block takes one whole-bus slot
-  const int32_t ib = item_block_for(nl);
+  const int32_t ib = kItemBlock, waves = item_waves_for(nl);
   const int32_t nib = item_blocks_bound(nl, ng, ns);
   std::vector<int32_t> icode((size_t)nib * ib, kItemPad), ibus((size_t)nib * ib, -1), ihead((size_t)nib * ib),
       ilen((size_t)nib * ib, 0), iblk(ns + 1);
   for (size_t q = 0; q < ihead.size(); ++q) ihead[q] = (int32_t)(q % ib);
   int32_t blk = 0;
   for (int k = 0; k < ns; ++k) {
+    blk = (blk + waves - 1) / waves * waves;  // a workgroup serves one scenario
     iblk[k] = blk;
     int fill = 0;
     bool open = false;
@@ -1379,6 +1378,7 @@ acopf_status setup_impl(const acopf_grid* g, const int32_t* bus_off_h, const int
     }
     if (open) ++blk;
   }
+  blk = (blk + waves - 1) / waves * waves;
   iblk[ns] = blk;
   if (blk > nib) return fail(ACOPF_ERR_UNSUPPORTED, "acopf_setup: item blocks exceed their bound");
   Workspace w = ws_of(g, workspace);
@@ -1483,26 +1483,27 @@ struct SweepLaunch {
   double eps_pri, eps_dual;
 };
 
-template <bool kTrace, int kBlock>
-void launch_bus_items_norm(const SweepLaunch& a, dim3 grid, dim3 block, hipStream_t s) {
+template <bool kTrace, int kWaves>
+void launch_bus_items_norm(const SweepLaunch& a, hipStream_t s) {
+  const dim3 grid(xcd_grid(a.nbb)), block(kItemBlock * kWaves);
   if (a.norm_inf)
-    hipLaunchKernelGGL((k_bus_items<kTrace, kBlock, true>), grid, block, 0, s, a.g, a.w, a.single);
+    hipLaunchKernelGGL((k_bus_items<kTrace, true, kWaves>), grid, block, 0, s, a.g, a.w, a.single);
   else
-    hipLaunchKernelGGL((k_bus_items<kTrace, kBlock, false>), grid, block, 0, s, a.g, a.w, a.single);
+    hipLaunchKernelGGL((k_bus_items<kTrace, false, kWaves>), grid, block, 0, s, a.g, a.w, a.single);
 }
 
-void launch_bus_items(const SweepLaunch& a, bool small, dim3 grid, dim3 block, hipStream_t s) {
-  if (a.trace && small) launch_bus_items_norm<true, 64>(a, grid, block, s);
-  else if (a.trace) launch_bus_items_norm<true, 256>(a, grid, block, s);
-  else if (small) launch_bus_items_norm<false, 64>(a, grid, block, s);
-  else launch_bus_items_norm<false, 256>(a, grid, block, s);
+void launch_bus_items(const SweepLaunch& a, hipStream_t s) {
+  const bool one = item_waves_for(a.g.n_line) == 1;
+  if (a.trace && one) launch_bus_items_norm<true, 1>(a, s);
+  else if (a.trace) launch_bus_items_norm<true, 4>(a, s);
+  else if (one) launch_bus_items_norm<false, 1>(a, s);
+  else launch_bus_items_norm<false, 4>(a, s);
 }
 
 // n sweeps: each line phase but the first tests the sweep before it; the
 // chunk ends with k_finish_phase.
 void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
-  const bool small = item_block_for(a.g.n_line) == 64;
-  const dim3 grid(xcd_grid(a.nbb)), block(small ? 64 : 256);
+  const int search = a.g.n_line < kSearchMaxLines ? 1 : 0;
   const int stop_test = (a.eps_pri > 0.0 || a.eps_dual > 0.0) ? (a.norm_inf ? 2 : 1) : 0;
   for (int k = 0; k < n; ++k) {
     if (a.solver == 1)
@@ -1513,8 +1514,8 @@ void enqueue_sweeps(const SweepLaunch& a, int n, hipStream_t s) {
                          (k > 0) ? stop_test : 0, a.eps_pri, a.eps_dual);
     else
       hipLaunchKernelGGL(k_line_phase, dim3(xcd_grid(a.nbl)), dim3(a.bs), 0, s, a.g, a.w, a.single,
-                         (k > 0) ? stop_test : 0, small ? 1 : 0, a.eps_pri, a.eps_dual);
-    launch_bus_items(a, small, grid, block, s);
+                         (k > 0) ? stop_test : 0, search, a.eps_pri, a.eps_dual);
+    launch_bus_items(a, s);
   }
   hipLaunchKernelGGL(k_finish_phase, dim3(a.ns), dim3(64), 0, s, a.w, a.max_sweeps, a.eps_pri, a.eps_dual);
 }
@@ -1717,9 +1718,10 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     // per-scenario block counts (excess blocks exit)
     const int single = ns == 1 ? 1 : 0;
     const long long nbl = (g->n_line + bs - 1) / bs + (single ? 0 : ns);
-    // bus phase by item blocks (bound from the sizes; excess blocks exit)
-    const long long nbb = item_blocks_bound(g->n_line, g->n_gen, ns);
-    if (nbb > w.max_partials || nbl > 65535 || nbb > 65535)
+    // bus phase by workgroups of item_waves_for item blocks (bound from
+    // the sizes; excess workgroups exit)
+    const long long nbb = item_blocks_bound(g->n_line, g->n_gen, ns) / item_waves_for(g->n_line);
+    if (nbb > w.max_partials || nbl > kMaxSweepBlocks || nbb > kMaxSweepBlocks)
       return fail(ACOPF_ERR_UNSUPPORTED, "acopf_admm_solve: grid too large for the block size");
     SweepLaunch a;
     a.g = *g;
@@ -1741,7 +1743,8 @@ acopf_status acopf_admm_solve(const acopf_grid* g, const acopf_admm_params* p, v
     // a stream under capture records plain launches, and every chunk up to
     // the cap (the stop test then acts on the device only)
     const bool use_graph = p->sweep_mode == ACOPF_SWEEP_GRAPH && !capturing;
-    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs, 1, p->norm_inf);
+    hipLaunchKernelGGL(k_reset_solve, dim3(reset_blocks), dim3(256), 0, s, w, (int)nbb, bs,
+                       item_waves_for(g->n_line), p->norm_inf);
     for (int k0 = 0; k0 < p->max_sweeps; k0 += kSweepChunk) {
       const int k1 = std::min(p->max_sweeps, k0 + kSweepChunk);
       hipGraphExec_t ge = nullptr;

@@ -118,7 +118,7 @@ struct Workspace {
   int32_t* line_blk_off;   // [n_scen + 1] first block of each scenario in the line phase
   int32_t* bus_blk_off;    // [n_scen + 1] same for the bus phase
   // bus phase by coupling items (launch modes): the generators, then the
-  // line ends of each bus in consecutive slots of one block (item_block_for)
+  // line ends of each bus in consecutive slots of one block (kItemBlock slots)
   int32_t* item_code;      // [slots] 2 l + side for a line end, -(k + 1) for generator k, kItemBus, kItemPad
   int32_t* item_bus;       // [slots] bus of the item (-1 for padding)
   int32_t* item_head;      // [slots] slot (within the block) of the bus's first item
@@ -164,17 +164,28 @@ inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // slots than one block together; this bounds the block count by the sizes
 // alone (blocks past a scenario's last one exit at once).  A bus with more
 // items than a block takes one slot (kItemBus) whose thread runs the whole
-// per-bus update.  Small grids use 64-slot blocks (one wave: more blocks in
-// flight for a latency-bound sweep), larger ones 256-slot blocks.
+// per-bus update.  Blocks have 64 slots, one wave each: a wave solves its
+// buses with no workgroup barrier (with blocks in XCD order, faster than
+// 128- and 256-slot blocks).  A bus-phase workgroup runs item_waves_for
+// item blocks, one per wave, and adds their residual terms into one partial:
+// on large grids four (the stop test then reads a quarter as many
+// partials), on small, latency-bound ones one (the most workgroups, spread
+// over the most CUs).  A scenario's item blocks start at a multiple of that
+// count, so that a workgroup serves one scenario.
 constexpr int32_t kItemPad = -0x7fffffff;
 constexpr int32_t kItemBus = -0x7ffffffe;
-constexpr int32_t kItemSmallLines = 16384;
+constexpr int32_t kItemBlock = 64;
+// Grids below this many lines run the line phase's wave search and
+// one-wave bus-phase workgroups.
+constexpr int32_t kSearchMaxLines = 16384;
 
-inline int32_t item_block_for(int32_t nl) { return nl < kItemSmallLines ? 64 : 256; }
+inline int32_t item_waves_for(int32_t nl) { return nl < kSearchMaxLines ? 1 : 4; }
 
+// Item blocks (a multiple of item_waves_for) for the sizes.
 inline int32_t item_blocks_bound(int32_t nl, int32_t ng, int32_t ns) {
-  const int64_t items = 2 * (int64_t)nl + ng, b = item_block_for(nl);
-  return (int32_t)(2 * ((items + b - 1) / b) + 2 * (int64_t)ns + 1);
+  const int64_t items = 2 * (int64_t)nl + ng, b = kItemBlock, wv = item_waves_for(nl);
+  const int64_t n = 2 * ((items + b - 1) / b) + 2 * (int64_t)ns + 1 + (wv - 1) * ((int64_t)ns + 1);
+  return (int32_t)((n + wv - 1) / wv * wv);
 }
 
 inline int32_t max_partials_for(int32_t nb, int32_t nl, int32_t ng, int32_t ns) {
@@ -211,7 +222,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.scen_gen_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.line_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
   t.bus_blk_off = (int32_t*)take((size_t)(ns + 1) * I);
-  const size_t slots = (size_t)item_blocks_bound(nl, ng, ns) * item_block_for(nl);
+  const size_t slots = (size_t)item_blocks_bound(nl, ng, ns) * kItemBlock;
   t.item_code = (int32_t*)take(slots * I);
   t.item_bus = (int32_t*)take(slots * I);
   t.item_head = (int32_t*)take(slots * I);

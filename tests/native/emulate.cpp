@@ -7,11 +7,20 @@
 #include <vector>
 
 #include "../../paper_2310_13143_amd/csrc/components.h"
+#include "../../paper_2310_13143_amd/csrc/launch_order.h"
 #include "../../paper_2310_13143_amd/csrc/linfeas.h"
 
 using namespace acopf;
 
 extern "C" {
+
+// Logical block of each of the xcd_grid(bound) workgroups of a launch that
+// uses n blocks (out: xcd_grid(bound) entries); returns the workgroup count.
+int emu_xcd_blocks(int n, int bound, int* out) {
+  const int g = (int)xcd_grid(bound);
+  for (int b = 0; b < g; ++b) out[b] = xcd_block(b, n);
+  return g;
+}
 
 // warm: per-instance starting working sets (NULL = none); mask_out
 // (optional): the returned working sets.

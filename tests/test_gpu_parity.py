@@ -165,8 +165,8 @@ def test_rgg2000_500_sweeps_match_the_stored_oracle_run():
 
 def test_batch_with_large_scenarios_matches_solo_runs_and_oracle():
     """A batch of the 300-bus grid and two 10,000-bus scenarios (27,400
-    lines: the bus phase runs 256-slot item blocks in batch mode, while each
-    10,000-bus grid alone runs 64-slot blocks) in the bench's graph mode:
+    lines, whose bus phase runs item blocks of several scenarios in one
+    launch) in the bench's graph mode:
     the large scenarios reproduce their solo runs bit for bit and the
     300-bus scenario matches the oracle.  A grid below 16,384 lines alone
     runs the line phase's wave search, the batch runs one full solve per

@@ -539,3 +539,27 @@ def test_restoration_qp_sweeps_and_merit_match_oracle(emu):
     emu.emu_merit(ctypes.byref(hg.c), ctypes.byref(cx), ctypes.byref(cd), ctypes.c_void_p(base), ptr(mer))
     assert mer[3] == pytest.approx(acopf.infeas_h(g, x), rel=1e-10)
     assert mer[4] == pytest.approx(acopf.infeas_h(g, x.plus(dref)), rel=1e-7)
+
+
+@pytest.mark.parametrize("n,bound", [(1, 1), (7, 7), (8, 8), (9, 9), (730, 1457), (688, 688), (1375, 1375),
+                                     (5, 40), (61, 64), (64, 61 + 8)])
+def test_xcd_block_order_covers_every_block_once(emu, n, bound):
+    """The sweep launches' workgroup -> block map: every used block is taken
+    by exactly one workgroup of the rounded-up launch, each XCD (workgroups
+    b, b + 8, ...) runs one contiguous run of blocks, and the runs follow
+    XCD order."""
+    out = np.full(bound + 8, -2, dtype=np.int32)
+    g = emu.emu_xcd_blocks(n, bound, ptr(out))
+    assert g % 8 == 0 and bound <= g < bound + 8
+    got = out[:g]
+    used = got[got >= 0]
+    assert np.array_equal(np.sort(used), np.arange(n))
+    assert (got[got < 0] == -1).all()
+    starts = []
+    for x in range(8):
+        run = got[x::8]
+        run = run[run >= 0]
+        if run.size:
+            assert np.array_equal(run, np.arange(run[0], run[0] + run.size))
+            starts.append(run[0])
+    assert starts == sorted(starts)
