@@ -211,6 +211,54 @@ def test_batch_with_large_scenarios_matches_solo_runs_and_oracle():
     assert rel_err_cols(part["xg"].T, ref.state.xg) <= TOL and rel_err_cols(part["lam_g"].T, ref.state.lam_g) <= TOL
 
 
+def test_infinity_norms_on_a_large_batch():
+    """The infinity-norm residuals of the batch kernels used above 16,384
+    lines (four item blocks per bus-phase workgroup): the norm leaves the
+    iterates unchanged (bit for bit against the Euclidean run), each
+    scenario's reported primal norm is the largest coupling residual
+    |x_c - xbar_c| recomputed from the exported state (a maximum does not
+    depend on the reduction order), and both norms sit between the
+    Euclidean ones divided by sqrt(couplings) and the Euclidean ones."""
+    from paper_2310_13143_amd import _abi
+    from synth.grids import grid_300, grid_10000, perturb_loads
+    print("[gpu] infinity norms, batch 300 + 2 x 10000", flush=True)
+    grids = [perturb_loads(grid_300(), 64000), perturb_loads(grid_10000(), 64002), perturb_loads(grid_10000(), 64005)]
+    pts = [start_point(g, pi_scale=20.0, seed=k) for k, g in enumerate(grids)]
+    dg = _dev()(grids)
+    assert dg.n_line > 16384
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), np.concatenate([p[1] for p in pts]))
+    dg.qp_build(xb, 0.05)
+    nsw = 40
+    runs = []
+    for inf in (False, True):
+        dg.admm_init(*dg.rho_scalar(2e4))
+        dg.admm_solve(nsw, 0.0, 0.0, sweep_mode=_abi.SWEEP_GRAPH, block_size=64, norm_inf=inf)
+        runs.append((dg.admm_results(), {k: v.cpu().numpy() for k, v in dg.admm_state().items()}))
+    (res2, st2), (resi, sti) = runs
+    for name in ("xl", "lam_l", "xbar_f", "xg", "xbar_g", "lam_g", "dw", "dth", "nu"):
+        assert np.array_equal(st2[name], sti[name]), name
+    G, L, B = dg.n_gen, dg.n_line, dg.n_bus
+    bo, lo, go = dg.offsets["bus"], dg.offsets["line"], dg.offsets["gen"]
+    for k, g in enumerate(grids):
+        xl = sti["xl"].reshape(8, L)[:, lo[k]:lo[k + 1]]
+        xbf = sti["xbar_f"].reshape(4, L)[:, lo[k]:lo[k + 1]]
+        dw, dth = sti["dw"][bo[k]:bo[k + 1]], sti["dth"][bo[k]:bo[k + 1]]
+        f, t = np.asarray(g.f), np.asarray(g.t)
+        r = np.concatenate([
+            (sti["xg"].reshape(2, G) - sti["xbar_g"].reshape(2, G))[:, go[k]:go[k + 1]].ravel(),
+            (xl[:4] - xbf).ravel(),
+            xl[4] - dw[f], xl[5] - dth[f], xl[6] - dw[t], xl[7] - dth[t]])
+        n_c = r.size
+        assert n_c == 2 * g.n_gen + 8 * g.n_line
+        r_max = np.abs(r).max()
+        assert resi[k]["sweeps"] == nsw and res2[k]["sweeps"] == nsw
+        assert abs(resi[k]["r"] - r_max) <= 1e-14 * r_max, (k, resi[k]["r"], r_max)
+        for q in ("r", "s"):
+            e, i = res2[k][q], resi[k][q]
+            assert 0.0 < i <= e * (1 + 1e-12) and e <= np.sqrt(n_c) * i * (1 + 1e-12), (k, q, e, i)
+
+
 @pytest.mark.parametrize("rho,mu", [(2e4, 10.0), (2e2, 2.0)])
 def test_residual_balancing_matches_oracle(rho, mu):
     """Residual balancing of the penalties every 64 sweeps (graph sweeps)
