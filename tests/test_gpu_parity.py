@@ -259,6 +259,55 @@ def test_infinity_norms_on_a_large_batch():
             assert 0.0 < i <= e * (1 + 1e-12) and e <= np.sqrt(n_c) * i * (1 + 1e-12), (k, q, e, i)
 
 
+def test_traced_sweeps_on_a_large_batch():
+    """Traced sweeps (the per-coupling sums of |r_c| and |s_c| that the
+    learned warm start trains on) in the bus kernel used above 16,384 lines:
+    the 300-bus scenario of the batch against the oracle's sums, the two
+    10,000-bus scenarios against their solo runs (one-block bus-phase
+    workgroups, the line phase's wave search: the same minimisers to
+    rounding, hence 1e-9 per column)."""
+    from paper_2310_13143_amd import _abi
+    from oracle import mlp
+    from synth.grids import grid_300, grid_10000, perturb_loads
+    print("[gpu] traced sweeps, batch 300 + 2 x 10000", flush=True)
+    grids = [perturb_loads(grid_300(), 64000), perturb_loads(grid_10000(), 64002), perturb_loads(grid_10000(), 64005)]
+    pts = [start_point(g, pi_scale=20.0, seed=k) for k, g in enumerate(grids)]
+    DeviceGrid = _dev()
+    nsw = 30
+    dg = DeviceGrid(grids)
+    assert dg.n_line > 16384
+    cat = lambda name: np.concatenate([getattr(p[0], name) for p in pts])
+    xb = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), np.concatenate([p[1] for p in pts]))
+    dg.qp_build(xb, 0.05)
+    dg.admm_init(*dg.rho_scalar(2e4))
+    dg.admm_solve(nsw, 0.0, 0.0, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=64, trace=True)
+    st = {k: v.cpu().numpy() for k, v in dg.admm_state().items()}
+    G, L = dg.n_gen, dg.n_line
+    lo, go = dg.offsets["line"], dg.offsets["gen"]
+
+    def sums(state, k, G, L, lo, go):
+        return [state["sum_r_g"].reshape(2, G)[:, go[k]:go[k + 1]].T, state["sum_s_g"].reshape(2, G)[:, go[k]:go[k + 1]].T,
+                state["sum_r_l"].reshape(8, L)[:, lo[k]:lo[k + 1]].T, state["sum_s_l"].reshape(8, L)[:, lo[k]:lo[k + 1]].T]
+
+    g, (x, pik) = grids[0], pts[0]
+    rho = admm.Rho.scalar(g, 2e4)
+    start = admm.warm_state(g, np.zeros((g.n_gen, 2)), np.zeros((g.n_line, 8)))
+    ref = admm.solve(g, qpm.build_qp(g, x, pik, 0.05), rho, nsw, 0.0, 0.0, state=start, record_states=True)
+    for a, b in zip(sums(st, 0, G, L, lo, go), mlp.trace_sums(g, rho, start, ref.history)):
+        assert rel_err_cols(a, b) <= 1e-8
+    for k in (1, 2):
+        x, pik = pts[k]
+        solo = DeviceGrid(grids[k])
+        xs = solo.iterate(x.pg, x.qg, x.w, x.th, x.wR, x.wI, pik)
+        solo.qp_build(xs, 0.05)
+        solo.admm_init(*solo.rho_scalar(2e4))
+        solo.admm_solve(nsw, 0.0, 0.0, sweep_mode=_abi.SWEEP_LAUNCHES, block_size=64, trace=True)
+        ss = {k2: v.cpu().numpy() for k2, v in solo.admm_state().items()}
+        Gs, Ls = solo.n_gen, solo.n_line
+        for a, b in zip(sums(st, k, G, L, lo, go), sums(ss, 0, Gs, Ls, [0, Ls], [0, Gs])):
+            assert rel_err_cols(a, b) <= 1e-9, k
+
+
 @pytest.mark.parametrize("rho,mu", [(2e4, 10.0), (2e2, 2.0)])
 def test_residual_balancing_matches_oracle(rho, mu):
     """Residual balancing of the penalties every 64 sweeps (graph sweeps)
