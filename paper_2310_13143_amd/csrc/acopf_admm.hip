@@ -424,23 +424,31 @@ __device__ __forceinline__ bool batch_done(const Workspace& w) {
 
 // `single`: one scenario, ceil(n / block) blocks used (the launch rounded up
 // to the XCD order's multiple of 8), so a block needs no table lookup (one
-// flag read before the line work).  Blocks b are logical (xcd_block).  At
+// flag read before the line work).  Blocks b are logical: in XCD order
+// (xcd_block) with kXcdOrder, else in workgroup order.  At
 // most 256 registers per lane: two waves per SIMD (measured faster than one
 // wave with more registers; a cap of three waves spills hundreds of bytes).
 // Start of a line-phase block: its scenario s and, with `test`, the stop
 // test of the previous sweep (launch modes; 1 on Euclidean norms, 2 on
 // infinity norms, an argument so that no flag load precedes the test).
 // False when the block has nothing to do (scenario done or stopped now).
+template <bool kXcdOrder>
+__device__ __forceinline__ int line_block(int n) {
+  if (kXcdOrder) return xcd_block(blockIdx.x, n);
+  return (int)blockIdx.x < n ? (int)blockIdx.x : -1;
+}
+
+template <bool kXcdOrder>
 __device__ __forceinline__ bool line_phase_begin(const Workspace& w, int single, int test, double eps_pri,
                                                  double eps_dual, int& s, int& b, int* s_stop) {
   s = 0;
   if (single) {
     if (w.scen[0].done) return false;
-    b = xcd_block(blockIdx.x, (w.n_line + (int)blockDim.x - 1) / (int)blockDim.x);
+    b = line_block<kXcdOrder>((w.n_line + (int)blockDim.x - 1) / (int)blockDim.x);
     if (b < 0) return false;
   } else {
     if (batch_done(w)) return false;
-    b = xcd_block(blockIdx.x, w.line_blk_off[w.n_scen]);
+    b = line_block<kXcdOrder>(w.line_blk_off[w.n_scen]);
     s = b < 0 ? -1 : scen_of_block(w.line_blk_off, w.n_scen, b);
     if (s < 0 || w.scen[s].done) return false;
   }
@@ -473,7 +481,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
   int s, b;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  if (!line_phase_begin<true>(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
   const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   // one full solve per thread (the exact solver's own warm start and guess)
@@ -518,12 +526,15 @@ k_line_phase(acopf_grid g, Workspace w, int single, int test, int search, double
 
 // Line phase with the local line solver (hessian mode RAW_LOCAL): one
 // ALM + TRON solve per thread.  A kernel of its own, so that the exact
-// solver's kernel keeps its register budget.
+// solver's kernel keeps its register budget.  Its blocks run in workgroup
+// order: the solve is compute-bound and its cost varies from line to line,
+// and contiguous runs of blocks per XCD measured slower (spatial clusters
+// of expensive lines land on one XCD).
 __global__ void __launch_bounds__(256)
 k_line_phase_local(Workspace w, int single, int test, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
   int s, b;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  if (!line_phase_begin<false>(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
   const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   if (update_line_local(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
@@ -535,7 +546,7 @@ __global__ void __launch_bounds__(256)
 k_line_phase_linfeas(Workspace w, int single, int test, double eps_pri, double eps_dual) {
   __shared__ int s_stop;
   int s, b;
-  if (!line_phase_begin(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
+  if (!line_phase_begin<true>(w, single, test, eps_pri, eps_dual, s, b, &s_stop)) return;
   const int l = line_of_thread(w, single, s, b);
   if (l < 0) return;
   if (update_line_linfeas(w, l) != 0) atomicAdd(&w.scen[s].infeasible[w.scen[s].sweeps & 1], 1);
