@@ -38,7 +38,7 @@ typedef enum {
 } acopf_status;
 
 typedef enum {
-  ACOPF_ADMM_CONVERGED = 0,       /* ||r||_2 <= eps_pri and ||s||_2 <= eps_dual */
+  ACOPF_ADMM_CONVERGED = 0,       /* ||r|| <= eps_pri and ||s|| <= eps_dual (norm_inf) */
   ACOPF_ADMM_MAX_SWEEPS = 1,      /* stopped at max_sweeps */
   ACOPF_ADMM_FAILED = 2           /* not solved: the scenario's QP build or factorisation failed (status) */
 } acopf_admm_outcome;
@@ -98,8 +98,9 @@ typedef struct {
 
 typedef struct {
   int32_t max_sweeps;   /* cap on ADMM iterations (Algorithm 2)                    */
-  double eps_pri;       /* stop when ||r||_2 <= eps_pri ...                       */
-  double eps_dual;      /* ... and ||s||_2 <= eps_dual (Section IV-B5); 0 = never */
+  double eps_pri;       /* stop when ||r|| <= eps_pri ...                         */
+  double eps_dual;      /* ... and ||s|| <= eps_dual (Section IV-B5; Euclidean
+                           norms unless norm_inf); 0 = never                      */
   int32_t sweep_mode;   /* acopf_sweep_mode                                       */
   int32_t block_size;   /* threads per block, multiple of 64, <= 256; 0 = 256     */
   int32_t max_blocks;   /* persistent grid size cap; 0 = as many as fit resident  */
