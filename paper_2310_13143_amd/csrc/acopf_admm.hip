@@ -816,30 +816,74 @@ __global__ void k_merit_parts(acopf_grid g, acopf_iterate x, Workspace w, acopf_
 // Fixed-order sums of scenario s's merit pieces (one block): a = (f at x,
 // f at x + d, generator model terms, h at x, h at x + d, m(d), line model
 // terms); smax = ||d||_inf over (pg, qg, w, th).
-__device__ void merit_sums(const Workspace& w, int s, double a[7], double& smax, double* lds) {
+// Chunk k of K of the components [c0, c1) of a scenario.
+__device__ __forceinline__ void red_chunk(int c0, int c1, int k, int K, int& a, int& b) {
+  const long long n = c1 - c0;
+  a = c0 + (int)(n * k / K);
+  b = c0 + (int)(n * (k + 1) / K);
+}
+
+__device__ __forceinline__ double* red_slot(const Workspace& w, int s, int k) {
+  return w.red + ((size_t)s * kRedBlocks + k) * 8;
+}
+
+// Block partials of the merit sums: block s K + k adds chunk k of scenario
+// s's line, generator and bus pieces (block sums in fixed order) and writes
+// them with the chunk's largest step component to Workspace::red.
+__global__ void k_merit_partial(Workspace w, int K) {
+  __shared__ double lds[16];
+  const int s = blockIdx.x / K, k = blockIdx.x % K;
   const int L = w.n_line, G = w.n_gen;
-  const int l0 = w.scen_line_off[s], l1 = w.scen_line_off[s + 1];
-  const int g0 = w.scen_gen_off[s], g1 = w.scen_gen_off[s + 1];
-  const int b0 = w.scen_bus_off[s], b1 = w.scen_bus_off[s + 1];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) a[k] = 0.0;
-  smax = 0.0;
+  int l0, l1, g0, g1, b0, b1;
+  red_chunk(w.scen_line_off[s], w.scen_line_off[s + 1], k, K, l0, l1);
+  red_chunk(w.scen_gen_off[s], w.scen_gen_off[s + 1], k, K, g0, g1);
+  red_chunk(w.scen_bus_off[s], w.scen_bus_off[s + 1], k, K, b0, b1);
+  double a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, smax = 0.0;
   for (int l = l0 + (int)threadIdx.x; l < l1; l += blockDim.x) {
     a[3] += w.line_comp[l];
     a[4] += w.line_comp[L + l];
     a[5] += w.line_comp[2 * L + l];
     a[6] += w.line_comp[3 * L + l];
   }
-  for (int k = g0 + (int)threadIdx.x; k < g1; k += blockDim.x) {
-    a[0] += w.gen_comp[k];
-    a[1] += w.gen_comp[G + k];
-    a[2] += w.gen_comp[2 * G + k];
-    smax = fmax(smax, w.gen_comp[3 * G + k]);
+  for (int q = g0 + (int)threadIdx.x; q < g1; q += blockDim.x) {
+    a[0] += w.gen_comp[q];
+    a[1] += w.gen_comp[G + q];
+    a[2] += w.gen_comp[2 * G + q];
+    smax = fmax(smax, w.gen_comp[3 * G + q]);
   }
   for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) smax = fmax(smax, w.bus_comp[i]);
 #pragma unroll
-  for (int k = 0; k < 7; ++k) a[k] = block_sum(a[k], lds);
+  for (int j = 0; j < 7; ++j) a[j] = block_sum(a[j], lds);
   smax = block_max(smax, lds);
+  if (threadIdx.x == 0) {
+    double* r = red_slot(w, s, k);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) r[j] = a[j];
+    r[7] = smax;
+  }
+}
+
+// Merit sums of scenario s from its K block partials, by one wave (the
+// block's first 64 threads): lane t adds partials t, t + 64, ... in order,
+// then a butterfly of shuffles combines the lanes (both partners of a step
+// add the same two values, so every lane ends with the same bits).
+__device__ void merit_sums(const Workspace& w, int s, int K, double a[7], double& smax) {
+  const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) a[j] = 0.0;
+  smax = 0.0;
+  for (int k = lane; k < K; k += 64) {
+    const double* r = red_slot(w, s, k);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) a[j] += r[j];
+    smax = fmax(smax, r[7]);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) a[j] += __shfl_xor(a[j], off, 64);
+    smax = fmax(smax, __shfl_xor(smax, off, 64));
+  }
 }
 
 // Acceptance test and trust-radius update of Algorithm 1, one block per
@@ -847,11 +891,11 @@ __device__ void merit_sums(const Workspace& w, int s, double a[7], double& smax,
 // rejected step with pred > 0 of a scenario whose QP was solved is marked
 // for a second-order correction (decided by k_soc_decide).
 // restore: a restoration step, accepted iff it lowers h; radius and pi kept.
-__global__ void k_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule, int soc, int restore) {
-  __shared__ double lds[16];
+__global__ void k_decide(Workspace w, int K, double mu, double delta_max, double grow, int pi_rule, int soc,
+                         int restore) {
   const int s = blockIdx.x;
   double a[7], smax;
-  merit_sums(w, s, a, smax, lds);
+  merit_sums(w, s, K, a, smax);
   if (threadIdx.x == 0) {
     SqpDecision* dc = &w.decision[s];
     const double delta = w.scen[s].delta;
@@ -968,8 +1012,7 @@ __global__ void k_soc_init(acopf_grid g, Workspace w) {
 // positive, judged against the first step's model (pred of k_decide); the
 // radius grows as after an accepted step that reached it.  Clears the
 // left-out marks of every scenario.
-__global__ void k_soc_decide(Workspace w, double mu, double delta_max, double grow, int pi_rule) {
-  __shared__ double lds[16];
+__global__ void k_soc_decide(Workspace w, int K, double mu, double delta_max, double grow, int pi_rule) {
   const int s = blockIdx.x;
   SqpDecision* dc = &w.decision[s];
   if (dc->soc != 1) {
@@ -977,7 +1020,7 @@ __global__ void k_soc_decide(Workspace w, double mu, double delta_max, double gr
     return;
   }
   double a[7], smax;
-  merit_sums(w, s, a, smax, lds);
+  merit_sums(w, s, K, a, smax);
   if (threadIdx.x == 0) {
     ScenState* sc = &w.scen[s];
     dc->soc_sweeps = sc->sweeps;
@@ -1085,30 +1128,56 @@ __global__ void k_residual_parts(acopf_grid g, acopf_iterate x, Workspace w) {
   }
 }
 
-// One block per scenario: maxima over the scenario's components.
-__global__ void k_residual_reduce(Workspace w) {
+// Block partials of the residual maxima: block s K + k takes chunk k of
+// scenario s's components.
+__global__ void k_residual_partial(Workspace w, int K) {
   __shared__ double lds[16];
-  const int s = blockIdx.x, L = w.n_line, G = w.n_gen, B = w.n_bus;
+  const int s = blockIdx.x / K, k = blockIdx.x % K, L = w.n_line, G = w.n_gen, B = w.n_bus;
+  int l0, l1, g0, g1, b0, b1;
+  red_chunk(w.scen_line_off[s], w.scen_line_off[s + 1], k, K, l0, l1);
+  red_chunk(w.scen_gen_off[s], w.scen_gen_off[s + 1], k, K, g0, g1);
+  red_chunk(w.scen_bus_off[s], w.scen_bus_off[s + 1], k, K, b0, b1);
   double a[7] = {0, 0, 0, 0, 0, 0, 0};  // balance, c11, c12, limit, bounds, dual, gradf
-  for (int l = w.scen_line_off[s] + (int)threadIdx.x; l < w.scen_line_off[s + 1]; l += blockDim.x) {
+  for (int l = l0 + (int)threadIdx.x; l < l1; l += blockDim.x) {
     a[1] = fmax(a[1], w.line_comp[l]);
     a[2] = fmax(a[2], w.line_comp[L + l]);
     a[3] = fmax(a[3], w.line_comp[2 * L + l]);
     a[5] = fmax(a[5], w.line_comp[3 * L + l]);
   }
-  for (int i = w.scen_bus_off[s] + (int)threadIdx.x; i < w.scen_bus_off[s + 1]; i += blockDim.x) {
+  for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
     a[0] = fmax(a[0], w.bus_comp[i]);
     a[4] = fmax(a[4], w.bus_comp[B + i]);
     a[5] = fmax(a[5], w.bus_comp[2 * B + i]);
   }
-  for (int k = w.scen_gen_off[s] + (int)threadIdx.x; k < w.scen_gen_off[s + 1]; k += blockDim.x) {
-    a[4] = fmax(a[4], w.gen_comp[k]);
-    a[5] = fmax(a[5], w.gen_comp[G + k]);
-    a[6] = fmax(a[6], w.gen_comp[2 * G + k]);
+  for (int q = g0 + (int)threadIdx.x; q < g1; q += blockDim.x) {
+    a[4] = fmax(a[4], w.gen_comp[q]);
+    a[5] = fmax(a[5], w.gen_comp[G + q]);
+    a[6] = fmax(a[6], w.gen_comp[2 * G + q]);
   }
 #pragma unroll
-  for (int k = 0; k < 7; ++k) a[k] = block_max(a[k], lds);
+  for (int j = 0; j < 7; ++j) a[j] = block_max(a[j], lds);
   if (threadIdx.x == 0) {
+    double* r = red_slot(w, s, k);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) r[j] = a[j];
+  }
+}
+
+// The residual report of each scenario (one 64-thread block per scenario):
+// the largest of its K block partials, lane-strided then by shuffles.
+__global__ void k_residual_reduce(Workspace w, int K) {
+  const int s = blockIdx.x, lane = (int)threadIdx.x;
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int k = lane; k < K; k += 64) {
+    const double* r = red_slot(w, s, k);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) a[j] = fmax(a[j], r[j]);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < 7; ++j) a[j] = fmax(a[j], __shfl_xor(a[j], off, 64));
+  if (lane == 0) {
     ResidualReport* r = &w.report[s];
     r->balance = a[0];
     r->c11 = a[1];
@@ -1139,6 +1208,15 @@ int blocks_for(long long n, int bs) {
   if (b < 1) b = 1;
   if (b > 65535) b = 65535;
   return (int)b;
+}
+
+// Blocks per scenario of the per-scenario reductions: about 1,024 of a
+// scenario's components (by the batch's average) per block, at most
+// kRedBlocks.  Fixed by the sizes, so the order of the sums is too.
+int red_blocks(const acopf_grid* g, int ns) {
+  const long long n = std::max(std::max((long long)g->n_line, (long long)g->n_bus), (long long)g->n_gen);
+  const long long per = (n + ns - 1) / ns;
+  return (int)std::min<long long>(kRedBlocks, std::max<long long>(1, (per + 1023) / 1024));
 }
 
 // ---------------------------------------------------------------- learned warm start
@@ -1956,8 +2034,10 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   if (rc != ACOPF_OK) return rc;
   const int bs = 256;
   const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
+  const int K = red_blocks(g, w.n_scen);
   hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
-  hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
+  hipLaunchKernelGGL(k_merit_partial, dim3(w.n_scen * K), dim3(256), 0, s, w, K);
+  hipLaunchKernelGGL(k_decide, dim3(w.n_scen), dim3(64), 0, s, w, K, p->mu, p->delta_max, p->grow_ratio,
                      (int)p->pi_update, soc ? 1 : 0, p->restore);
   hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w, 0);
   HIP_TRY(hipGetLastError());
@@ -1992,7 +2072,8 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
       hipLaunchKernelGGL(k_step_nodes, dim3(blocks_for(std::max(g->n_bus, g->n_gen), bs)), dim3(bs), 0, s, *g, w, *d,
                          1);
       hipLaunchKernelGGL(k_merit_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w, *d);
-      hipLaunchKernelGGL(k_soc_decide, dim3(w.n_scen), dim3(256), 0, s, w, p->mu, p->delta_max, p->grow_ratio,
+      hipLaunchKernelGGL(k_merit_partial, dim3(w.n_scen * K), dim3(256), 0, s, w, K);
+      hipLaunchKernelGGL(k_soc_decide, dim3(w.n_scen), dim3(64), 0, s, w, K, p->mu, p->delta_max, p->grow_ratio,
                          (int)p->pi_update);
       hipLaunchKernelGGL(k_apply, dim3(nb), dim3(bs), 0, s, *g, *x, *d, w, 1);
       HIP_TRY(hipGetLastError());
@@ -2000,7 +2081,8 @@ acopf_status acopf_sqp_step_batch(const acopf_grid* g, const acopf_iterate* x, c
   }
   if (p->stop) {
     hipLaunchKernelGGL(k_residual_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w);
-    hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_residual_partial, dim3(w.n_scen * K), dim3(256), 0, s, w, K);
+    hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(64), 0, s, w, K);
     hipLaunchKernelGGL(k_sqp_stop, dim3(blocks_for(w.n_scen, 64)), dim3(64), 0, s, w, p->tol_primal, p->tol_dual,
                        p->tol_step, p->delta_min);
     HIP_TRY(hipGetLastError());
@@ -2077,8 +2159,10 @@ acopf_status acopf_residuals_batch(const acopf_grid* g, const acopf_iterate* x, 
   Workspace w = ws_of(g, workspace);
   const int bs = 256;
   const int nb = blocks_for(std::max(std::max(g->n_line, g->n_bus), g->n_gen), bs);
+  const int K = red_blocks(g, w.n_scen);
   hipLaunchKernelGGL(k_residual_parts, dim3(nb), dim3(bs), 0, s, *g, *x, w);
-  hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(256), 0, s, w);
+  hipLaunchKernelGGL(k_residual_partial, dim3(w.n_scen * K), dim3(256), 0, s, w, K);
+  hipLaunchKernelGGL(k_residual_reduce, dim3(w.n_scen), dim3(64), 0, s, w, K);
   HIP_TRY(hipGetLastError());
   std::vector<ResidualReport> r(w.n_scen);
   HIP_TRY(hipMemcpyAsync(r.data(), w.report, w.n_scen * sizeof(ResidualReport), hipMemcpyDeviceToHost, s));

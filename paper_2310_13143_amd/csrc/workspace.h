@@ -102,6 +102,9 @@ struct ResidualReport {
 
 // Arrival flags of different blocks sit on different 128-byte lines.
 constexpr int kArriveStride = 32;
+// Most blocks per scenario of the per-scenario reductions (merit sums,
+// residual maxima): each writes its block's partial to Workspace::red.
+constexpr int kRedBlocks = 256;
 
 struct Workspace {
   int32_t n_bus, n_line, n_gen, n_scen, max_partials;
@@ -155,6 +158,7 @@ struct Workspace {
   ScenState* scen;         // [n_scen]
   SqpDecision* decision;   // [n_scen]
   ResidualReport* report;  // [n_scen]
+  double* red;             // [n_scen][kRedBlocks][8] block partials of the per-scenario reductions
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -264,6 +268,7 @@ inline size_t layout_workspace(void* base, int32_t nb, int32_t nl, int32_t ng, i
   t.scen = (ScenState*)take((size_t)ns * sizeof(ScenState));
   t.decision = (SqpDecision*)take((size_t)ns * sizeof(SqpDecision));
   t.report = (ResidualReport*)take((size_t)ns * sizeof(ResidualReport));
+  t.red = (double*)take((size_t)ns * kRedBlocks * 8 * D);
   if (w) *w = t;
   return off;
 }
