@@ -41,7 +41,7 @@ SWEEP_SOURCES = ("paper_2310_13143_amd/csrc/acopf_admm.hip", "paper_2310_13143_a
                  "paper_2310_13143_amd/csrc/small_linalg.h",
                  "paper_2310_13143_amd/csrc/workspace.h", "paper_2310_13143_amd/csrc/errors.h",
                  "include/acopf_admm.h")
-MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("b2944da2b315986d", 112102443)}
+MEASURED_SWEEP_TRAFFIC = {"rgg70000": ("b9d2cf52492be334", 111921145)}
 
 
 def sweep_sources_sha() -> str:

@@ -886,8 +886,8 @@ __device__ void merit_sums(const Workspace& w, int s, int K, double a[7], double
   }
 }
 
-// Acceptance test and trust-radius update of Algorithm 1, one block per
-// scenario (fixed-order sums over the scenario's components).  soc = 1: a
+// Acceptance test and trust-radius update of Algorithm 1, one 64-thread
+// block per scenario (fixed-order sums of the scenario's block partials).  soc = 1: a
 // rejected step with pred > 0 of a scenario whose QP was solved is marked
 // for a second-order correction (decided by k_soc_decide).
 // restore: a restoration step, accepted iff it lowers h; radius and pi kept.
