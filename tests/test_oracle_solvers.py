@@ -329,7 +329,9 @@ def test_pi_recovery_equals_sensitivity_of_optimal_value():
 
 def test_infinity_norm_stop_test_bounds_the_euclidean_one():
     """One sweep from the same state with both residual norms: the infinity
-    norms are the largest coupling residuals, so ||.||_inf <= ||.||_2 <=
+    norm of r is the largest coupling residual |x_c - xbar_c| rebuilt here
+    from the new state (generators; flows against their bus-side copies;
+    voltage copies against the end buses' values), ||.||_inf <= ||.||_2 <=
     sqrt(couplings) ||.||_inf, and the state is the same."""
     from oracle import admm, qp as qpm
     from synth.grids import grid_14, power_flow_start
@@ -347,6 +349,10 @@ def test_infinity_norm_stop_test_bounds_the_euclidean_one():
         s2, r2, q2, _ = admm.sweep(g, Q, st, rho)
         si, ri, qi, _ = admm.sweep(g, Q, st, rho, norm="inf")
         np.testing.assert_array_equal(s2.xl, si.xl)
+        f, t = np.asarray(g.f), np.asarray(g.t)
+        bus_side = np.column_stack([si.xbar_f, si.dw[f], si.dth[f], si.dw[t], si.dth[t]])
+        r_direct = max(np.abs(si.xg - si.xbar_g).max(), np.abs(si.xl - bus_side).max())
+        assert abs(ri - r_direct) <= 1e-15 * r_direct
         assert ri <= r2 * (1 + 1e-15) and r2 <= np.sqrt(n) * ri * (1 + 1e-15)
         assert qi <= q2 * (1 + 1e-15) and q2 <= np.sqrt(n) * qi * (1 + 1e-15)
         st = s2
