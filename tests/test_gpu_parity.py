@@ -308,6 +308,40 @@ def test_traced_sweeps_on_a_large_batch():
             assert rel_err_cols(a, b) <= 1e-9, k
 
 
+def test_step_decision_and_residuals_on_a_large_grid():
+    """The step decision's merit sums and the residual report on the
+    2,000-bus grid, whose reductions run several blocks per scenario,
+    against the oracle's merit, model and residual functions at the device's
+    own iterate and trial step: ared = phi(x) - phi(x + d), pred = q(0) -
+    q(d) on the QP built at x, the step's infinity norm, and the maxima of
+    the constraint violations at the new iterate."""
+    from paper_2310_13143_amd import _abi
+    print("[gpu] step decision and residual report, rgg2000", flush=True)
+    g = grid_2000()
+    x0, _ = start_point(g)
+    dg = _dev()(g)
+    assert g.n_line > 2048
+    x = dg.iterate(x0.pg, x0.qg, x0.w, x0.th, x0.wR, x0.wI, None)
+    rho_g, rho_l = dg.rho_scalar(2e4)
+    d = dg.empty_iterate()
+    mu = 1e5
+    out = dg.sqp_step(x, 0.05, rho_g, rho_l, mu=mu, max_sweeps=200, eps=0.0, d=d, sweep_mode=_abi.SWEEP_GRAPH)
+    host = lambda it: acopf.Iterate(*(it[k].cpu().numpy() for k in ("pg", "qg", "w", "th", "wR", "wI")))
+    dh = host(d)
+    Q = qpm.build_qp(g, x0, np.zeros((g.n_line, 4)), 0.05)
+    m0, m1 = acopf.merit(g, x0, mu), acopf.merit(g, x0.plus(dh), mu)
+    assert abs(out["ared"] - (m0 - m1)) <= 1e-11 * (abs(m0) + abs(m1)), (out["ared"], m0 - m1)
+    pred = sqp.predicted_reduction(g, x0, Q, dh, mu)
+    assert abs(out["pred"] - pred) <= 1e-11 * (abs(m0) + abs(pred)), (out["pred"], pred)
+    assert out["step_inf"] == pytest.approx(sqp.step_norm(dh), rel=1e-15)
+    xn = host(x)
+    np.testing.assert_array_equal(xn.pg, (x0.plus(dh) if out["accepted"] else x0).pg)
+    res = dg.residuals(x)
+    ref = acopf.primal_infeasibility(g, xn)
+    for k in ("primal", "balance", "c11", "c12", "limit", "bounds"):
+        assert abs(res[k] - ref[k]) <= 1e-10 * (1.0 + ref[k]), (k, res[k], ref[k])
+
+
 @pytest.mark.parametrize("rho,mu", [(2e4, 10.0), (2e2, 2.0)])
 def test_residual_balancing_matches_oracle(rho, mu):
     """Residual balancing of the penalties every 64 sweeps (graph sweeps)
