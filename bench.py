@@ -263,20 +263,23 @@ def bench_batch(args):
     size is tuned on the batch first (--block 0)."""
     import torch
     from synth.grids import power_flow_start
-    from paper_2310_13143_amd.solver import DeviceGrid, autotune_block
+    from paper_2310_13143_amd.solver import DeviceGrid, autotune_schedule
     from paper_2310_13143_amd._abi import PI_IF_CONVERGED, SWEEP_GRAPH, SWEEP_LAUNCHES
     grids = batch_grids()
     starts = [power_flow_start(g) for g in grids]
+    mode = SWEEP_GRAPH if args.mode == "graph" else SWEEP_LAUNCHES
+    tuned, schedule = None, "given"
+    if args.block == 0:
+        # segment schedule (scenario order in the packed batch) x block size
+        order, bs, tuned = autotune_schedule(grids, starts, args.delta, args.rho, sweep_mode=mode)
+        schedule = min(tuned, key=tuned.get).split("/")[0]
+        grids, starts = [grids[k] for k in order], [starts[k] for k in order]
+    else:
+        bs = args.block
     dg = DeviceGrid(grids, "cuda:0")
     cat = lambda k: np.concatenate([st[k] for st in starts])
     x = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
     x0 = {k: v.clone() for k, v in x.items()}
-    mode = SWEEP_GRAPH if args.mode == "graph" else SWEEP_LAUNCHES
-    tuned = None
-    if args.block == 0:
-        bs, tuned = autotune_block(dg, x, args.delta, args.rho, sweep_mode=mode)
-    else:
-        bs = args.block
     rho_g, rho_l = dg.rho_scalar(args.rho)
 
     def run(steps):
@@ -313,8 +316,8 @@ def bench_batch(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batch64: 64 load scenarios (N(1,0.1) per-bus factors) over the 300-, 2,000- and "
                                "10,000-bus grids (22/21/21), shared launches, per-scenario stop tests and SQP "
-                               f"decisions; <= {args.sweeps} sweeps per QP, eps={args.eps:g}, block {bs}"
-                               + (" (tuned)" if tuned else ""),
+                               f"decisions; <= {args.sweeps} sweeps per QP, eps={args.eps:g}, block {bs}, "
+                               f"scenario order {schedule}" + (" (tuned)" if tuned else ""),
                    "buses": dg.n_bus, "lines": dg.n_line, "generators": dg.n_gen},
         "batch": {"scenarios_per_s": len(grids) * args.steps / wall,
                   "stopped_at_1e-4": int(len(t_stop)),
@@ -323,7 +326,7 @@ def bench_batch(args):
                   "run_s": wall,
                   "accepted": int(sum(o[k]["accepted"] for o in outs for k in range(len(grids)))),
                   "primal_max": float(max(r["primal"] for r in res)), "primal_min": float(min(r["primal"] for r in res)),
-                  "block": bs, "tuning_ms": tuned},
+                  "block": bs, "schedule": schedule, "tuning_ms": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(args.workload),
                      "kernel": "k_line_phase+k_bus_items",

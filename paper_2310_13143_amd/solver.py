@@ -345,13 +345,13 @@ _TUNED = {}
 
 
 def autotune_block(dg: DeviceGrid, x: dict, delta: float = 0.05, rho: float = 2e4, sweeps: int = 128,
-                   candidates=(64, 128, 256), sweep_mode: int = _abi.SWEEP_GRAPH):
+                   candidates=(64, 128, 256), sweep_mode: int = _abi.SWEEP_GRAPH, cache: bool = True):
     """Block size of the line phase that runs fastest on this grid or batch
     in the given sweep mode, timed with HIP events over a few sweeps of the
     QP at x (after one untimed pass per candidate); cached per (buses, lines,
     scenarios, mode) for the process.  Returns (block size, {candidate: ms})."""
     key = (dg.n_bus, dg.n_line, dg.n_scen, sweep_mode)
-    if key in _TUNED:
+    if cache and key in _TUNED:
         return _TUNED[key]
     stream = torch.cuda.current_stream(dg.device)
     dg.qp_build(x, delta)
@@ -367,5 +367,57 @@ def autotune_block(dg: DeviceGrid, x: dict, delta: float = 0.05, rho: float = 2e
         b.synchronize()
         times[bs] = a.elapsed_time(b)
     best = min(times, key=times.get)
-    _TUNED[key] = (best, times)
-    return _TUNED[key]
+    if cache:
+        _TUNED[key] = (best, times)
+    return best, times
+
+
+# Segment schedules: orders of the scenario segments in a packed batch.
+# The sweep kernels' blocks follow the packing (each XCD runs a contiguous
+# run of them), so the order decides which scenarios share an XCD and how
+# evenly the work of mixed sizes spreads.
+SCHEDULES = ("given", "largest_first", "interleaved")
+
+
+def schedule_order(grids, kind: str) -> list:
+    """Permutation of the scenarios for a schedule: 'given' (as passed),
+    'largest_first' (by line count, stable), 'interleaved' (one scenario of
+    each size in turn, largest size first)."""
+    n = [g.n_line for g in grids]
+    idx = list(range(len(grids)))
+    if kind == "given":
+        return idx
+    if kind == "largest_first":
+        return sorted(idx, key=lambda k: -n[k])
+    if kind == "interleaved":
+        queues = [[k for k in idx if n[k] == c] for c in sorted(set(n), reverse=True)]
+        out = []
+        while any(queues):
+            for q in queues:
+                if q:
+                    out.append(q.pop(0))
+        return out
+    raise ValueError(f"unknown schedule {kind!r}")
+
+
+def autotune_schedule(grids, starts, delta: float = 0.05, rho: float = 2e4, sweeps: int = 128,
+                      schedules=SCHEDULES, blocks=(64, 128, 256), sweep_mode: int = _abi.SWEEP_GRAPH,
+                      device: str = "cuda:0"):
+    """Segment schedule x line block size of a batch that runs fastest: for
+    each schedule the batch is packed in that order and its block size tuned
+    (autotune_block, timed sweeps of the QP at the given starts).  Returns
+    (order, block, {"schedule/block": ms}); a caller packs
+    [grids[k] for k in order] and maps per-scenario results back with order."""
+    times, best = {}, None
+    for kind in schedules:
+        order = schedule_order(grids, kind)
+        dg = DeviceGrid([grids[k] for k in order], device)
+        cat = lambda name: np.concatenate([starts[k][name] for k in order])
+        x = dg.iterate(cat("pg"), cat("qg"), cat("w"), cat("th"), cat("wR"), cat("wI"), None)
+        bs, tb = autotune_block(dg, x, delta, rho, sweeps, blocks, sweep_mode, cache=False)
+        for b, ms in tb.items():
+            times[f"{kind}/{b}"] = ms
+        if best is None or tb[bs] < best[2]:
+            best = (order, bs, tb[bs])
+        del dg, x
+    return best[0], best[1], times

@@ -38,3 +38,22 @@ def test_reorder_keeps_the_network_and_narrows_the_band():
     np.testing.assert_allclose(rqo, rq[bp], atol=1e-12)
     assert o.ref == int(np.nonzero(bp == h.ref)[0][0])
     assert dataclasses.fields(o) == dataclasses.fields(h)
+
+
+def test_segment_schedules_are_permutations():
+    """Scenario orders of a packed batch (the autotuner's segment
+    schedules): each is a permutation; 'largest_first' sorts by line count
+    keeping the given order among equal sizes; 'interleaved' takes one
+    scenario of each size in turn, largest first, each size in given order."""
+    from types import SimpleNamespace
+    from paper_2310_13143_amd.solver import SCHEDULES, schedule_order
+    sizes = [405, 2700, 13500, 405, 2700, 13500, 405, 2700, 13500, 405]
+    grids = [SimpleNamespace(n_line=n) for n in sizes]
+    for kind in SCHEDULES:
+        assert sorted(schedule_order(grids, kind)) == list(range(len(grids)))
+    assert schedule_order(grids, "given") == list(range(len(grids)))
+    lf = schedule_order(grids, "largest_first")
+    assert [sizes[k] for k in lf] == sorted(sizes, reverse=True)
+    assert lf[:3] == [2, 5, 8] and lf[-4:] == [0, 3, 6, 9]
+    il = schedule_order(grids, "interleaved")
+    assert il == [2, 1, 0, 5, 4, 3, 8, 7, 6, 9]
